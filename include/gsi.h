@@ -1,0 +1,155 @@
+/*
+ * gsi -- gradient-type subspace iteration on MI355X (gfx950).
+ *
+ * Computes an orthonormal basis X (n x p) of the dominant invariant subspace of a sparse
+ * symmetric matrix A by minimizing phi(X) = -1/2 Tr(X^T A X) over X^T X = I
+ * (Sec. 2.2, eq. phi) with Riemannian steepest descent (Algorithm 2) or Riemannian
+ * nonlinear conjugate gradients with Polak-Ribiere directions (Sec. 5.1, Algorithm 4),
+ * each step using the polar retraction (Sec. 3.1 eq. Ynew, Sec. 5.2 eq. Xnew_P) and the
+ * exact line search on the p x p projected problem (Sec. 3.2, Algorithm 3; Sec. 5.2
+ * eq. phi_P / deriv_P; Sec. 6.1). A X is carried by the recursion of Sec. 6.1
+ * (eq. save_matvec) so that one block product A*P is formed per iteration.
+ * The smallest eigenvalues are targeted by running on -A (Sec. 2.2).
+ *
+ * Conventions for every entry point:
+ *  - All n x p blocks are row-major with leading dimension p (no padding), in device
+ *    memory owned by the caller. Matrix arrays passed to gsi_create are device pointers
+ *    owned by the caller; gsi_create copies what it needs, the caller may free them after.
+ *  - All work is ordered on the HIP stream given to gsi_create (NULL = default stream).
+ *    Calls marked "syncs" wait for that stream before returning.
+ *  - No exceptions or aborts cross this interface. Every call returns a gsi_status; the
+ *    text of the last error of a handle is returned by gsi_last_error.
+ *  - A handle must not be used from two host threads at once.
+ */
+#ifndef GSI_H
+#define GSI_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gsi_ctx* gsi_handle;
+
+typedef enum {
+  GSI_OK = 0,
+  GSI_EINVAL = 1,         /* invalid argument (sizes, pointers, options, CSR structure) */
+  GSI_ENOMEM = 2,         /* device allocation failed */
+  GSI_EDEVICE = 3,        /* a HIP call failed (text in gsi_last_error) */
+  GSI_NOT_CONVERGED = 4,  /* max_iter reached; the iterate stays valid */
+  GSI_BREAKDOWN = 5,      /* non-finite values or a rank-deficient block */
+  GSI_EUNSUPPORTED = 6    /* option combination not built (e.g. p above the supported maximum) */
+} gsi_status;
+
+typedef enum { GSI_RSD = 1, GSI_RCG = 2 } gsi_method;
+
+typedef enum {
+  GSI_FP64 = 0,        /* every step in float64 */
+  GSI_MIXED_FP32 = 1   /* SpMM, Gram and update passes in float32 (float32 accumulation) with
+                          float64 small solves; then a float64 refinement phase to tol */
+} gsi_precision;
+
+/* Full symmetric CSR (both triangles stored), int32 row pointers and column indices,
+ * float64 values, all device pointers. Column indices must be sorted within a row. */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int32_t* rowptr; /* n + 1 */
+  const int32_t* colind; /* nnz */
+  const double* vals;    /* nnz */
+} gsi_csr;
+
+typedef struct {
+  int32_t p;            /* block size, 1 <= p < n, p <= 64 */
+  int32_t which;        /* +1 largest eigenvalues, -1 smallest (the solver runs on -A) */
+  int32_t method;       /* gsi_method */
+  int32_t precision;    /* gsi_precision */
+  int32_t recompute_ax; /* 0: A X by the recursion of Sec. 6.1; 1: A X formed every iteration
+                           (the RCG(+) variant of Sec. 6.4) */
+  int32_t k_restart;    /* restart the CG direction every k_restart iterations (0 = never) */
+  int32_t max_iter;     /* iteration cap (accepted steps) */
+  double tol;           /* stop when rho = ||G||_F / (sqrt(p) ||A||_inf) <= tol */
+  double switch_tol;    /* GSI_MIXED_FP32: rho at which the float64 refinement phase starts */
+  int32_t check_every;  /* gsi_solve polls the convergence flag every this many iterations */
+  int32_t use_graph;    /* capture the per-iteration launch sequence in a HIP graph */
+  int32_t explicit_c;   /* 1: form C = X^T A X and W = X^T P_old by Gram passes in the retraction
+                           pass; 0: carry them by the p x p recursion C <- M (C - mu (P^T Y +
+                           Y^T P) + mu^2 P^T Z) M, W <- -mu M P^T P */
+} gsi_options;
+
+/* Fill *opt with defaults: p=8, which=+1, RCG, FP64, recursion, no restart, max_iter=10000,
+ * tol=1e-8, switch_tol=1e-5, check_every=25, use_graph=1, explicit_c=0. */
+void gsi_options_default(gsi_options* opt);
+
+/* Create a solver for A with options opt, starting block X0 (n x p float64, device; its
+ * columns need not be orthonormal: the library orthonormalizes them by two passes of
+ * Cholesky QR). X0 == NULL draws nothing and is an error (GSI_EINVAL): starting blocks
+ * are always supplied by the caller. Validates sizes and CSR structure (monotone rowptr,
+ * column indices in range). On success *h owns device copies of A and X0 and all
+ * workspace; gsi_step / gsi_solve never allocate. Syncs. */
+gsi_status gsi_create(gsi_handle* h, const gsi_csr* A, const gsi_options* opt, const double* X0,
+                      void* hip_stream);
+
+/* Enqueue n_iter iterations (fewer if the convergence flag is raised on the device;
+ * the remaining launches return immediately). Asynchronous. */
+gsi_status gsi_step(gsi_handle h, int32_t n_iter);
+
+/* Iterate until rho <= tol or max_iter accepted steps. *iters_out (nullable) receives the
+ * number of accepted steps. Returns GSI_OK, GSI_NOT_CONVERGED or GSI_BREAKDOWN. Syncs. */
+gsi_status gsi_solve(gsi_handle h, int32_t* iters_out);
+
+/* Rayleigh-Ritz on the current X (Sec. 2.3, eq. rr1): Ritz values of A (host array of p,
+ * largest first for which=+1, smallest first for which=-1), per-column residual norms
+ * ||A u_i - theta_i u_i|| (host array of p), rho and phi (host scalars). Any output may be
+ * NULL. Replaces X by the Ritz vectors X U (same span). Syncs. */
+gsi_status gsi_residuals(gsi_handle h, double* ritz, double* col_res, double* rho, double* phi);
+
+/* Copy the current X (n x p, row-major, float64) to the device pointer X_out. Syncs. */
+gsi_status gsi_get_x(gsi_handle h, double* X_out);
+
+/* Replace the iterate by span(X0) (n x p float64 device block; orthonormalized inside) and
+ * reset the iteration state: a warm start (Sec. 2.3: restarting from a previous subspace). */
+gsi_status gsi_set_x0(gsi_handle h, const double* X0);
+
+/* Z = A_op W for the handle's operator (A, or -A when which = -1), W and Z n x p float64
+ * device blocks. The same SpMM kernel the iteration uses. Asynchronous. */
+gsi_status gsi_spmm(gsi_handle h, const double* W, double* Z);
+
+/* Per-iteration history, host arrays of length >= count (nullable): rho, phi, mu, beta_pr
+ * and ||G||_inf / ||G_0||_inf per recorded iterate. Returns the number of records in
+ * *count (at most the capacity passed in *count). Syncs. */
+gsi_status gsi_history(gsi_handle h, int32_t* count, double* rho, double* phi, double* mu,
+                       double* beta_pr, double* ginf_rel);
+
+/* Counters: accepted iterations, block products with A, restarts, explicit A X refreshes,
+ * null steps (line search or descent test failed: the next step restarts), low-precision
+ * iterations (mixed mode). Any pointer may be NULL. Syncs. */
+gsi_status gsi_counters(gsi_handle h, int32_t* iters, int32_t* spmm, int32_t* restarts,
+                        int32_t* refreshes, int32_t* null_steps, int32_t* low_iters);
+
+/* Per-pass kernel timing with HIP events recorded on the handle's stream around every
+ * launch of the iteration. Indices of ms[] / counts[] (arrays of GSI_NPASS, nullable): */
+enum {
+  GSI_PASS_GRAD = 0,       /* gradient pass */
+  GSI_PASS_DIR = 1,        /* direction pass */
+  GSI_PASS_SPMM = 2,       /* block SpMM A P with its Gram epilogue */
+  GSI_PASS_UPDATE = 3,     /* retraction pass */
+  GSI_PASS_REDUCE = 4,     /* fixed-order reductions of partial sums */
+  GSI_PASS_SMALL = 5,      /* p x p kernels other than the line search */
+  GSI_PASS_LINESEARCH = 6, /* eigendecomposition of P^T P, Get_Mu and M */
+  GSI_PASS_REFRESH = 7,    /* explicit A X (launched every iteration, runs when requested) */
+  GSI_NPASS = 8
+};
+/* Returns the accumulated milliseconds and launch counts since the last reset, then, if
+ * enable >= 0, resets them and turns timing on (1) or off (0). While timing is on, gsi_solve
+ * launches without the graph and polls every iteration. Syncs. */
+gsi_status gsi_pass_times(gsi_handle h, int32_t enable, double* ms, int32_t* counts);
+
+void gsi_destroy(gsi_handle h);
+const char* gsi_status_str(gsi_status s);
+const char* gsi_last_error(gsi_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSI_H */

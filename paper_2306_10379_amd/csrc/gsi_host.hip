@@ -1,0 +1,675 @@
+// Host driver and C ABI of libgsi (see include/gsi.h).
+//
+// One handle owns device copies of the CSR matrix and X0, the tall blocks, the p x p
+// small state and the scalars. An iteration is a fixed launch sequence (gradient pass,
+// direction pass, SpMM with Gram epilogue, line search, retraction, optional explicit
+// A X); every kernel reads the control flags from device memory, so the sequence is
+// identical for all iterations, needs no host round trip and is captured once in a HIP
+// graph. The host only polls the convergence flag every check_every iterations.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/gsi.h"
+#include "gsi_kernels.h"
+
+using namespace gsi;
+
+namespace {
+
+constexpr int MAXP = 64;
+
+int round16(int p) { return (p + 15) / 16 * 16; }
+
+struct Dev {
+  std::vector<void*> ptrs;
+  hipError_t err = hipSuccess;
+  template <typename U>
+  U* alloc(size_t count) {
+    if (err != hipSuccess) return nullptr;
+    void* p = nullptr;
+    err = hipMalloc(&p, count * sizeof(U) + 256);
+    if (err != hipSuccess) return nullptr;
+    ptrs.push_back(p);
+    return reinterpret_cast<U*>(p);
+  }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+};
+
+// Tall blocks, matrix values and per-solve state for one block precision.
+template <typename T>
+struct Engine {
+  int64_t n = 0;
+  int p = 0, PP = 0, nb = 0;
+  T *X = nullptr, *Y = nullptr, *G0 = nullptr, *G1 = nullptr, *P0 = nullptr, *P1 = nullptr, *Z = nullptr;
+  T* vals = nullptr;
+  double* small = nullptr;
+  Scalars* sc = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  bool explicit_grams = false;
+
+  bool alloc(Dev& d, int64_t n_, int p_, int nb_, int64_t nnz) {
+    n = n_; p = p_; PP = round16(p_); nb = nb_;
+    const size_t blk = (size_t)n * PP;
+    X = d.alloc<T>(blk); Y = d.alloc<T>(blk); G0 = d.alloc<T>(blk); G1 = d.alloc<T>(blk);
+    P0 = d.alloc<T>(blk); P1 = d.alloc<T>(blk); Z = d.alloc<T>(blk);
+    vals = d.alloc<T>((size_t)nnz);
+    small = d.alloc<double>((size_t)S_COUNT * PP * PP + 8 * PP);
+    sc = d.alloc<Scalars>(1);
+    return d.err == hipSuccess;
+  }
+  void destroy_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr; graph = nullptr;
+  }
+};
+
+}  // namespace
+
+struct gsi_ctx {
+  gsi_options opt;
+  hipStream_t st = nullptr;
+  int64_t n = 0, nnz = 0;
+  int p = 0, PP = 0, nb = 0;
+  Dev dev;
+  int32_t *rowptr = nullptr, *colind = nullptr;
+  double* partials = nullptr;  // nb * (2 PP^2 + 8)
+  double* red = nullptr;       // 2 PP^2 + 8
+  double* hist = nullptr;      // (hist_cap) * H_FIELDS
+  double* dvec = nullptr;      // device vector scratch (Ritz values etc.)
+  int* flags = nullptr;
+  int hist_cap = 0;
+  double nA = 0.0;
+  Engine<double> e64;
+  Engine<float> e32;
+  bool mixed = false;
+  int phase = 0;          // 0: float64 engine active; 1: float32 engine active (mixed mode)
+  int low_iters = 0;      // accepted iterations of the float32 phase
+  int low_spmm = 0, low_restarts = 0, low_refresh = 0, low_null = 0;
+  int hist_off = 0;       // history offset of the float64 phase
+  bool own_stream = false;
+  // optional per-pass event timing (gsi_pass_times)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+  size_t ev_next = 0;
+  double pass_ms[GSI_NPASS] = {0};
+  int32_t pass_count[GSI_NPASS] = {0};
+  std::string err;
+};
+
+namespace {
+
+gsi_status fail(gsi_ctx* h, gsi_status s, const std::string& msg) {
+  if (h) h->err = msg;
+  return s;
+}
+
+gsi_status hip_check(gsi_ctx* h, hipError_t e, const char* what) {
+  if (e == hipSuccess) return GSI_OK;
+  return fail(h, GSI_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define GSI_TRY(expr)                       \
+  do {                                      \
+    gsi_status _s = (expr);                 \
+    if (_s != GSI_OK) return _s;            \
+  } while (0)
+
+template <typename T, typename F>
+void dispatch_pp(int PP, F&& f) {
+  switch (PP) {
+    case 16: f(std::integral_constant<int, 16>()); break;
+    case 32: f(std::integral_constant<int, 32>()); break;
+    case 64: f(std::integral_constant<int, 64>()); break;
+    default: break;
+  }
+}
+
+// Event timing of one launch (only when the handle's timing mode is on).
+struct PassTimer {
+  gsi_ctx* h;
+  int pass;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipEvent_t get() {
+    if (h->ev_next >= h->ev_pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      h->ev_pool.push_back(e);
+    }
+    return h->ev_pool[h->ev_next++];
+  }
+  PassTimer(gsi_ctx* h_, int pass_) : h(h_), pass(pass_) {
+    if (!h->timing) return;
+    a = get();
+    b = get();
+    if (a && b) (void)hipEventRecord(a, h->st);
+  }
+  ~PassTimer() {
+    if (!h->timing || !a || !b) return;
+    (void)hipEventRecord(b, h->st);
+    h->ev_pending.push_back({pass, {a, b}});
+  }
+};
+
+// Fold completed event pairs into the per-pass totals (the stream has been synchronized).
+void collect_times(gsi_ctx* h) {
+  for (auto& pe : h->ev_pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pe.second.first, pe.second.second) == hipSuccess) {
+      h->pass_ms[pe.first] += ms;
+      h->pass_count[pe.first] += 1;
+    }
+  }
+  h->ev_pending.clear();
+  h->ev_next = 0;
+}
+
+// reduce partials of nv values (sum below max_from, max above)
+void reduce(gsi_ctx* h, int nb, int64_t nv, int64_t max_from, const Scalars* sc, int cond) {
+  PassTimer t(h, GSI_PASS_REDUCE);
+  launch_reduce(h->st, h->partials, nb, nv, max_from, h->red, sc, cond);
+}
+
+// Orthonormalize the engine's X in place by two passes of Cholesky QR.
+template <typename T>
+gsi_status cholqr2(gsi_ctx* h, Engine<T>& e) {
+  for (int pass = 0; pass < 2; ++pass) {
+    dispatch_pp<T>(e.PP, [&](auto PPc) {
+      constexpr int PP = decltype(PPc)::value;
+      Kernels<T, PP>::gram(h->st, e.nb, e.n, e.X, e.X, h->partials);
+      reduce(h, e.nb, (int64_t)PP * PP, (int64_t)PP * PP, e.sc, 0);
+      Small::chol_inv(h->st, PP, e.p, h->red, e.small, h->flags);
+      Kernels<T, PP>::product(h->st, e.nb, e.n, e.X, e.X, e.small + S_M * PP * PP);
+    });
+  }
+  int flag = 0;
+  GSI_TRY(hip_check(h, hipMemcpyAsync(&flag, h->flags, sizeof(int), hipMemcpyDeviceToHost, h->st), "copy flag"));
+  GSI_TRY(hip_check(h, hipStreamSynchronize(h->st), "cholqr2"));
+  if (flag) {
+    (void)hipMemsetAsync(h->flags, 0, sizeof(int), h->st);
+    return fail(h, GSI_BREAKDOWN, "Cholesky QR: the block is rank deficient or not finite");
+  }
+  return GSI_OK;
+}
+
+// Y = A X explicitly with C = sym(X^T Y); reset the iteration state (k = 0, restart).
+template <typename T>
+gsi_status init_state(gsi_ctx* h, Engine<T>& e, double tol, int max_iter, int hist_off) {
+  Scalars s;
+  memset(&s, 0, sizeof(s));
+  s.nA = h->nA;
+  s.tol = tol;
+  s.sqrt_p = sqrt((double)e.p);
+  s.max_iter = max_iter;
+  s.k_restart = h->opt.k_restart;
+  s.method = h->opt.method;
+  s.p = e.p;
+  s.hist_cap = h->hist_cap - hist_off;
+  GSI_TRY(hip_check(h, hipMemcpyAsync(e.sc, &s, sizeof(s), hipMemcpyHostToDevice, h->st), "state upload"));
+  GSI_TRY(hip_check(h, hipMemsetAsync(e.small, 0, sizeof(double) * ((size_t)S_COUNT * e.PP * e.PP + 8 * e.PP), h->st),
+                    "small reset"));
+  dispatch_pp<T>(e.PP, [&](auto PPc) {
+    constexpr int PP = decltype(PPc)::value;
+    Kernels<T, PP>::spmm(h->st, e.nb, e.n, h->rowptr, h->colind, e.vals, e.X, e.X, e.Y, nullptr, e.sc, 0, true,
+                         h->partials);
+    reduce(h, e.nb, (int64_t)PP * PP, (int64_t)PP * PP, e.sc, 0);
+    launch_set_sym(h->st, PP, h->red, e.small + S_C * PP * PP);
+  });
+  return hip_check(h, hipGetLastError(), "init_state launch");
+}
+
+// One iteration's launch sequence.
+template <typename T>
+void launch_iteration(gsi_ctx* h, Engine<T>& e, double* hist) {
+  const int recompute = h->opt.recompute_ax;
+  dispatch_pp<T>(e.PP, [&](auto PPc) {
+    constexpr int PP = decltype(PPc)::value;
+    const int64_t P2 = (int64_t)PP * PP;
+    {
+      PassTimer t(h, GSI_PASS_GRAD);
+      Kernels<T, PP>::grad(h->st, e.nb, e.n, e.X, e.Y, e.G0, e.G1, e.small, e.sc, h->partials);
+    }
+    reduce(h, e.nb, P2 + 3, P2 + 2, e.sc, 3);
+    {
+      PassTimer t(h, GSI_PASS_SMALL);
+      Small::after_grad(h->st, PP, h->red, e.small, e.sc, hist);
+    }
+    {
+      PassTimer t(h, GSI_PASS_DIR);
+      Kernels<T, PP>::dir(h->st, e.nb, e.n, e.X, e.G0, e.G1, e.P0, e.P1, e.small, e.sc, h->partials);
+    }
+    reduce(h, e.nb, P2 + 1, P2 + 1, e.sc, 1);
+    {
+      PassTimer t(h, GSI_PASS_SMALL);
+      Small::after_dir(h->st, PP, h->red, e.small, e.sc);
+    }
+    {
+      PassTimer t(h, GSI_PASS_SPMM);
+      Kernels<T, PP>::spmm(h->st, e.nb, e.n, h->rowptr, h->colind, e.vals, e.P0, e.P1, e.Z, e.Y, e.sc, 1, true,
+                           h->partials);
+    }
+    reduce(h, e.nb, 2 * P2, 2 * P2, e.sc, 1);
+    {
+      PassTimer t(h, GSI_PASS_LINESEARCH);
+      Small::linesearch(h->st, PP, h->red, e.small, e.sc, hist, recompute);
+    }
+    {
+      PassTimer t(h, GSI_PASS_UPDATE);
+      Kernels<T, PP>::update(h->st, e.nb, e.n, e.X, e.Y, e.P0, e.P1, e.Z, e.small, e.sc, h->partials,
+                             e.explicit_grams);
+    }
+    if (e.explicit_grams) {
+      reduce(h, e.nb, 2 * P2, 2 * P2, e.sc, 1);
+      PassTimer t(h, GSI_PASS_SMALL);
+      Small::after_update_grams(h->st, PP, h->red, e.small, e.sc);
+    }
+    {
+      PassTimer t(h, GSI_PASS_REFRESH);
+      Kernels<T, PP>::spmm(h->st, e.nb, e.n, h->rowptr, h->colind, e.vals, e.X, e.X, e.Y, nullptr, e.sc, 2, true,
+                           h->partials);
+    }
+    reduce(h, e.nb, P2, P2, e.sc, 2);
+    {
+      PassTimer t(h, GSI_PASS_SMALL);
+      Small::after_refresh(h->st, PP, h->red, e.small, e.sc);
+    }
+  });
+}
+
+template <typename T>
+gsi_status enqueue_iterations(gsi_ctx* h, Engine<T>& e, double* hist, int count) {
+  if (h->opt.use_graph && !h->timing) {
+    if (!e.gexec) {
+      GSI_TRY(hip_check(h, hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal), "begin capture"));
+      launch_iteration(h, e, hist);
+      hipError_t ce = hipStreamEndCapture(h->st, &e.graph);
+      GSI_TRY(hip_check(h, ce, "end capture"));
+      GSI_TRY(hip_check(h, hipGraphInstantiate(&e.gexec, e.graph, nullptr, nullptr, 0), "graph instantiate"));
+    }
+    for (int i = 0; i < count; ++i)
+      GSI_TRY(hip_check(h, hipGraphLaunch(e.gexec, h->st), "graph launch"));
+  } else {
+    for (int i = 0; i < count; ++i) launch_iteration(h, e, hist);
+  }
+  return hip_check(h, hipGetLastError(), "iteration launch");
+}
+
+template <typename T>
+gsi_status run_until_done(gsi_ctx* h, Engine<T>& e, double* hist, Scalars* out) {
+  // in timing mode poll every iteration so that no launch after convergence is timed
+  const int every = h->timing ? 1 : (h->opt.check_every > 0 ? h->opt.check_every : 25);
+  for (;;) {
+    GSI_TRY(enqueue_iterations(h, e, hist, every));
+    GSI_TRY(hip_check(h, hipMemcpyAsync(out, e.sc, sizeof(Scalars), hipMemcpyDeviceToHost, h->st), "poll"));
+    GSI_TRY(hip_check(h, hipStreamSynchronize(h->st), "iterate"));
+    if (h->timing) collect_times(h);
+    if (out->done) return GSI_OK;
+  }
+}
+
+gsi_status read_scalars(gsi_ctx* h, const Scalars* dsc, Scalars* out) {
+  GSI_TRY(hip_check(h, hipMemcpyAsync(out, dsc, sizeof(Scalars), hipMemcpyDeviceToHost, h->st), "scalars"));
+  return hip_check(h, hipStreamSynchronize(h->st), "scalars sync");
+}
+
+// Switch a mixed-precision solve to the float64 phase: X64 <- X32, Cholesky QR in
+// float64, explicit A X, fresh state (the refinement phase restarts the direction).
+gsi_status switch_to_fp64(gsi_ctx* h) {
+  Scalars s32;
+  GSI_TRY(read_scalars(h, h->e32.sc, &s32));
+  h->low_iters = s32.k;
+  h->low_spmm = s32.n_spmm + 1;
+  h->low_restarts = s32.n_restart;
+  h->low_refresh = s32.n_refresh;
+  h->low_null = s32.n_null;
+  launch_convert<float, double>(h->st, h->n * h->PP, h->e32.X, h->e64.X, 1.0);
+  GSI_TRY(cholqr2(h, h->e64));
+  h->hist_off = s32.hist_len < h->hist_cap ? s32.hist_len : h->hist_cap;
+  const int left = h->opt.max_iter - s32.k > 0 ? h->opt.max_iter - s32.k : 0;
+  GSI_TRY(init_state(h, h->e64, h->opt.tol, left, h->hist_off));
+  h->phase = 0;
+  return GSI_OK;
+}
+
+gsi_status start(gsi_ctx* h, const double* X0) {
+  // pack X0 into the active engine, orthonormalize, form A X and reset the state
+  h->e64.destroy_graph();
+  h->e32.destroy_graph();
+  h->low_iters = h->low_spmm = h->low_restarts = h->low_refresh = h->low_null = 0;
+  h->hist_off = 0;
+  if (h->mixed) {
+    launch_pack<float>(h->st, h->n, h->p, h->PP, X0, h->e32.X, 1.0);
+    GSI_TRY(cholqr2(h, h->e32));
+    GSI_TRY(init_state(h, h->e32, h->opt.switch_tol > h->opt.tol ? h->opt.switch_tol : h->opt.tol,
+                       h->opt.max_iter, 0));
+    h->phase = 1;
+  } else {
+    launch_pack<double>(h->st, h->n, h->p, h->PP, X0, h->e64.X, 1.0);
+    GSI_TRY(cholqr2(h, h->e64));
+    GSI_TRY(init_state(h, h->e64, h->opt.tol, h->opt.max_iter, 0));
+    h->phase = 0;
+  }
+  return hip_check(h, hipStreamSynchronize(h->st), "start");
+}
+
+}  // namespace
+
+extern "C" {
+
+void gsi_options_default(gsi_options* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->p = 8;
+  o->which = 1;
+  o->method = GSI_RCG;
+  o->precision = GSI_FP64;
+  o->recompute_ax = 0;
+  o->k_restart = 0;
+  o->max_iter = 10000;
+  o->tol = 1e-8;
+  o->switch_tol = 1e-5;
+  o->check_every = 25;
+  o->use_graph = 1;
+}
+
+const char* gsi_status_str(gsi_status s) {
+  switch (s) {
+    case GSI_OK: return "ok";
+    case GSI_EINVAL: return "invalid argument";
+    case GSI_ENOMEM: return "out of device memory";
+    case GSI_EDEVICE: return "device error";
+    case GSI_NOT_CONVERGED: return "not converged";
+    case GSI_BREAKDOWN: return "breakdown";
+    case GSI_EUNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* gsi_last_error(gsi_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+gsi_status gsi_create(gsi_handle* out, const gsi_csr* A, const gsi_options* opt, const double* X0, void* stream) {
+  if (!out || !A || !opt) return GSI_EINVAL;
+  *out = nullptr;
+  gsi_ctx* h = new (std::nothrow) gsi_ctx();
+  if (!h) return GSI_ENOMEM;
+  h->opt = *opt;
+  h->st = reinterpret_cast<hipStream_t>(stream);
+  if (!h->st) {
+    // graphs cannot be captured on the null stream: use an owned blocking stream, which
+    // is ordered with the null stream
+    if (hipStreamCreate(&h->st) != hipSuccess) {
+      delete h;
+      return GSI_EDEVICE;
+    }
+    h->own_stream = true;
+  }
+  auto bail = [&](gsi_status s, const std::string& m) {
+    // keep the handle so the caller can read the error text
+    h->err = m;
+    *out = h;
+    return s;
+  };
+  if (A->n < 2 || A->nnz < 1 || !A->rowptr || !A->colind || !A->vals) return bail(GSI_EINVAL, "bad CSR arguments");
+  if (A->n > (int64_t)INT32_MAX || A->nnz > (int64_t)INT32_MAX) return bail(GSI_EUNSUPPORTED, "n or nnz >= 2^31");
+  if (opt->p < 1 || opt->p >= A->n) return bail(GSI_EINVAL, "need 1 <= p < n");
+  if (opt->p > MAXP) return bail(GSI_EUNSUPPORTED, "p above 64 is not built");
+  if (opt->which != 1 && opt->which != -1) return bail(GSI_EINVAL, "which must be +1 or -1");
+  if (opt->method != GSI_RSD && opt->method != GSI_RCG) return bail(GSI_EINVAL, "unknown method");
+  if (opt->precision != GSI_FP64 && opt->precision != GSI_MIXED_FP32) return bail(GSI_EINVAL, "unknown precision");
+  if (!(opt->tol >= 0.0) || opt->max_iter < 0) return bail(GSI_EINVAL, "bad tol or max_iter");
+  if (!X0) return bail(GSI_EINVAL, "X0 is required");
+  h->n = A->n;
+  h->nnz = A->nnz;
+  h->p = opt->p;
+  h->PP = round16(opt->p);
+  h->mixed = opt->precision == GSI_MIXED_FP32;
+  const int64_t ntiles = (h->n + TR - 1) / TR;
+  int dev = 0;
+  hipDeviceProp_t prop;
+  (void)hipGetDevice(&dev);
+  int ncu = 256;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0) ncu = prop.multiProcessorCount;
+  h->nb = (int)(ntiles < 2 * ncu ? ntiles : 2 * ncu);
+  h->hist_cap = opt->max_iter + 2;
+  Dev& d = h->dev;
+  h->rowptr = d.alloc<int32_t>(h->n + 1);
+  h->colind = d.alloc<int32_t>(h->nnz);
+  h->partials = d.alloc<double>((size_t)h->nb * (2 * h->PP * h->PP + 8) + 4096);
+  h->red = d.alloc<double>(2 * h->PP * h->PP + 8);
+  h->hist = d.alloc<double>((size_t)h->hist_cap * H_FIELDS);
+  h->dvec = d.alloc<double>(4 * MAXP + 4096);
+  h->flags = d.alloc<int>(4);
+  if (d.err != hipSuccess) { d.release(); return bail(GSI_ENOMEM, "device allocation failed"); }
+  if (!h->e64.alloc(d, h->n, h->p, h->nb, h->nnz)) { d.release(); return bail(GSI_ENOMEM, "device allocation failed"); }
+  if (h->mixed && !h->e32.alloc(d, h->n, h->p, h->nb, h->nnz)) {
+    d.release();
+    return bail(GSI_ENOMEM, "device allocation failed");
+  }
+  // kernel attributes
+  hipError_t ke = Small::init();
+  dispatch_pp<double>(h->PP, [&](auto PPc) {
+    constexpr int PP = decltype(PPc)::value;
+    if (ke == hipSuccess) ke = Kernels<double, PP>::init();
+    if (ke == hipSuccess) ke = Kernels<float, PP>::init();
+  });
+  if (ke != hipSuccess) return bail(GSI_EDEVICE, std::string("kernel attributes: ") + hipGetErrorString(ke));
+  hipStream_t st = h->st;
+  gsi_status s = GSI_OK;
+  s = hip_check(h, hipMemcpyAsync(h->rowptr, A->rowptr, sizeof(int32_t) * (h->n + 1), hipMemcpyDeviceToDevice, st),
+                "copy rowptr");
+  if (s == GSI_OK)
+    s = hip_check(h, hipMemcpyAsync(h->colind, A->colind, sizeof(int32_t) * h->nnz, hipMemcpyDeviceToDevice, st),
+                  "copy colind");
+  if (s == GSI_OK) s = hip_check(h, hipMemsetAsync(h->flags, 0, 4 * sizeof(int), st), "flags");
+  if (s != GSI_OK) return bail(s, h->err);
+  // validate the CSR and compute ||A||_inf
+  const int cb = 256;
+  launch_csr_check(st, cb, h->n, h->nnz, A->rowptr, A->colind, A->vals, h->dvec, h->flags);
+  launch_finite(st, h->n * (int64_t)h->p, X0, h->flags + 1);
+  std::vector<double> pm(cb);
+  int fl[2] = {0, 0};
+  s = hip_check(h, hipMemcpyAsync(pm.data(), h->dvec, sizeof(double) * cb, hipMemcpyDeviceToHost, st), "norm");
+  if (s == GSI_OK) s = hip_check(h, hipMemcpyAsync(fl, h->flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st), "flags");
+  if (s == GSI_OK) s = hip_check(h, hipStreamSynchronize(st), "validate");
+  if (s != GSI_OK) return bail(s, h->err);
+  if (fl[0] & 1) return bail(GSI_EINVAL, "rowptr is not monotone or out of range");
+  if (fl[0] & 2) return bail(GSI_EINVAL, "column index out of range");
+  if (fl[0] & 8) return bail(GSI_EINVAL, "column indices not sorted within a row");
+  if (fl[0] & 4) return bail(GSI_BREAKDOWN, "non-finite matrix value");
+  if (fl[1]) return bail(GSI_BREAKDOWN, "non-finite value in X0");
+  (void)hipMemsetAsync(h->flags, 0, 4 * sizeof(int), st);
+  double nA = 0.0;
+  for (double v : pm) nA = v > nA ? v : nA;
+  if (!(nA > 0.0)) return bail(GSI_EINVAL, "zero matrix");
+  h->nA = nA;
+  const double sign = opt->which > 0 ? 1.0 : -1.0;
+  launch_convert<double, double>(st, h->nnz, A->vals, h->e64.vals, sign);
+  if (h->mixed) launch_convert<double, float>(st, h->nnz, A->vals, h->e32.vals, sign);
+  h->e64.explicit_grams = opt->explicit_c != 0;
+  h->e32.explicit_grams = opt->explicit_c != 0;
+  s = start(h, X0);
+  if (s != GSI_OK) return bail(s, h->err);
+  *out = h;
+  return GSI_OK;
+}
+
+gsi_status gsi_step(gsi_handle h, int32_t n_iter) {
+  if (!h || n_iter < 0) return GSI_EINVAL;
+  if (h->phase == 1) return enqueue_iterations(h, h->e32, h->hist, n_iter);
+  return enqueue_iterations(h, h->e64, h->hist + (size_t)h->hist_off * H_FIELDS, n_iter);
+}
+
+gsi_status gsi_solve(gsi_handle h, int32_t* iters_out) {
+  if (!h) return GSI_EINVAL;
+  Scalars s;
+  if (h->phase == 1) {
+    GSI_TRY(run_until_done(h, h->e32, h->hist, &s));
+    if (s.done == 3) return fail(h, GSI_BREAKDOWN, "breakdown in the float32 phase");
+    GSI_TRY(switch_to_fp64(h));
+  }
+  GSI_TRY(run_until_done(h, h->e64, h->hist + (size_t)h->hist_off * H_FIELDS, &s));
+  if (iters_out) *iters_out = s.k + h->low_iters;
+  if (s.done == 1) return GSI_OK;
+  if (s.done == 2) return fail(h, GSI_NOT_CONVERGED, "max_iter reached");
+  return fail(h, GSI_BREAKDOWN, "breakdown: non-finite values or no descent step");
+}
+
+gsi_status gsi_residuals(gsi_handle h, double* ritz, double* col_res, double* rho, double* phi) {
+  if (!h) return GSI_EINVAL;
+  if (h->phase == 1) GSI_TRY(switch_to_fp64(h));
+  Engine<double>& e = h->e64;
+  const int p = h->p;
+  double* theta = h->dvec;
+  dispatch_pp<double>(e.PP, [&](auto PPc) {
+    constexpr int PP = decltype(PPc)::value;
+    Kernels<double, PP>::spmm(h->st, e.nb, e.n, h->rowptr, h->colind, e.vals, e.X, e.X, e.Y, nullptr, e.sc, 0, true,
+                              h->partials);
+    reduce(h, e.nb, (int64_t)PP * PP, (int64_t)PP * PP, e.sc, 0);
+    Small::ritz(h->st, PP, p, h->red, e.small, theta);
+    Kernels<double, PP>::product(h->st, e.nb, e.n, e.X, e.X, e.small + S_M * PP * PP);
+    Kernels<double, PP>::product(h->st, e.nb, e.n, e.Y, e.Y, e.small + S_M * PP * PP);
+    Kernels<double, PP>::colres(h->st, e.nb, e.n, e.X, e.Y, theta, h->partials);
+    reduce(h, e.nb, PP, PP, e.sc, 0);
+  });
+  std::vector<double> th(p), cr(h->PP);
+  GSI_TRY(hip_check(h, hipMemcpyAsync(th.data(), theta, sizeof(double) * p, hipMemcpyDeviceToHost, h->st), "ritz"));
+  GSI_TRY(hip_check(h, hipMemcpyAsync(cr.data(), h->red, sizeof(double) * h->PP, hipMemcpyDeviceToHost, h->st),
+                    "colres"));
+  GSI_TRY(hip_check(h, hipStreamSynchronize(h->st), "residuals"));
+  // restart the iteration from the rotated basis
+  e.destroy_graph();
+  {
+    Scalars s;
+    GSI_TRY(read_scalars(h, e.sc, &s));
+    int done = 0, one = 1;
+    GSI_TRY(hip_check(h, hipMemcpyAsync(&e.sc->done, &done, sizeof(int), hipMemcpyHostToDevice, h->st), "reset"));
+    GSI_TRY(hip_check(h, hipMemcpyAsync(&e.sc->restart_next, &one, sizeof(int), hipMemcpyHostToDevice, h->st),
+                      "reset"));
+    dispatch_pp<double>(e.PP, [&](auto PPc) {
+      constexpr int PP = decltype(PPc)::value;
+      Kernels<double, PP>::gram(h->st, e.nb, e.n, e.X, e.Y, h->partials);
+      reduce(h, e.nb, (int64_t)PP * PP, (int64_t)PP * PP, e.sc, 0);
+      launch_set_sym(h->st, PP, h->red, e.small + S_C * PP * PP);
+    });
+    GSI_TRY(hip_check(h, hipStreamSynchronize(h->st), "restart"));
+  }
+  double sq = 0.0, ph = 0.0;
+  const double sign = h->opt.which > 0 ? 1.0 : -1.0;
+  for (int i = 0; i < p; ++i) {
+    sq += cr[i];
+    ph += th[i];
+    if (ritz) ritz[i] = sign * th[i];
+    if (col_res) col_res[i] = sqrt(cr[i] > 0.0 ? cr[i] : 0.0);
+  }
+  if (rho) *rho = sqrt(sq) / (sqrt((double)p) * h->nA);
+  if (phi) *phi = -0.5 * ph;
+  return GSI_OK;
+}
+
+gsi_status gsi_get_x(gsi_handle h, double* X_out) {
+  if (!h || !X_out) return GSI_EINVAL;
+  if (h->phase == 1)
+    launch_unpack<float>(h->st, h->n, h->p, h->PP, h->e32.X, X_out);
+  else
+    launch_unpack<double>(h->st, h->n, h->p, h->PP, h->e64.X, X_out);
+  return hip_check(h, hipStreamSynchronize(h->st), "get_x");
+}
+
+gsi_status gsi_set_x0(gsi_handle h, const double* X0) {
+  if (!h || !X0) return GSI_EINVAL;
+  return start(h, X0);
+}
+
+gsi_status gsi_spmm(gsi_handle h, const double* W, double* Z) {
+  if (!h || !W || !Z) return GSI_EINVAL;
+  Engine<double>& e = h->e64;
+  // stage through the engine's Z / G0 buffers (padded layout)
+  launch_pack<double>(h->st, h->n, h->p, h->PP, W, e.G0, 1.0);
+  dispatch_pp<double>(e.PP, [&](auto PPc) {
+    constexpr int PP = decltype(PPc)::value;
+    Kernels<double, PP>::spmm(h->st, e.nb, e.n, h->rowptr, h->colind, e.vals, e.G0, e.G0, e.Z, nullptr, e.sc, 0,
+                              false, h->partials);
+  });
+  launch_unpack<double>(h->st, h->n, h->p, h->PP, e.Z, Z);
+  return hip_check(h, hipGetLastError(), "spmm");
+}
+
+gsi_status gsi_history(gsi_handle h, int32_t* count, double* rho, double* phi, double* mu, double* beta_pr,
+                       double* ginf_rel) {
+  if (!h || !count) return GSI_EINVAL;
+  Scalars s;
+  GSI_TRY(read_scalars(h, h->phase == 1 ? h->e32.sc : h->e64.sc, &s));
+  const int len = (h->phase == 1 ? 0 : h->hist_off) + s.hist_len;
+  const int m = len < *count ? len : *count;
+  std::vector<double> buf((size_t)(m > 0 ? m : 1) * H_FIELDS);
+  if (m > 0)
+    GSI_TRY(hip_check(h, hipMemcpy(buf.data(), h->hist, sizeof(double) * m * H_FIELDS, hipMemcpyDeviceToHost),
+                      "history"));
+  for (int i = 0; i < m; ++i) {
+    const double* r = &buf[(size_t)i * H_FIELDS];
+    if (rho) rho[i] = r[H_RHO];
+    if (phi) phi[i] = r[H_PHI];
+    if (mu) mu[i] = r[H_MU];
+    if (beta_pr) beta_pr[i] = r[H_BETA];
+    if (ginf_rel) ginf_rel[i] = r[H_GINF];
+  }
+  *count = m;
+  return GSI_OK;
+}
+
+gsi_status gsi_counters(gsi_handle h, int32_t* iters, int32_t* spmm, int32_t* restarts, int32_t* refreshes,
+                        int32_t* null_steps, int32_t* low_iters) {
+  if (!h) return GSI_EINVAL;
+  Scalars s;
+  GSI_TRY(read_scalars(h, h->phase == 1 ? h->e32.sc : h->e64.sc, &s));
+  const bool lowonly = h->phase == 1;
+  if (iters) *iters = s.k + (lowonly ? 0 : h->low_iters);
+  if (spmm) *spmm = s.n_spmm + 1 + (lowonly ? 0 : h->low_spmm);
+  if (restarts) *restarts = s.n_restart + (lowonly ? 0 : h->low_restarts);
+  if (refreshes) *refreshes = s.n_refresh + (lowonly ? 0 : h->low_refresh);
+  if (null_steps) *null_steps = s.n_null + (lowonly ? 0 : h->low_null);
+  if (low_iters) *low_iters = lowonly ? s.k : h->low_iters;
+  return GSI_OK;
+}
+
+gsi_status gsi_pass_times(gsi_handle h, int32_t enable, double* ms, int32_t* counts) {
+  if (!h) return GSI_EINVAL;
+  GSI_TRY(hip_check(h, hipStreamSynchronize(h->st), "pass times"));
+  collect_times(h);
+  for (int i = 0; i < GSI_NPASS; ++i) {
+    if (ms) ms[i] = h->pass_ms[i];
+    if (counts) counts[i] = h->pass_count[i];
+  }
+  if (enable >= 0) {
+    h->timing = enable != 0;
+    for (int i = 0; i < GSI_NPASS; ++i) {
+      h->pass_ms[i] = 0.0;
+      h->pass_count[i] = 0;
+    }
+  }
+  return GSI_OK;
+}
+
+void gsi_destroy(gsi_handle h) {
+  if (!h) return;
+  if (h->st) (void)hipStreamSynchronize(h->st);
+  h->e64.destroy_graph();
+  h->e32.destroy_graph();
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  h->dev.release();
+  if (h->own_stream) (void)hipStreamDestroy(h->st);
+  delete h;
+}
+
+}  // extern "C"

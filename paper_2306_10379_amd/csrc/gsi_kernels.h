@@ -1,0 +1,69 @@
+// Host-side launchers of the device kernels (internal to libgsi).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gsi_device.h"
+#include "gsi_state.h"
+
+namespace gsi {
+
+enum class Pass { Grad, Dir, Update, UpdateGrams, Spmm, SpmmPlain, Gram, Product };
+
+template <typename T, int PP>
+int lds_bytes(Pass pass);
+
+// Streaming passes for block element type T and padded width PP.
+template <typename T, int PP>
+struct Kernels {
+  static hipError_t init();
+  static void grad(hipStream_t st, int nb, int64_t n, const T* X, const T* Y, T* G0, T* G1, const double* small,
+                   const Scalars* sc, double* partials);
+  static void dir(hipStream_t st, int nb, int64_t n, const T* X, const T* G0, const T* G1, T* P0, T* P1,
+                  const double* small, const Scalars* sc, double* partials);
+  static void update(hipStream_t st, int nb, int64_t n, T* X, T* Y, const T* P0, const T* P1, const T* Z,
+                     const double* small, const Scalars* sc, double* partials, bool grams);
+  static void spmm(hipStream_t st, int nb, int64_t n, const int32_t* rowptr, const int32_t* colind, const T* vals,
+                   const T* W0, const T* W1, T* Z, const T* Y3, const Scalars* sc, int mode, bool grams,
+                   double* partials);
+  static void gram(hipStream_t st, int nb, int64_t n, const T* A, const T* B, double* partials);
+  static void product(hipStream_t st, int nb, int64_t n, const T* IN, T* OUT, const double* M);
+  static void colres(hipStream_t st, int nb, int64_t n, const T* X, const T* Y, const double* theta,
+                     double* partials);
+};
+
+void launch_reduce(hipStream_t st, const double* partials, int nb, int64_t nv, int64_t max_from, double* out,
+                   const Scalars* sc, int cond);
+void launch_set_sym(hipStream_t st, int PP, const double* red, double* dst);
+template <typename T>
+void launch_pack(hipStream_t st, int64_t n, int p, int PP, const double* src, T* dst, double scale);
+template <typename T>
+void launch_unpack(hipStream_t st, int64_t n, int p, int PP, const T* src, double* dst);
+template <typename TS, typename TD>
+void launch_convert(hipStream_t st, int64_t count, const TS* src, TD* dst, double scale);
+void launch_csr_check(hipStream_t st, int nb, int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colind,
+                      const double* vals, double* partial_max, int* flags);
+void launch_finite(hipStream_t st, int64_t count, const double* x, int* flags);
+
+// Single-workgroup p x p solves (gsi_small.hip). All read/write the small buffer and the
+// scalars; `red` is the reduced partial-sum vector of the preceding pass.
+struct Small {
+  static hipError_t init();
+  // after the gradient pass: rho, history, stop test, Polak-Ribiere beta, K + beta W
+  static void after_grad(hipStream_t st, int PP, const double* red, double* small, Scalars* sc, double* hist);
+  // after the direction pass: S = P^T P, descent test
+  static void after_dir(hipStream_t st, int PP, const double* red, double* small, Scalars* sc);
+  // after the SpMM: eig(P^T P), line-search diagonals, Get_Mu, M, next C and W
+  static void linesearch(hipStream_t st, int PP, const double* red, double* small, Scalars* sc, double* hist,
+                         int recompute_ax);
+  // after an update with Gram epilogue: C = sym(X^T Y), W = X^T P (explicit)
+  static void after_update_grams(hipStream_t st, int PP, const double* red, double* small, Scalars* sc);
+  // after an explicit A X: C = sym(X^T Y) (runs only when sc->refresh)
+  static void after_refresh(hipStream_t st, int PP, const double* red, double* small, Scalars* sc);
+  // Cholesky factor of the reduced Gram (PP x PP): writes R^{-1} into small[S_M]; flag on failure
+  static void chol_inv(hipStream_t st, int PP, int p, const double* red, double* small, int* flag);
+  // eigendecomposition of sym(red) (p x p): theta (descending) into out_vals, U into small[S_M]
+  static void ritz(hipStream_t st, int PP, int p, const double* red, double* small, double* out_vals);
+};
+
+}  // namespace gsi

@@ -1,0 +1,655 @@
+// Single-workgroup float64 solves on the p x p projected problem: the stop test and
+// Polak-Ribiere coefficient, the eigendecomposition of P^T P (parallel cyclic Jacobi in
+// LDS), the line-search diagonals, the exact line search (bracket from the branch roots,
+// Brent's method on phi'), the retraction factor M, Cholesky QR and Rayleigh-Ritz.
+// The matrices live in the small buffer with row stride PP (>= p); only the leading
+// p x p block is meaningful and the padding is kept at zero.
+#include <math.h>
+
+#include "gsi_kernels.h"
+
+namespace gsi {
+
+constexpr double EPS = 2.220446049250313e-16;
+constexpr int MAXP = 64;
+
+// Order LDS traffic among the lanes of one wavefront (used where only wave 0 runs).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// ---------------------------------------------------------------- helpers (whole workgroup)
+
+// C (p x p, stride ld) = A * B, or A^T * B when ta. Reads/writes any memory space.
+__device__ void mm(int p, int ld, const double* A, const double* B, double* C, bool ta) {
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    double s = 0.0;
+    if (ta)
+      for (int k = 0; k < p; ++k) s += A[k * ld + i] * B[k * ld + j];
+    else
+      for (int k = 0; k < p; ++k) s += A[i * ld + k] * B[k * ld + j];
+    C[i * ld + j] = s;
+  }
+}
+
+// diag(V^T A V)_i for i < p (A not necessarily symmetric), into out[i].
+__device__ void vtav_diag(int p, int ld, const double* V, const double* A, double* tmp, double* out) {
+  // tmp = A V
+  mm(p, ld, A, V, tmp, false);
+  __syncthreads();
+  for (int i = threadIdx.x; i < p; i += blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < p; ++k) s += V[k * ld + i] * tmp[k * ld + i];
+    out[i] = s;
+  }
+  __syncthreads();
+}
+
+// Parallel cyclic Jacobi (round-robin pairs, Brent-Luk ordering) for a symmetric p x p
+// matrix A in LDS (stride ld). On return the diagonal of A holds the eigenvalues and V
+// (LDS, stride ld) the eigenvectors as columns. V must hold an orthogonal starting basis
+// (normally I) on entry and is multiplied by the rotations. Returns the sweep count.
+__device__ int jacobi(int p, int ld, double* A, double* V, double* cs /* 2*MAXP */, int* uv /* MAXP */,
+                      int* flag) {
+  const int m = p + (p & 1);
+  const int half = m / 2;
+  // absolute threshold: eps * ||A||_F (a rotation is skipped when the pivot is below it or
+  // below eps * sqrt(|a_uu a_vv|)); accuracy is then that of a backward-stable solver
+  __shared__ double fro;
+  if (threadIdx.x < 64) {
+    double s = 0.0;
+    for (int e = threadIdx.x; e < p * p; e += 64) {
+      const double v = A[(e / p) * ld + e % p];
+      s += v * v;
+    }
+    s = wave_sum(s);
+    if (threadIdx.x == 0) fro = sqrt(s);
+  }
+  __syncthreads();
+  const double athr = EPS * fro;
+  int sweep = 0;
+  for (; sweep < 40; ++sweep) {
+    if (threadIdx.x == 0) *flag = 0;
+    __syncthreads();
+    for (int round = 0; round < m - 1; ++round) {
+      if ((int)threadIdx.x < half) {
+        const int i = threadIdx.x;
+        // circle method: position 0 fixed, positions 1..m-1 rotate
+        auto player = [&](int pos) { return pos == 0 ? 0 : ((pos - 1 + round) % (m - 1)) + 1; };
+        int u = player(i), v = player(m - 1 - i);
+        if (u > v) { int t = u; u = v; v = t; }
+        double c = 1.0, s = 0.0;
+        int code = -1;
+        if (v < p) {
+          const double auu = A[u * ld + u], avv = A[v * ld + v], auv = A[u * ld + v];
+          if (fabs(auv) > EPS * sqrt(fabs(auu * avv)) && fabs(auv) > athr && fabs(auv) > 1e-300) {
+            const double tau = (avv - auu) / (2.0 * auv);
+            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+            code = u * MAXP + v;
+            *flag = 1;
+          }
+        }
+        cs[2 * i] = c;
+        cs[2 * i + 1] = s;
+        uv[i] = code;
+      }
+      __syncthreads();
+      // rows: A <- J^T A
+      for (int e = threadIdx.x; e < half * p; e += blockDim.x) {
+        const int i = e / p, k = e % p;
+        const int code = uv[i];
+        if (code < 0) continue;
+        const int u = code / MAXP, v = code % MAXP;
+        const double c = cs[2 * i], s = cs[2 * i + 1];
+        const double au = A[u * ld + k], av = A[v * ld + k];
+        A[u * ld + k] = c * au - s * av;
+        A[v * ld + k] = s * au + c * av;
+      }
+      __syncthreads();
+      // columns: A <- A J, V <- V J
+      for (int e = threadIdx.x; e < half * p; e += blockDim.x) {
+        const int i = e / p, k = e % p;
+        const int code = uv[i];
+        if (code < 0) continue;
+        const int u = code / MAXP, v = code % MAXP;
+        const double c = cs[2 * i], s = cs[2 * i + 1];
+        const double au = A[k * ld + u], av = A[k * ld + v];
+        A[k * ld + u] = c * au - s * av;
+        A[k * ld + v] = s * au + c * av;
+        const double vu = V[k * ld + u], vv = V[k * ld + v];
+        V[k * ld + u] = c * vu - s * vv;
+        V[k * ld + v] = s * vu + c * vv;
+      }
+      __syncthreads();
+    }
+    if (*flag == 0) break;
+    __syncthreads();
+  }
+  __syncthreads();
+  return sweep;
+}
+
+// ---------------------------------------------------------------- line search (wave 0)
+
+struct Terms {
+  double a[MAXP], b[MAXP], g[MAXP], z[MAXP];
+  int act[MAXP];
+};
+
+// phi'(mu) = - sum over active terms of (z + d mu - b z mu^2) / (1 + b mu^2)^2 (Sec. 5.2,
+// eq. deriv_P), evaluated by wave 0 (lane i holds term i).
+__device__ double dphi(const Terms& T, int p, double mu) {
+  const int l = threadIdx.x & 63;
+  double v = 0.0;
+  if (l < p && T.act[l]) {
+    const double b = T.b[l], z = T.z[l], d = T.g[l] - T.a[l] * b;
+    const double den = 1.0 + b * mu * mu;
+    v = (z + d * mu - b * z * mu * mu) / (den * den);
+  }
+  return -wave_sum(v);
+}
+
+// Get_Mu (Algorithm 3, Sec. 5.2, Sec. 6.1): returns mu > 0 or -1 when no usable bracket.
+// Called by wave 0 only; *evals counts phi' evaluations.
+__device__ double get_mu(Terms& T, int p, int* evals) {
+  const int l = threadIdx.x & 63;
+  const double bl = l < p ? T.b[l] : 0.0;
+  const double bmax = wave_max(bl);
+  int ev = 0;
+  if (!(bmax > 0.0)) { *evals = 0; return -1.0; }
+  const bool act = l < p && bl > p * EPS * bmax;
+  if (l < p) T.act[l] = act ? 1 : 0;
+  wave_sync();
+  const bool conv = act && T.z[l] > 0.0;
+  if (__ballot(conv) == 0) { *evals = 0; return -1.0; }
+  // f(0) = -sum of active zeta
+  const double f0 = dphi(T, p, 0.0);
+  ++ev;
+  if (!(f0 < 0.0)) { *evals = ev; return -1.0; }
+  // branch roots of the convex branches, without cancellation (Sec. 6.1, eqs. derv1/derv2)
+  double xi = INFINITY;
+  if (conv) {
+    const double b = T.b[l], z = T.z[l], d = T.g[l] - T.a[l] * b;
+    const double s = sqrt(d * d + 4.0 * b * z * z);
+    xi = d < 0.0 ? 2.0 * z / (fabs(d) + s) : (d + s) / (2.0 * b * z);
+  }
+  // phi' at every candidate root, each lane evaluating its own candidate
+  double fxi = -1.0;
+  if (conv) {
+    double acc = 0.0;
+    for (int i = 0; i < p; ++i) {
+      if (!T.act[i]) continue;
+      const double b = T.b[i], z = T.z[i], d = T.g[i] - T.a[i] * b;
+      const double den = 1.0 + b * xi * xi;
+      acc += (z + d * xi - b * z * xi * xi) / (den * den);
+    }
+    fxi = -acc;
+  }
+  ev += 1;
+  // hi: smallest root with phi' >= 0; lo: largest root below hi (or 0)
+  double hi = (conv && fxi >= 0.0) ? xi : INFINITY;
+  for (int o = 32; o > 0; o >>= 1) hi = fmin(hi, __shfl_xor(hi, o, 64));
+  double lo = (conv && xi < hi) ? xi : 0.0;
+  for (int o = 32; o > 0; o >>= 1) lo = fmax(lo, __shfl_xor(lo, o, 64));
+  double fhi;
+  if (hi == INFINITY) {
+    int widen = 0;
+    hi = 2.0 * (lo > 0.0 ? lo : 1.0);
+    fhi = dphi(T, p, hi);
+    ++ev;
+    while (fhi < 0.0 && widen < 60) {
+      lo = hi;
+      hi *= 2.0;
+      fhi = dphi(T, p, hi);
+      ++ev;
+      ++widen;
+    }
+    if (fhi < 0.0) { *evals = ev; return -1.0; }
+  } else {
+    fhi = dphi(T, p, hi);
+    ++ev;
+  }
+  if (fhi == 0.0) { *evals = ev; return hi; }
+  double flo = dphi(T, p, lo);
+  ++ev;
+  if (flo == 0.0) { *evals = ev; return lo; }
+  // Brent's method (Brent 1973, ch. 4): inverse quadratic interpolation / secant steps
+  // safeguarded by bisection, on phi' over [lo, hi] with flo < 0 < fhi.
+  double a = lo, b = hi, c = lo, fa = flo, fb = fhi, fc = flo;
+  double d = b - a, e = d;
+  c = a; fc = fa;
+  for (int it = 0; it < 200; ++it) {
+    if ((fb > 0.0 && fc > 0.0) || (fb < 0.0 && fc < 0.0)) {
+      c = a; fc = fa; d = b - a; e = d;
+    }
+    if (fabs(fc) < fabs(fb)) {
+      a = b; b = c; c = a;
+      fa = fb; fb = fc; fc = fa;
+    }
+    const double tol1 = 2.0 * EPS * fabs(b) + 1e-300;
+    const double xm = 0.5 * (c - b);
+    if (fabs(xm) <= tol1 || fb == 0.0) break;
+    if (fabs(e) >= tol1 && fabs(fa) > fabs(fb)) {
+      double pp, q, r;
+      const double s = fb / fa;
+      if (a == c) {
+        pp = 2.0 * xm * s;
+        q = 1.0 - s;
+      } else {
+        q = fa / fc;
+        r = fb / fc;
+        pp = s * (2.0 * xm * q * (q - r) - (b - a) * (r - 1.0));
+        q = (q - 1.0) * (r - 1.0) * (s - 1.0);
+      }
+      if (pp > 0.0) q = -q; else pp = -pp;
+      if (2.0 * pp < fmin(3.0 * xm * q - fabs(tol1 * q), fabs(e * q))) {
+        e = d;
+        d = pp / q;
+      } else {
+        d = xm;
+        e = d;
+      }
+    } else {
+      d = xm;
+      e = d;
+    }
+    a = b;
+    fa = fb;
+    b += fabs(d) > tol1 ? d : (xm > 0.0 ? tol1 : -tol1);
+    fb = dphi(T, p, b);
+    ++ev;
+  }
+  *evals = ev;
+  return b;
+}
+
+// ---------------------------------------------------------------- kernels
+
+__global__ __launch_bounds__(WG) void k_after_grad(int PP, const double* __restrict__ red, double* __restrict__ small,
+                                                   Scalars* __restrict__ sc, double* __restrict__ hist) {
+  if (sc->done) return;
+  __shared__ double sbeta;
+  const int p = sc->p;
+  const double* K = red;
+  if (threadIdx.x == 0) {
+    const double gg = red[PP * PP], gdot = red[PP * PP + 1], ginf = red[PP * PP + 2];
+    const int k = sc->k;
+    sc->gg = gg;
+    sc->gdot = gdot;
+    sc->ginf = ginf;
+    const double rho = sqrt(gg) / (sc->sqrt_p * sc->nA);
+    double phi = 0.0;
+    for (int i = 0; i < p; ++i) phi += small[S_C * PP * PP + i * PP + i];
+    phi *= -0.5;
+    sc->rho = rho;
+    sc->phi = phi;
+    if (k == 0) sc->ginf0 = ginf;
+    if (k < sc->hist_cap) {
+      double* h = hist + (int64_t)k * H_FIELDS;
+      h[H_RHO] = rho;
+      h[H_PHI] = phi;
+      h[H_MU] = 0.0;
+      h[H_BETA] = 0.0;
+      h[H_GINF] = sc->ginf0 > 0.0 ? ginf / sc->ginf0 : 0.0;
+      if (k + 1 > sc->hist_len) sc->hist_len = k + 1;
+    }
+    double beta = 0.0;
+    if (!isfinite(gg)) {
+      sc->done = 3;
+    } else if (rho <= sc->tol) {
+      sc->done = 1;
+    } else if (k >= sc->max_iter) {
+      sc->done = 2;
+    } else {
+      const bool restart = sc->method == 1 || k == 0 || sc->restart_next ||
+                           (sc->k_restart > 0 && k % sc->k_restart == 0) || !(sc->gg_old > 0.0);
+      beta = restart ? 0.0 : (gg - gdot) / sc->gg_old;
+      sc->restart = restart ? 1 : 0;
+      sc->restart_next = 0;
+      sc->null_step = 0;
+      sc->beta_pr = beta;
+      if (k < sc->hist_cap) hist[(int64_t)k * H_FIELDS + H_BETA] = beta;
+    }
+    sbeta = beta;
+  }
+  __syncthreads();
+  if (sc->done) return;
+  const double beta = sbeta;
+  double* Kd = small + S_KD * PP * PP;
+  double* Ks = small + S_K * PP * PP;
+  const double* W = small + S_W * PP * PP;
+  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) {
+    Ks[e] = K[e];
+    Kd[e] = K[e] + (beta != 0.0 ? beta * W[e] : 0.0);
+  }
+}
+
+__global__ __launch_bounds__(WG) void k_after_dir(int PP, const double* __restrict__ red, double* __restrict__ small,
+                                                  Scalars* __restrict__ sc) {
+  if (sc->done) return;
+  double* S = small + S_S * PP * PP;
+  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) {
+    const int i = e / PP, j = e % PP;
+    S[e] = 0.5 * (red[i * PP + j] + red[j * PP + i]);
+  }
+  if (threadIdx.x == 0) {
+    const double gp = red[PP * PP];
+    sc->gp = gp;
+    if (!(gp > 0.0)) {
+      if (sc->restart) {
+        sc->done = 3;  // the projected gradient is not a descent direction: G = 0 to rounding
+      } else {
+        sc->null_step = 1;
+        sc->restart_next = 1;
+        sc->n_null += 1;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(WG) void k_linesearch(int PP, const double* __restrict__ red, double* __restrict__ small,
+                                                   Scalars* __restrict__ sc, double* __restrict__ hist,
+                                                   int recompute_ax) {
+  if (sc->done || sc->null_step) return;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int p = sc->p;
+  const int ld = p;
+  double* A = reinterpret_cast<double*>(lds_raw);
+  double* V = A + MAXP * MAXP;
+  double* Tm = V + MAXP * MAXP;
+  double* Cc = Tm;                 // p x p scratch
+  double* tmp = Tm + MAXP * MAXP;  // p x p scratch
+  __shared__ Terms terms;
+  __shared__ double cs[2 * MAXP];
+  __shared__ int uv[MAXP];
+  __shared__ int flag;
+  __shared__ double smu;
+  __shared__ int sok;
+  const double* PZr = red;
+  const double* PYr = red + PP * PP;
+  double* S = small + S_S * PP * PP;
+  double* C = small + S_C * PP * PP;
+  double* PZ = small + S_PZ * PP * PP;
+  double* PY = small + S_PY * PP * PP;
+  // load S into A (compact stride p), V = I; keep symmetrized P^T A P and raw P^T A X
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    A[e] = S[i * PP + j];
+    V[e] = (i == j) ? 1.0 : 0.0;
+  }
+  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) {
+    const int i = e / PP, j = e % PP;
+    PZ[e] = 0.5 * (PZr[i * PP + j] + PZr[j * PP + i]);
+    PY[e] = PYr[e];
+  }
+  __syncthreads();
+  jacobi(p, ld, A, V, cs, uv, &flag);
+  // line-search diagonals (Sec. 5.2, eq. CG_linesearch_D) in the basis V
+  for (int i = threadIdx.x; i < p; i += blockDim.x) terms.b[i] = fmax(A[i * ld + i], 0.0);
+  __syncthreads();
+  // compact copies of C, PZ, PY into Tm-based scratch for the diagonal products
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) Cc[e] = C[(e / p) * PP + e % p];
+  __syncthreads();
+  vtav_diag(p, ld, V, Cc, tmp, terms.a);
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) Cc[e] = PZ[(e / p) * PP + e % p];
+  __syncthreads();
+  vtav_diag(p, ld, V, Cc, tmp, terms.g);
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) Cc[e] = PY[(e / p) * PP + e % p];
+  __syncthreads();
+  vtav_diag(p, ld, V, Cc, tmp, terms.z);
+  for (int i = threadIdx.x; i < p; i += blockDim.x) terms.z[i] = -terms.z[i];
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    int evals = 0;
+    const double mu = get_mu(terms, p, &evals);
+    if (threadIdx.x == 0) {
+      smu = mu;
+      sok = mu > 0.0 && isfinite(mu);
+      sc->brent_evals = evals;
+    }
+  }
+  __syncthreads();
+  if (!sok) {
+    if (threadIdx.x == 0) {
+      if (sc->restart) {
+        sc->done = 3;
+      } else {
+        sc->null_step = 1;
+        sc->restart_next = 1;
+        sc->n_null += 1;
+      }
+    }
+    return;
+  }
+  const double mu = smu;
+  // M = V diag((1 + mu^2 b)^{-1/2}) V^T (Sec. 5.2, eq. Xnew_P). The rotations leave V
+  // orthogonal only to about (number of rotations) * eps, which would make X(mu) drift from
+  // orthonormality step after step; one Newton step for the inverse square root of
+  // B = I + mu^2 S, M <- M (3 I - M B M) / 2, restores M B M = I to second order.
+  double* Mc = A;  // compact M (A's eigenvalues are in terms.b already)
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    double s = 0.0;
+    for (int k = 0; k < p; ++k) s += V[i * ld + k] * V[j * ld + k] / sqrt(1.0 + mu * mu * terms.b[k]);
+    Mc[e] = s;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {  // Cc = B M
+    const int i = e / p, j = e % p;
+    double s = Mc[e];
+    for (int k = 0; k < p; ++k) s += mu * mu * S[i * PP + k] * Mc[k * p + j];
+    Cc[e] = s;
+  }
+  __syncthreads();
+  mm(p, p, Mc, Cc, tmp, false);  // tmp = M B M
+  __syncthreads();
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    Cc[e] = ((i == j) ? 3.0 : 0.0) - tmp[e];
+  }
+  __syncthreads();
+  mm(p, p, Mc, Cc, tmp, false);  // tmp = M (3 I - M B M)
+  __syncthreads();
+  double* M = small + S_M * PP * PP;
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    Mc[e] = 0.25 * (tmp[i * p + j] + tmp[j * p + i]);  // symmetric part of tmp / 2
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) {
+    const int i = e / PP, j = e % PP;
+    M[e] = (i < p && j < p) ? Mc[i * p + j] : 0.0;
+  }
+  __syncthreads();
+  // next C = M (C - mu (P^T Y + Y^T P) + mu^2 P^T Z) M and next W = X_new^T P = -mu M S
+  // (X^T P = 0 for the tangent direction; A X recursion of Sec. 6.1, eq. save_matvec)
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    Cc[e] = C[i * PP + j] - mu * (PY[i * PP + j] + PY[j * PP + i]) + mu * mu * PZ[i * PP + j];
+  }
+  __syncthreads();
+  mm(p, ld, Mc, Cc, tmp, false);
+  __syncthreads();
+  mm(p, ld, tmp, Mc, Cc, false);
+  __syncthreads();
+  double* W = small + S_W * PP * PP;
+  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) {
+    const int i = e / PP, j = e % PP;
+    if (i < p && j < p) {
+      C[e] = 0.5 * (Cc[i * p + j] + Cc[j * p + i]);
+      double s = 0.0;
+      for (int k = 0; k < p; ++k) s += Mc[i * p + k] * S[k * PP + j];
+      W[e] = -mu * s;
+    }
+  }
+  if (threadIdx.x == 0) {
+    const int k = sc->k;
+    double bmax = 0.0;
+    for (int i = 0; i < p; ++i) bmax = fmax(bmax, terms.b[i]);
+    sc->mu = mu;
+    sc->refresh = (recompute_ax || mu * sqrt(bmax) <= 1e3 * EPS) ? 1 : 0;
+    if (k < sc->hist_cap) hist[(int64_t)k * H_FIELDS + H_MU] = mu;
+    sc->n_restart += sc->restart;
+    sc->n_refresh += sc->refresh;
+    sc->n_spmm += 1 + sc->refresh;
+    sc->gg_old = sc->gg;
+    sc->k = k + 1;
+  }
+}
+
+__global__ __launch_bounds__(WG) void k_after_update_grams(int PP, const double* __restrict__ red,
+                                                           double* __restrict__ small, Scalars* __restrict__ sc) {
+  if (sc->done || sc->null_step) return;
+  double* C = small + S_C * PP * PP;
+  double* W = small + S_W * PP * PP;
+  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) {
+    const int i = e / PP, j = e % PP;
+    if (!sc->refresh) C[e] = 0.5 * (red[i * PP + j] + red[j * PP + i]);
+    W[e] = red[PP * PP + e];
+  }
+}
+
+__global__ __launch_bounds__(WG) void k_after_refresh(int PP, const double* __restrict__ red,
+                                                      double* __restrict__ small, Scalars* __restrict__ sc) {
+  if (sc->done || sc->null_step || !sc->refresh) return;
+  double* C = small + S_C * PP * PP;
+  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) {
+    const int i = e / PP, j = e % PP;
+    C[e] = 0.5 * (red[i * PP + j] + red[j * PP + i]);
+  }
+}
+
+// Cholesky G = L L^T of the leading p x p block of red, then M = L^{-T} (so X M has
+// orthonormal columns when G = X^T X). flag = 1 on a non-positive or tiny pivot.
+__global__ __launch_bounds__(WG) void k_chol_inv(int PP, int p, const double* __restrict__ red,
+                                                 double* __restrict__ small, int* __restrict__ flag) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  double* L = reinterpret_cast<double*>(lds_raw);
+  double* Li = L + MAXP * MAXP;
+  __shared__ int bad;
+  __shared__ double dmax;
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    L[e] = 0.5 * (red[i * PP + j] + red[j * PP + i]);
+  }
+  if (threadIdx.x == 0) {
+    bad = 0;
+    double m = 0.0;
+    for (int i = 0; i < p; ++i) m = fmax(m, red[i * PP + i]);
+    dmax = m;
+  }
+  __syncthreads();
+  for (int j = 0; j < p; ++j) {
+    if (threadIdx.x == 0) {
+      const double piv = L[j * p + j];
+      if (!(piv > 1e-13 * dmax) || !isfinite(piv)) bad = 1;
+      L[j * p + j] = sqrt(fabs(piv) > 0.0 ? fabs(piv) : 1.0);
+    }
+    __syncthreads();
+    const double ljj = L[j * p + j];
+    for (int i = j + 1 + threadIdx.x; i < p; i += blockDim.x) L[i * p + j] /= ljj;
+    __syncthreads();
+    for (int e = threadIdx.x; e < (p - j - 1) * (p - j - 1); e += blockDim.x) {
+      const int i = j + 1 + e / (p - j - 1), k = j + 1 + e % (p - j - 1);
+      if (k <= i) L[i * p + k] -= L[i * p + j] * L[k * p + j];
+    }
+    __syncthreads();
+  }
+  // Li = L^{-1} (lower), one column per thread
+  for (int c = threadIdx.x; c < p; c += blockDim.x) {
+    for (int i = 0; i < p; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) s -= L[i * p + k] * Li[k * p + c];
+      Li[i * p + c] = i < c ? 0.0 : s / L[i * p + i];
+    }
+  }
+  __syncthreads();
+  double* M = small + S_M * PP * PP;
+  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) {
+    const int i = e / PP, j = e % PP;
+    M[e] = (i < p && j < p) ? Li[j * p + i] : 0.0;  // M = L^{-T}
+  }
+  if (threadIdx.x == 0 && bad) *flag = 1;
+}
+
+// Rayleigh-Ritz: eig of sym(red) (p x p): eigenvalues descending into vals[0..p),
+// eigenvectors as the columns of small[S_M] (stride PP, padding zero).
+__global__ __launch_bounds__(WG) void k_ritz(int PP, int p, const double* __restrict__ red, double* __restrict__ small,
+                                             double* __restrict__ vals) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  double* A = reinterpret_cast<double*>(lds_raw);
+  double* V = A + MAXP * MAXP;
+  __shared__ double cs[2 * MAXP];
+  __shared__ int uv[MAXP];
+  __shared__ int flag;
+  __shared__ int order[MAXP];
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    A[e] = 0.5 * (red[i * PP + j] + red[j * PP + i]);
+    V[e] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  jacobi(p, p, A, V, cs, uv, &flag);
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < p; ++i) order[i] = i;
+    for (int i = 1; i < p; ++i) {  // insertion sort, descending
+      const int o = order[i];
+      const double v = A[o * p + o];
+      int j = i - 1;
+      while (j >= 0 && A[order[j] * p + order[j]] < v) { order[j + 1] = order[j]; --j; }
+      order[j + 1] = o;
+    }
+    for (int i = 0; i < p; ++i) vals[i] = A[order[i] * p + order[i]];
+  }
+  __syncthreads();
+  double* M = small + S_M * PP * PP;
+  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) {
+    const int i = e / PP, j = e % PP;
+    M[e] = (i < p && j < p) ? V[i * p + order[j]] : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+
+static constexpr int LS_LDS = 4 * MAXP * MAXP * (int)sizeof(double);
+static constexpr int RITZ_LDS = 2 * MAXP * MAXP * (int)sizeof(double);
+
+hipError_t Small::init() {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_linesearch),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, LS_LDS);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ritz), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            RITZ_LDS);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_chol_inv), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            RITZ_LDS);
+  return e;
+}
+void Small::after_grad(hipStream_t st, int PP, const double* red, double* small, Scalars* sc, double* hist) {
+  hipLaunchKernelGGL(k_after_grad, dim3(1), dim3(WG), 0, st, PP, red, small, sc, hist);
+}
+void Small::after_dir(hipStream_t st, int PP, const double* red, double* small, Scalars* sc) {
+  hipLaunchKernelGGL(k_after_dir, dim3(1), dim3(WG), 0, st, PP, red, small, sc);
+}
+void Small::linesearch(hipStream_t st, int PP, const double* red, double* small, Scalars* sc, double* hist,
+                       int recompute_ax) {
+  hipLaunchKernelGGL(k_linesearch, dim3(1), dim3(WG), LS_LDS, st, PP, red, small, sc, hist, recompute_ax);
+}
+void Small::after_update_grams(hipStream_t st, int PP, const double* red, double* small, Scalars* sc) {
+  hipLaunchKernelGGL(k_after_update_grams, dim3(1), dim3(WG), 0, st, PP, red, small, sc);
+}
+void Small::after_refresh(hipStream_t st, int PP, const double* red, double* small, Scalars* sc) {
+  hipLaunchKernelGGL(k_after_refresh, dim3(1), dim3(WG), 0, st, PP, red, small, sc);
+}
+void Small::chol_inv(hipStream_t st, int PP, int p, const double* red, double* small, int* flag) {
+  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(WG), RITZ_LDS, st, PP, p, red, small, flag);
+}
+void Small::ritz(hipStream_t st, int PP, int p, const double* red, double* small, double* out_vals) {
+  hipLaunchKernelGGL(k_ritz, dim3(1), dim3(WG), RITZ_LDS, st, PP, p, red, small, out_vals);
+}
+
+}  // namespace gsi

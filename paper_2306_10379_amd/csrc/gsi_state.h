@@ -1,0 +1,51 @@
+// Per-solve device state shared by the kernels and the host driver.
+#pragma once
+#include <stdint.h>
+
+namespace gsi {
+
+// History fields per recorded iterate.
+enum { H_RHO = 0, H_PHI, H_MU, H_BETA, H_GINF, H_FIELDS };
+
+// Scalars, flags and counters; one instance in device memory per solve.
+struct Scalars {
+  double gg;        // <G, G>
+  double gdot;      // <G_old, G>
+  double ginf;      // ||G||_inf (max absolute row sum)
+  double gp;        // <G, P>
+  double gg_old;    // <G_old, G_old>
+  double rho, phi, ginf0;
+  double mu, beta_pr;
+  double nA;        // ||A||_inf
+  double tol;
+  double sqrt_p;
+  int32_t k;            // accepted iterations
+  int32_t done;         // 0 running, 1 converged, 2 max_iter, 3 breakdown
+  int32_t restart_next; // next direction is the projected gradient
+  int32_t null_step;    // current iteration takes no step
+  int32_t restart;      // current direction is a restart
+  int32_t refresh;      // A X is formed explicitly after this update
+  int32_t brent_evals;
+  int32_t max_iter, k_restart, method, p;
+  int32_t n_restart, n_refresh, n_null, n_spmm;
+  int32_t hist_len, hist_cap;
+  int32_t pad_[2];
+};
+
+// Offsets (in doubles) of the p x p matrices (stored PP x PP, row-major) in the small buffer.
+enum {
+  S_C = 0,   // C = sym(X^T A X)
+  S_K,       // X^T G
+  S_KD,      // K + beta W: right factor of the direction pass
+  S_W,       // X^T P_old
+  S_S,       // P^T P
+  S_PZ,      // P^T A P
+  S_PY,      // P^T A X
+  S_V,       // eigenvectors of P^T P (also kept as the next warm start)
+  S_M,       // retraction factor V diag((1 + mu^2 b)^-1/2) V^T
+  S_T1,      // temporaries
+  S_T2,
+  S_COUNT
+};
+
+}  // namespace gsi

@@ -1,0 +1,284 @@
+"""ctypes binding of the libgsi C ABI (include/gsi.h).
+
+Argument marshalling only: every step of the solver runs in the HIP kernels of
+libgsi.so. PyTorch provides device memory and the stream. Loading fails loudly when
+the library has not been built (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsi.so")
+
+GSI_OK, GSI_EINVAL, GSI_ENOMEM, GSI_EDEVICE, GSI_NOT_CONVERGED, GSI_BREAKDOWN, GSI_EUNSUPPORTED = range(7)
+GSI_RSD, GSI_RCG = 1, 2
+GSI_FP64, GSI_MIXED_FP32 = 0, 1
+
+EXPORTS = [
+    "gsi_options_default", "gsi_create", "gsi_step", "gsi_solve", "gsi_residuals", "gsi_get_x",
+    "gsi_set_x0", "gsi_spmm", "gsi_history", "gsi_counters", "gsi_pass_times", "gsi_destroy",
+    "gsi_status_str", "gsi_last_error",
+]
+PASSES = ["grad", "dir", "spmm", "update", "reduce", "small", "linesearch", "refresh"]
+
+
+class GsiCsr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("rowptr", ctypes.c_void_p),
+                ("colind", ctypes.c_void_p), ("vals", ctypes.c_void_p)]
+
+
+class GsiOptions(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("which", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("recompute_ax", ctypes.c_int32), ("k_restart", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("switch_tol", ctypes.c_double),
+                ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("explicit_c", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libgsi.so (raises if it is missing: build it with paper_2306_10379_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libgsi.so not found at {path}; build it with `python -m paper_2306_10379_amd.build`")
+    L = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    L.gsi_options_default.argtypes = [P(GsiOptions)]
+    L.gsi_options_default.restype = None
+    L.gsi_create.argtypes = [P(vp), P(GsiCsr), P(GsiOptions), vp, vp]
+    L.gsi_create.restype = ctypes.c_int
+    L.gsi_step.argtypes = [vp, i32]
+    L.gsi_step.restype = ctypes.c_int
+    L.gsi_solve.argtypes = [vp, P(i32)]
+    L.gsi_solve.restype = ctypes.c_int
+    L.gsi_residuals.argtypes = [vp, P(dbl), P(dbl), P(dbl), P(dbl)]
+    L.gsi_residuals.restype = ctypes.c_int
+    L.gsi_get_x.argtypes = [vp, vp]
+    L.gsi_get_x.restype = ctypes.c_int
+    L.gsi_set_x0.argtypes = [vp, vp]
+    L.gsi_set_x0.restype = ctypes.c_int
+    L.gsi_spmm.argtypes = [vp, vp, vp]
+    L.gsi_spmm.restype = ctypes.c_int
+    L.gsi_history.argtypes = [vp, P(i32), P(dbl), P(dbl), P(dbl), P(dbl), P(dbl)]
+    L.gsi_history.restype = ctypes.c_int
+    L.gsi_counters.argtypes = [vp, P(i32), P(i32), P(i32), P(i32), P(i32), P(i32)]
+    L.gsi_counters.restype = ctypes.c_int
+    L.gsi_pass_times.argtypes = [vp, i32, P(dbl), P(i32)]
+    L.gsi_pass_times.restype = ctypes.c_int
+    L.gsi_destroy.argtypes = [vp]
+    L.gsi_destroy.restype = None
+    L.gsi_status_str.argtypes = [ctypes.c_int]
+    L.gsi_status_str.restype = ctypes.c_char_p
+    L.gsi_last_error.argtypes = [vp]
+    L.gsi_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+class GsiError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"gsi status {status}: {msg}")
+        self.status = status
+
+
+def _dptr(t) -> int:
+    return int(t.data_ptr())
+
+
+def options(**kw) -> GsiOptions:
+    o = GsiOptions()
+    load().gsi_options_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def gsi_create(rowptr, colind, vals, n: int, X0, opt: GsiOptions, stream=None):
+    """Create a handle. rowptr/colind int32, vals float64, X0 float64 n x p: device tensors."""
+    import torch
+    L = load()
+    for name, t, dt in (("rowptr", rowptr, torch.int32), ("colind", colind, torch.int32),
+                        ("vals", vals, torch.float64), ("X0", X0, torch.float64)):
+        if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous {dt} device tensor")
+    csr = GsiCsr(n=int(n), nnz=int(colind.numel()), rowptr=_dptr(rowptr), colind=_dptr(colind), vals=_dptr(vals))
+    h = ctypes.c_void_p()
+    st = ctypes.c_void_p(stream if stream is not None else torch.cuda.current_stream().cuda_stream)
+    s = L.gsi_create(ctypes.byref(h), ctypes.byref(csr), ctypes.byref(opt), ctypes.c_void_p(_dptr(X0)), st)
+    if s != GSI_OK:
+        msg = L.gsi_last_error(h).decode() if h.value else L.gsi_status_str(s).decode()
+        if h.value:
+            L.gsi_destroy(h)
+        raise GsiError(s, msg)
+    return h
+
+
+def _check(h, s, allowed=(GSI_OK,)):
+    if s not in allowed:
+        raise GsiError(s, load().gsi_last_error(h).decode())
+    return s
+
+
+def gsi_step(h, n_iter: int):
+    return _check(h, load().gsi_step(h, int(n_iter)))
+
+
+def gsi_solve(h):
+    it = ctypes.c_int32(0)
+    s = _check(h, load().gsi_solve(h, ctypes.byref(it)), (GSI_OK, GSI_NOT_CONVERGED))
+    return s, it.value
+
+
+def gsi_residuals(h, p: int):
+    ritz = (ctypes.c_double * p)()
+    res = (ctypes.c_double * p)()
+    rho, phi = ctypes.c_double(), ctypes.c_double()
+    _check(h, load().gsi_residuals(h, ritz, res, ctypes.byref(rho), ctypes.byref(phi)))
+    return np.array(ritz[:]), np.array(res[:]), rho.value, phi.value
+
+
+def gsi_get_x(h, out):
+    return _check(h, load().gsi_get_x(h, ctypes.c_void_p(_dptr(out))))
+
+
+def gsi_set_x0(h, X0):
+    return _check(h, load().gsi_set_x0(h, ctypes.c_void_p(_dptr(X0))))
+
+
+def gsi_spmm(h, W, Z):
+    return _check(h, load().gsi_spmm(h, ctypes.c_void_p(_dptr(W)), ctypes.c_void_p(_dptr(Z))))
+
+
+def gsi_history(h, capacity: int):
+    cnt = ctypes.c_int32(capacity)
+    arrs = [(ctypes.c_double * max(capacity, 1))() for _ in range(5)]
+    _check(h, load().gsi_history(h, ctypes.byref(cnt), *arrs))
+    m = cnt.value
+    keys = ["rho", "phi", "mu", "beta_pr", "ginf_rel"]
+    return {k: np.array(a[:m]) for k, a in zip(keys, arrs)}
+
+
+def gsi_counters(h):
+    vals = [ctypes.c_int32() for _ in range(6)]
+    _check(h, load().gsi_counters(h, *[ctypes.byref(v) for v in vals]))
+    keys = ["iters", "spmm", "restarts", "refreshes", "null_steps", "low_iters"]
+    return {k: v.value for k, v in zip(keys, vals)}
+
+
+def gsi_pass_times(h, enable: int = -1):
+    ms = (ctypes.c_double * len(PASSES))()
+    cnt = (ctypes.c_int32 * len(PASSES))()
+    _check(h, load().gsi_pass_times(h, int(enable), ms, cnt))
+    return {k: (ms[i], cnt[i]) for i, k in enumerate(PASSES)}
+
+
+def gsi_destroy(h):
+    if h is not None and h.value:
+        load().gsi_destroy(h)
+
+
+@dataclass
+class Result:
+    status: int
+    iters: int
+    ritz: np.ndarray
+    col_res: np.ndarray
+    rho: float
+    phi: float
+    counters: dict
+
+
+class Solver:
+    """Convenience wrapper owning a handle. A is an inputs.CSR (host arrays, copied to the
+    device) or a tuple (rowptr, colind, vals, n) of device tensors."""
+
+    def __init__(self, A, X0, p: int, device="cuda", **opts):
+        import torch
+        if isinstance(A, tuple):
+            rowptr, colind, vals, n = A
+        else:
+            rowptr = torch.as_tensor(np.asarray(A.rowptr, dtype=np.int32), device=device)
+            colind = torch.as_tensor(np.asarray(A.colind, dtype=np.int32), device=device)
+            vals = torch.as_tensor(np.asarray(A.vals, dtype=np.float64), device=device)
+            n = A.n
+        if not torch.is_tensor(X0):
+            X0 = torch.as_tensor(np.ascontiguousarray(X0, dtype=np.float64), device=device)
+        self.n, self.p = int(n), int(p)
+        method = opts.pop("method", "rcg")
+        precision = opts.pop("precision", "fp64")
+        opts["method"] = {"rsd": GSI_RSD, "rcg": GSI_RCG}[method] if isinstance(method, str) else method
+        opts["precision"] = {"fp64": GSI_FP64, "mixed": GSI_MIXED_FP32, "fp32": GSI_MIXED_FP32}[precision] \
+            if isinstance(precision, str) else precision
+        for b in ("recompute_ax", "use_graph", "explicit_c"):
+            if b in opts:
+                opts[b] = int(bool(opts[b]))
+        self.opt = options(p=self.p, **opts)
+        self.h = gsi_create(rowptr, colind, vals, self.n, X0, self.opt)
+        self.device = X0.device
+
+    def step(self, n_iter: int):
+        gsi_step(self.h, n_iter)
+
+    def solve(self) -> tuple[int, int]:
+        return gsi_solve(self.h)
+
+    def residuals(self):
+        return gsi_residuals(self.h, self.p)
+
+    def get_x(self):
+        import torch
+        out = torch.empty((self.n, self.p), dtype=torch.float64, device=self.device)
+        gsi_get_x(self.h, out)
+        return out
+
+    def set_x0(self, X0):
+        gsi_set_x0(self.h, X0)
+
+    def spmm(self, W):
+        import torch
+        Z = torch.empty_like(W)
+        gsi_spmm(self.h, W.contiguous(), Z)
+        torch.cuda.synchronize()
+        return Z
+
+    def history(self, capacity: int | None = None):
+        return gsi_history(self.h, capacity or (self.opt.max_iter + 2))
+
+    def counters(self):
+        return gsi_counters(self.h)
+
+    def pass_times(self, enable: int = -1):
+        return gsi_pass_times(self.h, enable)
+
+    def run(self) -> Result:
+        status, iters = self.solve()
+        ritz, res, rho, phi = self.residuals()
+        return Result(status, iters, ritz, res, rho, phi, self.counters())
+
+    def close(self):
+        gsi_destroy(self.h)
+        self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) is not None:
+                self.close()
+        except Exception:
+            pass
