@@ -46,7 +46,9 @@ typedef enum { GSI_RSD = 1, GSI_RCG = 2 } gsi_method;
 typedef enum {
   GSI_FP64 = 0,        /* every step in float64 */
   GSI_MIXED_FP32 = 1   /* SpMM, Gram and update passes in float32 (float32 accumulation) with
-                          float64 small solves; then a float64 refinement phase to tol */
+                          float64 small solves, until rho <= switch_tol or rho stops halving
+                          for 200 iterations; then the float64 phase continues the
+                          conjugate-gradient recursion to tol */
 } gsi_precision;
 
 /* Full symmetric CSR (both triangles stored), int32 row pointers and column indices,
@@ -123,22 +125,25 @@ gsi_status gsi_history(gsi_handle h, int32_t* count, double* rho, double* phi, d
 
 /* Counters: accepted iterations, block products with A, restarts, explicit A X refreshes,
  * null steps (line search or descent test failed: the next step restarts), low-precision
- * iterations (mixed mode). Any pointer may be NULL. Syncs. */
+ * iterations (mixed mode), Jacobi sweeps of the P^T P eigendecompositions (summed). Any
+ * pointer may be NULL. Syncs. */
 gsi_status gsi_counters(gsi_handle h, int32_t* iters, int32_t* spmm, int32_t* restarts,
-                        int32_t* refreshes, int32_t* null_steps, int32_t* low_iters);
+                        int32_t* refreshes, int32_t* null_steps, int32_t* low_iters, int32_t* eig_sweeps);
 
 /* Per-pass kernel timing with HIP events recorded on the handle's stream around every
  * launch of the iteration. Indices of ms[] / counts[] (arrays of GSI_NPASS, nullable): */
 enum {
   GSI_PASS_GRAD = 0,       /* gradient pass */
   GSI_PASS_DIR = 1,        /* direction pass */
-  GSI_PASS_SPMM = 2,       /* block SpMM A P with its Gram epilogue */
+  GSI_PASS_SPMM = 2,       /* block SpMM A P */
   GSI_PASS_UPDATE = 3,     /* retraction pass */
   GSI_PASS_REDUCE = 4,     /* fixed-order reductions of partial sums */
   GSI_PASS_SMALL = 5,      /* p x p kernels other than the line search */
-  GSI_PASS_LINESEARCH = 6, /* eigendecomposition of P^T P, Get_Mu and M */
+  GSI_PASS_LINESEARCH = 6, /* line-search diagonals, Get_Mu, M and the next C, W */
   GSI_PASS_REFRESH = 7,    /* explicit A X (launched every iteration, runs when requested) */
-  GSI_NPASS = 8
+  GSI_PASS_EIG = 8,        /* eigendecomposition of P^T P (second stream, overlaps the SpMM) */
+  GSI_PASS_GRAM = 9,       /* Gram pass P^T A P, P^T A X after the SpMM */
+  GSI_NPASS = 10
 };
 /* Returns the accumulated milliseconds and launch counts since the last reset, then, if
  * enable >= 0, resets them and turns timing on (1) or off (0). While timing is on, gsi_solve

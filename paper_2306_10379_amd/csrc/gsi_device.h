@@ -146,7 +146,8 @@ __device__ __forceinline__ void zero_acc(typename Vec4<T>::type (&acc)[PP / 16])
 
 // ---------------------------------------------------------------- Gram phase (per workgroup)
 //
-// The workgroup's TR x PP tiles of A and B sit row-major in LDS. Output blocks
+// The workgroup's TR x PP tiles of A and B sit row-major in LDS (A may also be a tile in
+// global memory with the same layout). Output blocks
 // (ib, jb) of A^T B (16 x 16 each, NBK = PP/16 per side) are dealt round-robin to the
 // 4 waves; a wave keeps its blocks in registers across all tiles it processes.
 template <int PP>

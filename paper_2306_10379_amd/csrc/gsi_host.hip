@@ -59,13 +59,17 @@ struct Engine {
 
   bool alloc(Dev& d, int64_t n_, int p_, int nb_, int64_t nnz) {
     n = n_; p = p_; PP = round16(p_); nb = nb_;
-    const size_t blk = (size_t)n * PP;
+    // whole TR-row tiles; the rows past n stay zero (cleared once here, never written)
+    const size_t blk = (size_t)((n + TR - 1) / TR * TR) * PP;
     X = d.alloc<T>(blk); Y = d.alloc<T>(blk); G0 = d.alloc<T>(blk); G1 = d.alloc<T>(blk);
     P0 = d.alloc<T>(blk); P1 = d.alloc<T>(blk); Z = d.alloc<T>(blk);
     vals = d.alloc<T>((size_t)nnz);
     small = d.alloc<double>((size_t)S_COUNT * PP * PP + 8 * PP);
     sc = d.alloc<Scalars>(1);
-    return d.err == hipSuccess;
+    if (d.err != hipSuccess) return false;
+    for (T* b : {X, Y, G0, G1, P0, P1, Z})
+      if (hipMemset(b, 0, blk * sizeof(T)) != hipSuccess) return false;
+    return true;
   }
   void destroy_graph() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -95,9 +99,11 @@ struct gsi_ctx {
   bool mixed = false;
   int phase = 0;          // 0: float64 engine active; 1: float32 engine active (mixed mode)
   int low_iters = 0;      // accepted iterations of the float32 phase
-  int low_spmm = 0, low_restarts = 0, low_refresh = 0, low_null = 0;
+  int low_spmm = 0, low_restarts = 0, low_refresh = 0, low_null = 0, low_sweeps = 0;
   int hist_off = 0;       // history offset of the float64 phase
   bool own_stream = false;
+  hipStream_t st2 = nullptr;  // second stream: the eigendecomposition overlaps the SpMM
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // optional per-pass event timing (gsi_pass_times)
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -140,6 +146,7 @@ void dispatch_pp(int PP, F&& f) {
 struct PassTimer {
   gsi_ctx* h;
   int pass;
+  hipStream_t st;
   hipEvent_t a = nullptr, b = nullptr;
   hipEvent_t get() {
     if (h->ev_next >= h->ev_pool.size()) {
@@ -149,15 +156,15 @@ struct PassTimer {
     }
     return h->ev_pool[h->ev_next++];
   }
-  PassTimer(gsi_ctx* h_, int pass_) : h(h_), pass(pass_) {
+  PassTimer(gsi_ctx* h_, int pass_, hipStream_t st_ = nullptr) : h(h_), pass(pass_), st(st_ ? st_ : h_->st) {
     if (!h->timing) return;
     a = get();
     b = get();
-    if (a && b) (void)hipEventRecord(a, h->st);
+    if (a && b) (void)hipEventRecord(a, st);
   }
   ~PassTimer() {
     if (!h->timing || !a || !b) return;
-    (void)hipEventRecord(b, h->st);
+    (void)hipEventRecord(b, st);
     h->ev_pending.push_back({pass, {a, b}});
   }
 };
@@ -187,7 +194,7 @@ gsi_status cholqr2(gsi_ctx* h, Engine<T>& e) {
   for (int pass = 0; pass < 2; ++pass) {
     dispatch_pp<T>(e.PP, [&](auto PPc) {
       constexpr int PP = decltype(PPc)::value;
-      Kernels<T, PP>::gram(h->st, e.nb, e.n, e.X, e.X, h->partials);
+      Kernels<T, PP>::gram(h->st, e.nb, e.n, e.X, e.X, e.X, nullptr, e.sc, 0, h->partials);
       reduce(h, e.nb, (int64_t)PP * PP, (int64_t)PP * PP, e.sc, 0);
       Small::chol_inv(h->st, PP, e.p, h->red, e.small, h->flags);
       Kernels<T, PP>::product(h->st, e.nb, e.n, e.X, e.X, e.small + S_M * PP * PP);
@@ -203,11 +210,21 @@ gsi_status cholqr2(gsi_ctx* h, Engine<T>& e) {
   return GSI_OK;
 }
 
-// Y = A X explicitly with C = sym(X^T Y); reset the iteration state (k = 0, restart).
+// Y = A X explicitly with C = sym(X^T Y); reset the iteration state. `cont` (nullable)
+// carries the counter, Polak-Ribiere denominator and history length of an earlier phase.
 template <typename T>
-gsi_status init_state(gsi_ctx* h, Engine<T>& e, double tol, int max_iter, int hist_off) {
+gsi_status init_state(gsi_ctx* h, Engine<T>& e, double tol, int max_iter, int hist_off,
+                      const Scalars* cont = nullptr, int stall_window = 0) {
   Scalars s;
   memset(&s, 0, sizeof(s));
+  s.stall_window = stall_window;
+  if (cont) {
+    s.k = cont->k;
+    s.gg_old = cont->gg_old;
+    s.hist_len = cont->hist_len;
+    s.ginf0 = cont->ginf0;
+    s.restart_next = cont->restart_next;
+  }
   s.nA = h->nA;
   s.tol = tol;
   s.sqrt_p = sqrt((double)e.p);
@@ -221,8 +238,8 @@ gsi_status init_state(gsi_ctx* h, Engine<T>& e, double tol, int max_iter, int hi
                     "small reset"));
   dispatch_pp<T>(e.PP, [&](auto PPc) {
     constexpr int PP = decltype(PPc)::value;
-    Kernels<T, PP>::spmm(h->st, e.nb, e.n, h->rowptr, h->colind, e.vals, e.X, e.X, e.Y, nullptr, e.sc, 0, true,
-                         h->partials);
+    Kernels<T, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.X, e.X, e.Y, e.sc, 0);
+    Kernels<T, PP>::gram(h->st, e.nb, e.n, e.X, e.X, e.Y, nullptr, e.sc, 0, h->partials);
     reduce(h, e.nb, (int64_t)PP * PP, (int64_t)PP * PP, e.sc, 0);
     launch_set_sym(h->st, PP, h->red, e.small + S_C * PP * PP);
   });
@@ -254,12 +271,29 @@ void launch_iteration(gsi_ctx* h, Engine<T>& e, double* hist) {
       PassTimer t(h, GSI_PASS_SMALL);
       Small::after_dir(h->st, PP, h->red, e.small, e.sc);
     }
+    // the eigendecomposition of P^T P needs only S: run it on the second stream while the
+    // SpMM and its Gram pass run on the first
+    // (in timing mode it runs alone on the first stream, so that its duration is its own)
+    hipStream_t est = h->timing ? h->st : h->st2;
+    if (!h->timing) {
+      (void)hipEventRecord(h->ev_fork, h->st);
+      (void)hipStreamWaitEvent(h->st2, h->ev_fork, 0);
+    }
+    {
+      PassTimer t(h, GSI_PASS_EIG, est);
+      Small::eig(est, PP, e.small, e.sc);
+    }
+    if (!h->timing) (void)hipEventRecord(h->ev_join, h->st2);
     {
       PassTimer t(h, GSI_PASS_SPMM);
-      Kernels<T, PP>::spmm(h->st, e.nb, e.n, h->rowptr, h->colind, e.vals, e.P0, e.P1, e.Z, e.Y, e.sc, 1, true,
-                           h->partials);
+      Kernels<T, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.P0, e.P1, e.Z, e.sc, 1);
+    }
+    {
+      PassTimer t(h, GSI_PASS_GRAM);
+      Kernels<T, PP>::gram(h->st, e.nb, e.n, e.P0, e.P1, e.Z, e.Y, e.sc, 1, h->partials);
     }
     reduce(h, e.nb, 2 * P2, 2 * P2, e.sc, 1);
+    if (!h->timing) (void)hipStreamWaitEvent(h->st, h->ev_join, 0);
     {
       PassTimer t(h, GSI_PASS_LINESEARCH);
       Small::linesearch(h->st, PP, h->red, e.small, e.sc, hist, recompute);
@@ -276,8 +310,8 @@ void launch_iteration(gsi_ctx* h, Engine<T>& e, double* hist) {
     }
     {
       PassTimer t(h, GSI_PASS_REFRESH);
-      Kernels<T, PP>::spmm(h->st, e.nb, e.n, h->rowptr, h->colind, e.vals, e.X, e.X, e.Y, nullptr, e.sc, 2, true,
-                           h->partials);
+      Kernels<T, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.X, e.X, e.Y, e.sc, 2);
+      Kernels<T, PP>::gram(h->st, e.nb, e.n, e.X, e.X, e.Y, nullptr, e.sc, 2, h->partials);
     }
     reduce(h, e.nb, P2, P2, e.sc, 2);
     {
@@ -305,8 +339,25 @@ gsi_status enqueue_iterations(gsi_ctx* h, Engine<T>& e, double* hist, int count)
   return hip_check(h, hipGetLastError(), "iteration launch");
 }
 
+// One Cholesky QR pass on X between iterations: X <- X R^{-1}, Y <- Y R^{-1} (Y = A X keeps
+// holding), C <- R^{-T} C R^{-1}, W <- R^{-T} W. Used in the float32 phase, where the
+// rounding of the retraction lets X^T X - I grow like sqrt(k) eps_32 and would floor the
+// attainable residual.
 template <typename T>
-gsi_status run_until_done(gsi_ctx* h, Engine<T>& e, double* hist, Scalars* out) {
+void reorthonormalize(gsi_ctx* h, Engine<T>& e) {
+  dispatch_pp<T>(e.PP, [&](auto PPc) {
+    constexpr int PP = decltype(PPc)::value;
+    Kernels<T, PP>::gram(h->st, e.nb, e.n, e.X, e.X, e.X, nullptr, e.sc, 0, h->partials);
+    reduce(h, e.nb, (int64_t)PP * PP, (int64_t)PP * PP, e.sc, 0);
+    Small::chol_inv(h->st, PP, e.p, h->red, e.small, h->flags + 2);
+    Small::transform_cw(h->st, PP, e.small, h->flags + 2);
+    Kernels<T, PP>::product(h->st, e.nb, e.n, e.X, e.X, e.small + S_M * PP * PP);
+    Kernels<T, PP>::product(h->st, e.nb, e.n, e.Y, e.Y, e.small + S_M * PP * PP);
+  });
+}
+
+template <typename T>
+gsi_status run_until_done(gsi_ctx* h, Engine<T>& e, double* hist, Scalars* out, bool reorth = false) {
   // in timing mode poll every iteration so that no launch after convergence is timed
   const int every = h->timing ? 1 : (h->opt.check_every > 0 ? h->opt.check_every : 25);
   for (;;) {
@@ -315,6 +366,7 @@ gsi_status run_until_done(gsi_ctx* h, Engine<T>& e, double* hist, Scalars* out) 
     GSI_TRY(hip_check(h, hipStreamSynchronize(h->st), "iterate"));
     if (h->timing) collect_times(h);
     if (out->done) return GSI_OK;
+    if (reorth) reorthonormalize(h, e);
   }
 }
 
@@ -324,35 +376,63 @@ gsi_status read_scalars(gsi_ctx* h, const Scalars* dsc, Scalars* out) {
 }
 
 // Switch a mixed-precision solve to the float64 phase: X64 <- X32, Cholesky QR in
-// float64, explicit A X, fresh state (the refinement phase restarts the direction).
+// float64, explicit A X and C. When the float32 phase stopped at its tolerance, the
+// conjugate-gradient recursion continues: iteration k is redone in float64 with the float32
+// G_{k-1}, P_{k-1} as the previous gradient and direction (W = X^T P_{k-1} formed
+// explicitly for the new X). After a float32 breakdown the float64 phase restarts with
+// the projected gradient.
 gsi_status switch_to_fp64(gsi_ctx* h) {
   Scalars s32;
   GSI_TRY(read_scalars(h, h->e32.sc, &s32));
-  h->low_iters = s32.k;
+  const int k = s32.k;
+  h->low_iters = k;
   h->low_spmm = s32.n_spmm + 1;
   h->low_restarts = s32.n_restart;
   h->low_refresh = s32.n_refresh;
   h->low_null = s32.n_null;
-  launch_convert<float, double>(h->st, h->n * h->PP, h->e32.X, h->e64.X, 1.0);
+  h->low_sweeps = s32.n_sweeps;
+  const bool carry = (s32.done == 1 || s32.done == 4) && k >= 1 && !s32.restart_next && s32.gg_old > 0.0;
+  const int64_t rows = (h->n + TR - 1) / TR * TR;
+  launch_convert<float, double>(h->st, rows * h->PP, h->e32.X, h->e64.X, 1.0);
   GSI_TRY(cholqr2(h, h->e64));
-  h->hist_off = s32.hist_len < h->hist_cap ? s32.hist_len : h->hist_cap;
-  const int left = h->opt.max_iter - s32.k > 0 ? h->opt.max_iter - s32.k : 0;
-  GSI_TRY(init_state(h, h->e64, h->opt.tol, left, h->hist_off));
+  Scalars cont = s32;
+  cont.restart_next = carry ? 0 : 1;
+  if (cont.hist_len > k + 1) cont.hist_len = k + 1;
+  h->hist_off = 0;
+  GSI_TRY(init_state(h, h->e64, h->opt.tol, h->opt.max_iter, 0, &cont));
+  if (carry) {
+    const int po = (k - 1) & 1;
+    Engine<float>& a = h->e32;
+    Engine<double>& b = h->e64;
+    launch_convert<float, double>(h->st, rows * h->PP, po ? a.G1 : a.G0, po ? b.G1 : b.G0, 1.0);
+    launch_convert<float, double>(h->st, rows * h->PP, po ? a.P1 : a.P0, po ? b.P1 : b.P0, 1.0);
+    const double* Pold = po ? b.P1 : b.P0;
+    dispatch_pp<double>(b.PP, [&](auto PPc) {
+      constexpr int PP = decltype(PPc)::value;
+      Kernels<double, PP>::gram(h->st, b.nb, b.n, b.X, b.X, Pold, nullptr, b.sc, 0, h->partials);
+      reduce(h, b.nb, (int64_t)PP * PP, (int64_t)PP * PP, b.sc, 0);
+    });
+    GSI_TRY(hip_check(h, hipMemcpyAsync(b.small + S_W * b.PP * b.PP, h->red, sizeof(double) * b.PP * b.PP,
+                                        hipMemcpyDeviceToDevice, h->st),
+                      "carry W"));
+  }
   h->phase = 0;
-  return GSI_OK;
+  return hip_check(h, hipStreamSynchronize(h->st), "switch");
 }
 
 gsi_status start(gsi_ctx* h, const double* X0) {
   // pack X0 into the active engine, orthonormalize, form A X and reset the state
   h->e64.destroy_graph();
   h->e32.destroy_graph();
-  h->low_iters = h->low_spmm = h->low_restarts = h->low_refresh = h->low_null = 0;
+  h->low_iters = h->low_spmm = h->low_restarts = h->low_refresh = h->low_null = h->low_sweeps = 0;
   h->hist_off = 0;
   if (h->mixed) {
     launch_pack<float>(h->st, h->n, h->p, h->PP, X0, h->e32.X, 1.0);
     GSI_TRY(cholqr2(h, h->e32));
+    // the float32 phase also ends when rho has not halved for 200 iterations (its rounding
+    // floor); the float64 phase then continues
     GSI_TRY(init_state(h, h->e32, h->opt.switch_tol > h->opt.tol ? h->opt.switch_tol : h->opt.tol,
-                       h->opt.max_iter, 0));
+                       h->opt.max_iter, 0, nullptr, 200));
     h->phase = 1;
   } else {
     launch_pack<double>(h->st, h->n, h->p, h->PP, X0, h->e64.X, 1.0);
@@ -414,6 +494,13 @@ gsi_status gsi_create(gsi_handle* out, const gsi_csr* A, const gsi_options* opt,
     }
     h->own_stream = true;
   }
+  if (hipStreamCreate(&h->st2) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) {
+    h->err = "stream or event creation failed";
+    *out = h;
+    return GSI_EDEVICE;
+  }
   auto bail = [&](gsi_status s, const std::string& m) {
     // keep the handle so the caller can read the error text
     h->err = m;
@@ -440,7 +527,7 @@ gsi_status gsi_create(gsi_handle* out, const gsi_csr* A, const gsi_options* opt,
   (void)hipGetDevice(&dev);
   int ncu = 256;
   if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0) ncu = prop.multiProcessorCount;
-  h->nb = (int)(ntiles < 2 * ncu ? ntiles : 2 * ncu);
+  h->nb = (int)(ntiles < 4 * ncu ? ntiles : 4 * ncu);
   h->hist_cap = opt->max_iter + 2;
   Dev& d = h->dev;
   h->rowptr = d.alloc<int32_t>(h->n + 1);
@@ -514,12 +601,12 @@ gsi_status gsi_solve(gsi_handle h, int32_t* iters_out) {
   if (!h) return GSI_EINVAL;
   Scalars s;
   if (h->phase == 1) {
-    GSI_TRY(run_until_done(h, h->e32, h->hist, &s));
-    if (s.done == 3) return fail(h, GSI_BREAKDOWN, "breakdown in the float32 phase");
+    // a float32 breakdown means float32 resolution is exhausted: refine in float64
+    GSI_TRY(run_until_done(h, h->e32, h->hist, &s, true));
     GSI_TRY(switch_to_fp64(h));
   }
   GSI_TRY(run_until_done(h, h->e64, h->hist + (size_t)h->hist_off * H_FIELDS, &s));
-  if (iters_out) *iters_out = s.k + h->low_iters;
+  if (iters_out) *iters_out = s.k;
   if (s.done == 1) return GSI_OK;
   if (s.done == 2) return fail(h, GSI_NOT_CONVERGED, "max_iter reached");
   return fail(h, GSI_BREAKDOWN, "breakdown: non-finite values or no descent step");
@@ -533,8 +620,8 @@ gsi_status gsi_residuals(gsi_handle h, double* ritz, double* col_res, double* rh
   double* theta = h->dvec;
   dispatch_pp<double>(e.PP, [&](auto PPc) {
     constexpr int PP = decltype(PPc)::value;
-    Kernels<double, PP>::spmm(h->st, e.nb, e.n, h->rowptr, h->colind, e.vals, e.X, e.X, e.Y, nullptr, e.sc, 0, true,
-                              h->partials);
+    Kernels<double, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.X, e.X, e.Y, e.sc, 0);
+    Kernels<double, PP>::gram(h->st, e.nb, e.n, e.X, e.X, e.Y, nullptr, e.sc, 0, h->partials);
     reduce(h, e.nb, (int64_t)PP * PP, (int64_t)PP * PP, e.sc, 0);
     Small::ritz(h->st, PP, p, h->red, e.small, theta);
     Kernels<double, PP>::product(h->st, e.nb, e.n, e.X, e.X, e.small + S_M * PP * PP);
@@ -558,7 +645,7 @@ gsi_status gsi_residuals(gsi_handle h, double* ritz, double* col_res, double* rh
                       "reset"));
     dispatch_pp<double>(e.PP, [&](auto PPc) {
       constexpr int PP = decltype(PPc)::value;
-      Kernels<double, PP>::gram(h->st, e.nb, e.n, e.X, e.Y, h->partials);
+      Kernels<double, PP>::gram(h->st, e.nb, e.n, e.X, e.X, e.Y, nullptr, e.sc, 0, h->partials);
       reduce(h, e.nb, (int64_t)PP * PP, (int64_t)PP * PP, e.sc, 0);
       launch_set_sym(h->st, PP, h->red, e.small + S_C * PP * PP);
     });
@@ -598,8 +685,7 @@ gsi_status gsi_spmm(gsi_handle h, const double* W, double* Z) {
   launch_pack<double>(h->st, h->n, h->p, h->PP, W, e.G0, 1.0);
   dispatch_pp<double>(e.PP, [&](auto PPc) {
     constexpr int PP = decltype(PPc)::value;
-    Kernels<double, PP>::spmm(h->st, e.nb, e.n, h->rowptr, h->colind, e.vals, e.G0, e.G0, e.Z, nullptr, e.sc, 0,
-                              false, h->partials);
+    Kernels<double, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.G0, e.G0, e.Z, e.sc, 0);
   });
   launch_unpack<double>(h->st, h->n, h->p, h->PP, e.Z, Z);
   return hip_check(h, hipGetLastError(), "spmm");
@@ -629,17 +715,18 @@ gsi_status gsi_history(gsi_handle h, int32_t* count, double* rho, double* phi, d
 }
 
 gsi_status gsi_counters(gsi_handle h, int32_t* iters, int32_t* spmm, int32_t* restarts, int32_t* refreshes,
-                        int32_t* null_steps, int32_t* low_iters) {
+                        int32_t* null_steps, int32_t* low_iters, int32_t* eig_sweeps) {
   if (!h) return GSI_EINVAL;
   Scalars s;
   GSI_TRY(read_scalars(h, h->phase == 1 ? h->e32.sc : h->e64.sc, &s));
   const bool lowonly = h->phase == 1;
-  if (iters) *iters = s.k + (lowonly ? 0 : h->low_iters);
+  if (iters) *iters = s.k;  // the float64 phase continues the float32 phase's count
   if (spmm) *spmm = s.n_spmm + 1 + (lowonly ? 0 : h->low_spmm);
   if (restarts) *restarts = s.n_restart + (lowonly ? 0 : h->low_restarts);
   if (refreshes) *refreshes = s.n_refresh + (lowonly ? 0 : h->low_refresh);
   if (null_steps) *null_steps = s.n_null + (lowonly ? 0 : h->low_null);
   if (low_iters) *low_iters = lowonly ? s.k : h->low_iters;
+  if (eig_sweeps) *eig_sweeps = s.n_sweeps + (lowonly ? 0 : h->low_sweeps);
   return GSI_OK;
 }
 
@@ -666,7 +753,11 @@ void gsi_destroy(gsi_handle h) {
   if (h->st) (void)hipStreamSynchronize(h->st);
   h->e64.destroy_graph();
   h->e32.destroy_graph();
+  if (h->st2) (void)hipStreamSynchronize(h->st2);
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+  if (h->st2) (void)hipStreamDestroy(h->st2);
   h->dev.release();
   if (h->own_stream) (void)hipStreamDestroy(h->st);
   delete h;

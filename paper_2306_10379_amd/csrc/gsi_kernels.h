@@ -23,10 +23,11 @@ struct Kernels {
                   const double* small, const Scalars* sc, double* partials);
   static void update(hipStream_t st, int nb, int64_t n, T* X, T* Y, const T* P0, const T* P1, const T* Z,
                      const double* small, const Scalars* sc, double* partials, bool grams);
-  static void spmm(hipStream_t st, int nb, int64_t n, const int32_t* rowptr, const int32_t* colind, const T* vals,
-                   const T* W0, const T* W1, T* Z, const T* Y3, const Scalars* sc, int mode, bool grams,
-                   double* partials);
-  static void gram(hipStream_t st, int nb, int64_t n, const T* A, const T* B, double* partials);
+  static void spmm(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind, const T* vals,
+                   const T* W0, const T* W1, T* Z, const Scalars* sc, int mode);
+  // A^T B1 (and A^T B2 when B2 != nullptr); mode as for spmm (mode 1 picks A0/A1 by parity)
+  static void gram(hipStream_t st, int nb, int64_t n, const T* A0, const T* A1, const T* B1, const T* B2,
+                   const Scalars* sc, int mode, double* partials);
   static void product(hipStream_t st, int nb, int64_t n, const T* IN, T* OUT, const double* M);
   static void colres(hipStream_t st, int nb, int64_t n, const T* X, const T* Y, const double* theta,
                      double* partials);
@@ -53,7 +54,9 @@ struct Small {
   static void after_grad(hipStream_t st, int PP, const double* red, double* small, Scalars* sc, double* hist);
   // after the direction pass: S = P^T P, descent test
   static void after_dir(hipStream_t st, int PP, const double* red, double* small, Scalars* sc);
-  // after the SpMM: eig(P^T P), line-search diagonals, Get_Mu, M, next C and W
+  // eigendecomposition of P^T P (warm-started); independent of the SpMM
+  static void eig(hipStream_t st, int PP, double* small, Scalars* sc);
+  // after the SpMM: line-search diagonals, Get_Mu, M, next C and W
   static void linesearch(hipStream_t st, int PP, const double* red, double* small, Scalars* sc, double* hist,
                          int recompute_ax);
   // after an update with Gram epilogue: C = sym(X^T Y), W = X^T P (explicit)
@@ -62,6 +65,9 @@ struct Small {
   static void after_refresh(hipStream_t st, int PP, const double* red, double* small, Scalars* sc);
   // Cholesky factor of the reduced Gram (PP x PP): writes R^{-1} into small[S_M]; flag on failure
   static void chol_inv(hipStream_t st, int PP, int p, const double* red, double* small, int* flag);
+  // after a Cholesky QR pass with R^{-1} in small[S_M]: C <- R^{-T} C R^{-1}, W <- R^{-T} W;
+  // when *flag is set (the factorization failed) M is reset to I and C, W are kept
+  static void transform_cw(hipStream_t st, int PP, double* small, int* flag);
   // eigendecomposition of sym(red) (p x p): theta (descending) into out_vals, U into small[S_M]
   static void ritz(hipStream_t st, int PP, int p, const double* red, double* small, double* out_vals);
 };

@@ -18,7 +18,8 @@ __device__ __forceinline__ void load_matrix_lds(T* __restrict__ sM, const double
 // G = -(Y - X C) (Sec. 3.1, eq. gradPhi) with C = X^T A X, fused with
 //   <G, G>, <G_old, G>, ||G||_inf (max absolute row sum) and the Gram K = X^T G
 // (the tangent-space defect of G, removed from the direction in the next pass).
-// Partials: K (PP*PP), <G,G>, <G_old,G>, ||G||_inf.
+// Partials: K (PP*PP), <G,G>, <G_old,G>, ||G||_inf. The tall blocks hold a whole number of
+// TR-row tiles (rows n .. are zero), so the Gram may read the last tile in full.
 template <typename T, int PP>
 __global__ __launch_bounds__(WG) void k_grad(int64_t n, const T* __restrict__ X, const T* __restrict__ Y,
                                              T* __restrict__ G0, T* __restrict__ G1,
@@ -27,8 +28,7 @@ __global__ __launch_bounds__(WG) void k_grad(int64_t n, const T* __restrict__ X,
   if (sc->done) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* sC = reinterpret_cast<T*>(lds_raw);
-  T* sX = sC + PP * PP;
-  T* sG = sX + TR * PP;
+  T* sG = sC + PP * PP;
   __shared__ double red[4 * 3];
   const int par = sc->k & 1;
   T* G = par ? G1 : G0;
@@ -76,12 +76,11 @@ __global__ __launch_bounds__(WG) void k_grad(int64_t n, const T* __restrict__ X,
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) ginf = fmax(ginf, group16_sum(rs[r]));
-    T x[PP / 16][4];
-    load_rl<T, PP>(X, row0, n, x);
-    rl_to_lds<T, PP>(sX, x);
+    // K += X^T G over the tile: X straight from memory (its rows were just read, and the
+    // tall blocks are allocated with whole tiles of zero rows), G through LDS
     rl_to_lds<T, PP>(sG, g);
     __syncthreads();
-    gram_tile<T, PP>(sX, sG, kacc);
+    gram_tile<T, PP>(X + t * TR * PP, sG, kacc);
     __syncthreads();
   }
   const int64_t nv = PP * PP + 3;
@@ -251,122 +250,178 @@ __global__ __launch_bounds__(WG) void k_update(int64_t n, T* __restrict__ X, T* 
 }
 
 // ---------------------------------------------------------------- block SpMM
-// Z = A_op W for a full symmetric CSR, W and Z row-major n x PP. A row is handled by
-// LPR = PP / 4 lanes, each owning 4 consecutive columns. Optional Gram epilogue over the
-// workgroup's TR rows: W^T Z and (if Y3 != nullptr) W^T Y3. Partials: 1 or 2 PP*PP.
-// sel: which buffers to use: 0 = fixed (W, Z as given), 1 = W is P of the current
-// iteration (picked by parity from W/W1), for the iteration's SpMM.
-template <typename T, int PP, bool GRAMS>
+// Z = A_op W for a full symmetric CSR, W and Z row-major n x PP. One workgroup per TR-row
+// tile; the tiles are dealt so that the workgroups running on one XCD (blockIdx.x congruent
+// mod 8) sweep one contiguous slab of rows, which keeps the stencil neighbours of a slab
+// in that XCD's L2. A row is handled by LPR = PP / 4 lanes, each owning 4 consecutive
+// columns; the column indices and values of up to 8 nonzeros are loaded before the 8
+// gathers are issued, so each lane has up to 8 independent loads in flight.
+// mode 0: always run, W = W0. mode 1: the iteration's SpMM (skipped when the solve is done
+// or the step is null), W = P of the current iteration (W0/W1 by parity). mode 2: explicit
+// A X (runs only when requested).
+__device__ __forceinline__ bool spmm_skip(const Scalars* sc, int mode) {
+  if (mode == 1) return sc->done || sc->null_step;
+  if (mode == 2) return sc->done || sc->null_step || !sc->refresh;
+  return false;
+}
+
+__device__ __forceinline__ int64_t xcd_tile(int64_t ntiles) {
+  const int64_t per = (ntiles + 7) / 8;
+  return (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+}
+
+template <typename T, int PP>
 __global__ __launch_bounds__(WG) void k_spmm(int64_t n, const int32_t* __restrict__ rowptr,
                                              const int32_t* __restrict__ colind, const T* __restrict__ vals,
                                              const T* __restrict__ W0, const T* __restrict__ W1, T* __restrict__ Z,
-                                             const T* __restrict__ Y3, const Scalars* __restrict__ sc, int mode,
-                                             double* __restrict__ partials) {
-  // mode 0: always run, W = W0. mode 1: iteration SpMM (skip when done / null step),
-  // W = P of the current iteration. mode 2: refresh A X (run only when sc->refresh).
-  if (mode == 1 && (sc->done || sc->null_step)) return;
-  if (mode == 2 && (sc->done || sc->null_step || !sc->refresh)) return;
-  const T* W = W0;
-  if (mode == 1) W = ((sc->k & 1) ? W1 : W0);
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  T* sW = reinterpret_cast<T*>(lds_raw);
-  T* sZ = sW + TR * PP;
-  T* sY = sZ + TR * PP;
+                                             const Scalars* __restrict__ sc, int mode) {
+  if (spmm_skip(sc, mode)) return;
+  const T* W = (mode == 1 && (sc->k & 1)) ? W1 : W0;
   constexpr int EPL = 4;
-  constexpr int LPR = PP / EPL;       // lanes per row
-  constexpr int RPW = 64 / LPR;       // rows per wave pass
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int sub = l / LPR, lane = l % LPR;
+  constexpr int LPR = PP / EPL;  // lanes per row
+  constexpr int RPB = WG / LPR;  // rows per block pass
+  constexpr int U = 8;           // nonzeros per batch
   const int64_t ntiles = (n + TR - 1) / TR;
-  int64_t t0, t1;
-  tile_range(ntiles, t0, t1);
-  typename Vec4<T>::type zacc[GRAMS ? GramSplit<PP>::PER_WAVE : 1], yacc[GRAMS ? GramSplit<PP>::PER_WAVE : 1];
-  if constexpr (GRAMS) {
-    gram_zero<T, PP>(zacc);
-    gram_zero<T, PP>(yacc);
-  }
-  for (int64_t t = t0; t < t1; ++t) {
+  const int64_t t = xcd_tile(ntiles);
+  if (t >= ntiles) return;
+  const int sub = threadIdx.x / LPR, lane = threadIdx.x % LPR;
 #pragma unroll
-    for (int pass = 0; pass < 16 / RPW; ++pass) {
-      const int lrow = 16 * w + pass * RPW + sub;
-      const int64_t row = t * TR + lrow;
-      T acc[EPL] = {T(0), T(0), T(0), T(0)};
-      if (row < n) {
-        const int32_t j0 = rowptr[row], j1 = rowptr[row + 1];
-        int32_t j = j0;
-        for (; j + 1 < j1; j += 2) {
-          const int32_t ca = colind[j], cbb = colind[j + 1];
-          const T va = vals[j], vb = vals[j + 1];
-          const T* pa = W + (int64_t)ca * PP + EPL * lane;
-          const T* pb = W + (int64_t)cbb * PP + EPL * lane;
+  for (int pass = 0; pass < TR / RPB; ++pass) {
+    const int64_t row = t * TR + pass * RPB + sub;
+    if (row >= n) continue;
+    T acc[EPL] = {T(0), T(0), T(0), T(0)};
+    const int32_t j0 = rowptr[row], j1 = rowptr[row + 1];
+    for (int32_t j = j0; j < j1; j += U) {
+      int32_t col[U];
+      T v[U];
 #pragma unroll
-          for (int e = 0; e < EPL; ++e) acc[e] += va * pa[e];
+      for (int u = 0; u < U; ++u) {
+        const bool ok = j + u < j1;
+        col[u] = ok ? colind[j + u] : 0;
+        v[u] = ok ? vals[j + u] : T(0);
+      }
+      T x[U][EPL];
 #pragma unroll
-          for (int e = 0; e < EPL; ++e) acc[e] += vb * pb[e];
+      for (int u = 0; u < U; ++u) {
+        const T* src = W + (int64_t)col[u] * PP + EPL * lane;
+        if constexpr (sizeof(T) == 8) {
+          const double2 q0 = *reinterpret_cast<const double2*>(src);
+          const double2 q1 = *reinterpret_cast<const double2*>(src + 2);
+          x[u][0] = q0.x; x[u][1] = q0.y; x[u][2] = q1.x; x[u][3] = q1.y;
+        } else {
+          const float4 q = *reinterpret_cast<const float4*>(src);
+          x[u][0] = q.x; x[u][1] = q.y; x[u][2] = q.z; x[u][3] = q.w;
         }
-        if (j < j1) {
-          const int32_t ca = colind[j];
-          const T va = vals[j];
-          const T* pa = W + (int64_t)ca * PP + EPL * lane;
-#pragma unroll
-          for (int e = 0; e < EPL; ++e) acc[e] += va * pa[e];
-        }
-        T* zr = Z + row * PP + EPL * lane;
-#pragma unroll
-        for (int e = 0; e < EPL; ++e) zr[e] = acc[e];
       }
-      if constexpr (GRAMS) {
 #pragma unroll
-        for (int e = 0; e < EPL; ++e) sZ[lrow * PP + EPL * lane + e] = acc[e];
-      }
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) acc[e] += v[u] * x[u][e];
     }
-    if constexpr (GRAMS) {
-      // own rows of W (and Y3) into LDS
-      for (int i = threadIdx.x; i < TR * PP; i += WG) {
-        const int64_t row = t * TR + i / PP;
-        sW[i] = row < n ? W[row * PP + (i % PP)] : T(0);
-        if (Y3) sY[i] = row < n ? Y3[row * PP + (i % PP)] : T(0);
-      }
-      __syncthreads();
-      gram_tile<T, PP>(sW, sZ, zacc);
-      if (Y3) gram_tile<T, PP>(sW, sY, yacc);
-      __syncthreads();
+    T* zr = Z + row * PP + EPL * lane;
+    if constexpr (sizeof(T) == 8) {
+      *reinterpret_cast<double2*>(zr) = make_double2(acc[0], acc[1]);
+      *reinterpret_cast<double2*>(zr + 2) = make_double2(acc[2], acc[3]);
+    } else {
+      *reinterpret_cast<float4*>(zr) = make_float4(acc[0], acc[1], acc[2], acc[3]);
     }
-  }
-  if constexpr (GRAMS) {
-    const int64_t nv = (Y3 ? 2 : 1) * PP * PP;
-    double* out = partials + (int64_t)blockIdx.x * nv;
-    gram_store<T, PP>(out, zacc);
-    if (Y3) gram_store<T, PP>(out + PP * PP, yacc);
   }
 }
 
-// ---------------------------------------------------------------- generic passes
-// Partials of A^T B (PP*PP per workgroup).
+// ---------------------------------------------------------------- Gram pass
+// Partials of A^T B1 and (when B2 != nullptr) A^T B2 over the workgroup's rows, without LDS.
+// At k-step s a lane (g = l/16, c = l%16) reads row 4s+g, columns c*V .. c*V+V-1 of each
+// operand (V = PP/16 contiguous values, one or two 16-byte loads), so every row is read
+// once per operand, fully coalesced. "Virtual block" vb of a lane's V values holds the
+// columns {c*V + vb}; MFMA unit (gram, ib) accumulates the 16 x 16 blocks (ib, jb) for all
+// jb, i.e. Gram entries (i*V + ib, j*V + jb). Units are dealt to the 4 waves so that a
+// wave works on one Gram only. With mode 1 / 2 the pass follows the SpMM of the same
+// mode (skip rules; A = P by parity for mode 1).
 template <typename T, int PP>
-__global__ __launch_bounds__(WG) void k_gram(int64_t n, const T* __restrict__ A, const T* __restrict__ B,
+struct GramUnits {
+  static constexpr int V = PP / 16;
+  static constexpr int MAXU = (2 * V + 3) / 4;  // units per wave with two Grams
+};
+
+template <typename T, int V>
+__device__ __forceinline__ void load_row_v(const T* __restrict__ B, int64_t row, int64_t n, int c, T (&v)[V]) {
+  const bool ok = row < n;
+  const T* p = B + (ok ? row : 0) * (16 * V) + V * c;
+  if constexpr (sizeof(T) * V == 32) {
+    if constexpr (sizeof(T) == 8) {
+      const double2 q0 = ok ? *reinterpret_cast<const double2*>(p) : make_double2(0.0, 0.0);
+      const double2 q1 = ok ? *reinterpret_cast<const double2*>(p + 2) : make_double2(0.0, 0.0);
+      v[0] = q0.x; v[1] = q0.y; v[2] = q1.x; v[3] = q1.y;
+    } else {
+      const float4 q0 = ok ? *reinterpret_cast<const float4*>(p) : make_float4(0.f, 0.f, 0.f, 0.f);
+      const float4 q1 = ok ? *reinterpret_cast<const float4*>(p + 4) : make_float4(0.f, 0.f, 0.f, 0.f);
+      v[0] = q0.x; v[1] = q0.y; v[2] = q0.z; v[3] = q0.w;
+      v[4] = q1.x; v[5] = q1.y; v[6] = q1.z; v[7] = q1.w;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < V; ++e) v[e] = ok ? p[e] : T(0);
+  }
+}
+
+template <typename T, int PP>
+__global__ __launch_bounds__(WG) void k_gram(int64_t n, const T* __restrict__ A0, const T* __restrict__ A1,
+                                             const T* __restrict__ B1, const T* __restrict__ B2,
+                                             const Scalars* __restrict__ sc, int mode,
                                              double* __restrict__ partials) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  T* sA = reinterpret_cast<T*>(lds_raw);
-  T* sB = sA + TR * PP;
-  const int w = threadIdx.x >> 6;
+  if (spmm_skip(sc, mode)) return;
+  constexpr int V = GramUnits<T, PP>::V;
+  constexpr int MAXU = GramUnits<T, PP>::MAXU;
+  const T* A = (mode == 1 && (sc->k & 1)) ? A1 : A0;
+  const int ng = B2 ? 2 : 1;
+  const int units = ng * V;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+  // unit u = w + 4q: gram = u % ng, ib = u / ng
+  const int gsel = w % ng;
+  const T* B = gsel ? B2 : B1;
+  const int nu = (units > w) ? (units - w + 3) / 4 : 0;
   const int64_t ntiles = (n + TR - 1) / TR;
   int64_t t0, t1;
   tile_range(ntiles, t0, t1);
-  typename Vec4<T>::type acc[GramSplit<PP>::PER_WAVE];
-  gram_zero<T, PP>(acc);
-  for (int64_t t = t0; t < t1; ++t) {
-    const int64_t row0 = t * TR + 16 * w;
-    T a[PP / 16][4], b[PP / 16][4];
-    load_rl<T, PP>(A, row0, n, a);
-    load_rl<T, PP>(B, row0, n, b);
-    rl_to_lds<T, PP>(sA, a);
-    rl_to_lds<T, PP>(sB, b);
-    __syncthreads();
-    gram_tile<T, PP>(sA, sB, acc);
-    __syncthreads();
+  typename Vec4<T>::type acc[MAXU][V];
+#pragma unroll
+  for (int q = 0; q < MAXU; ++q)
+#pragma unroll
+    for (int jb = 0; jb < V; ++jb) acc[q][jb] = typename Vec4<T>::type{0, 0, 0, 0};
+  if (nu > 0) {
+    for (int64_t t = t0; t < t1; ++t) {
+#pragma unroll 2
+      for (int s = 0; s < TR / 4; ++s) {
+        const int64_t row = t * TR + 4 * s + g;
+        T a[V], b[V];
+        load_row_v<T, V>(A, row, n, c, a);
+        load_row_v<T, V>(B, row, n, c, b);
+#pragma unroll
+        for (int q = 0; q < MAXU; ++q) {
+          if (q < nu) {
+            const int ib = (w + 4 * q) / ng;
+#pragma unroll
+            for (int jb = 0; jb < V; ++jb) acc[q][jb] = mfma(a[ib], b[jb], acc[q][jb]);
+          }
+        }
+      }
+    }
   }
-  gram_store<T, PP>(partials + (int64_t)blockIdx.x * PP * PP, acc);
+  double* out = partials + (int64_t)blockIdx.x * ng * PP * PP;
+#pragma unroll
+  for (int q = 0; q < MAXU; ++q) {
+    if (q < nu) {
+      const int ib = (w + 4 * q) / ng;
+      double* o = out + gsel * PP * PP;
+#pragma unroll
+      for (int jb = 0; jb < V; ++jb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = rowof<T>(g, r);
+          o[(i * V + ib) * PP + c * V + jb] = (double)acc[q][jb][r];
+        }
+    }
+  }
 }
 
 // OUT = IN M (M from the small buffer, PP x PP). IN and OUT may alias.
@@ -422,7 +477,9 @@ __global__ __launch_bounds__(WG) void k_colres(int64_t n, const T* __restrict__ 
 }
 
 // ---------------------------------------------------------------- reduction
-// out[v] = sum_b partials[b * nv + v] (fixed order) for v < max_from, max over b otherwise.
+// out[v] = sum_b partials[b * nv + v] for v < max_from, max over b otherwise. A workgroup
+// covers 64 consecutive values with 4 slices of the nb partials each (b = q, q+4, ...);
+// the slices are combined in a fixed order, so the result is deterministic.
 // cond: 0 always; 1 skip when the solve is done or the step is null; 2 run only when an
 // explicit A X refresh was requested; 3 skip when the solve is done.
 __global__ __launch_bounds__(WG) void k_reduce(const double* __restrict__ partials, int nb, int64_t nv,
@@ -431,15 +488,31 @@ __global__ __launch_bounds__(WG) void k_reduce(const double* __restrict__ partia
   if (cond == 1 && (sc->done || sc->null_step)) return;
   if (cond == 2 && (sc->done || sc->null_step || !sc->refresh)) return;
   if (cond == 3 && sc->done) return;
-  const int64_t v = (int64_t)blockIdx.x * WG + threadIdx.x;
-  if (v >= nv) return;
+  __shared__ double part[4][64];
+  const int q = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t v = (int64_t)blockIdx.x * 64 + l;
+  const bool use_max = v >= max_from;
   double s = 0.0;
-  if (v < max_from) {
-    for (int b = 0; b < nb; ++b) s += partials[(int64_t)b * nv + v];
-  } else {
-    for (int b = 0; b < nb; ++b) s = fmax(s, partials[(int64_t)b * nv + v]);
+  if (v < nv) {
+    int b = q;
+    for (; b + 28 < nb; b += 32) {
+      double x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = partials[(int64_t)(b + 4 * u) * nv + v];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s = use_max ? fmax(s, x[u]) : s + x[u];
+    }
+    for (; b < nb; b += 4) {
+      const double x = partials[(int64_t)b * nv + v];
+      s = use_max ? fmax(s, x) : s + x;
+    }
   }
-  out[v] = s;
+  part[q][l] = s;
+  __syncthreads();
+  if (q == 0 && v < nv) {
+    out[v] = use_max ? fmax(fmax(part[0][l], part[1][l]), fmax(part[2][l], part[3][l]))
+                     : (part[0][l] + part[1][l]) + (part[2][l] + part[3][l]);
+  }
 }
 
 // ---------------------------------------------------------------- packing and checks
@@ -515,13 +588,13 @@ template <typename T, int PP>
 int lds_bytes(Pass pass) {
   const int m = PP * PP * (int)sizeof(T), tile = TR * PP * (int)sizeof(T);
   switch (pass) {
-    case Pass::Grad: return m + 2 * tile;
+    case Pass::Grad: return m + tile;
     case Pass::Dir: return m + tile;
     case Pass::Update: return m;
     case Pass::UpdateGrams: return m + 3 * tile;
-    case Pass::Spmm: return 3 * tile;
+    case Pass::Spmm: return 0;
     case Pass::SpmmPlain: return 0;
-    case Pass::Gram: return 2 * tile;
+    case Pass::Gram: return 0;
     case Pass::Product: return m;
   }
   return 0;
@@ -538,8 +611,6 @@ hipError_t set_lds_limits() {
   GSI_SET((k_dir<T, PP>), Pass::Dir)
   GSI_SET((k_update<T, PP, false>), Pass::Update)
   GSI_SET((k_update<T, PP, true>), Pass::UpdateGrams)
-  GSI_SET((k_spmm<T, PP, true>), Pass::Spmm)
-  GSI_SET((k_gram<T, PP>), Pass::Gram)
   GSI_SET((k_product<T, PP>), Pass::Product)
 #undef GSI_SET
   return e;
@@ -564,17 +635,16 @@ void Kernels<T, PP>::update(hipStream_t st, int nb, int64_t n, T* X, T* Y, const
     k_update<T, PP, false><<<nb, WG, lds_bytes<T, PP>(Pass::Update), st>>>(n, X, Y, P0, P1, Z, small, sc, partials);
 }
 template <typename T, int PP>
-void Kernels<T, PP>::spmm(hipStream_t st, int nb, int64_t n, const int32_t* rowptr, const int32_t* colind,
-                          const T* vals, const T* W0, const T* W1, T* Z, const T* Y3, const Scalars* sc, int mode,
-                          bool grams, double* partials) {
-  if (grams)
-    k_spmm<T, PP, true><<<nb, WG, lds_bytes<T, PP>(Pass::Spmm), st>>>(n, rowptr, colind, vals, W0, W1, Z, Y3, sc, mode, partials);
-  else
-    k_spmm<T, PP, false><<<nb, WG, 0, st>>>(n, rowptr, colind, vals, W0, W1, Z, Y3, sc, mode, partials);
+void Kernels<T, PP>::spmm(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind, const T* vals,
+                          const T* W0, const T* W1, T* Z, const Scalars* sc, int mode) {
+  const int64_t ntiles = (n + TR - 1) / TR;
+  const int64_t grid = 8 * ((ntiles + 7) / 8);
+  k_spmm<T, PP><<<dim3((unsigned)grid), dim3(WG), 0, st>>>(n, rowptr, colind, vals, W0, W1, Z, sc, mode);
 }
 template <typename T, int PP>
-void Kernels<T, PP>::gram(hipStream_t st, int nb, int64_t n, const T* A, const T* B, double* partials) {
-  k_gram<T, PP><<<nb, WG, lds_bytes<T, PP>(Pass::Gram), st>>>(n, A, B, partials);
+void Kernels<T, PP>::gram(hipStream_t st, int nb, int64_t n, const T* A0, const T* A1, const T* B1, const T* B2,
+                          const Scalars* sc, int mode, double* partials) {
+  k_gram<T, PP><<<nb, WG, 0, st>>>(n, A0, A1, B1, B2, sc, mode, partials);
 }
 template <typename T, int PP>
 void Kernels<T, PP>::product(hipStream_t st, int nb, int64_t n, const T* IN, T* OUT, const double* M) {
@@ -592,7 +662,7 @@ hipError_t Kernels<T, PP>::init() {
 
 void launch_reduce(hipStream_t st, const double* partials, int nb, int64_t nv, int64_t max_from, double* out,
                    const Scalars* sc, int cond) {
-  const int blocks = (int)((nv + WG - 1) / WG);
+  const int blocks = (int)((nv + 63) / 64);
   hipLaunchKernelGGL(k_reduce, dim3(blocks), dim3(WG), 0, st, partials, nb, nv, max_from, out, sc, cond);
 }
 

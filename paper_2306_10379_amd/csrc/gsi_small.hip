@@ -1,9 +1,11 @@
 // Single-workgroup float64 solves on the p x p projected problem: the stop test and
 // Polak-Ribiere coefficient, the eigendecomposition of P^T P (parallel cyclic Jacobi in
-// LDS), the line-search diagonals, the exact line search (bracket from the branch roots,
-// Brent's method on phi'), the retraction factor M, Cholesky QR and Rayleigh-Ritz.
-// The matrices live in the small buffer with row stride PP (>= p); only the leading
-// p x p block is meaningful and the padding is kept at zero.
+// LDS, warm-started from the previous iteration's eigenvectors), the line-search diagonals,
+// the exact line search (bracket from the branch roots, Brent's method on phi'), the
+// retraction factor M, Cholesky QR and Rayleigh-Ritz.
+//
+// The p x p matrices live in the small buffer as PP x PP row-major arrays (PP = p rounded
+// up to 16) whose padding is zero; dense products among them use f64 MFMA.
 #include <math.h>
 
 #include "gsi_kernels.h"
@@ -19,44 +21,50 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// ---------------------------------------------------------------- helpers (whole workgroup)
+// ---------------------------------------------------------------- dense PP x PP products
 
-// C (p x p, stride ld) = A * B, or A^T * B when ta. Reads/writes any memory space.
-__device__ void mm(int p, int ld, const double* A, const double* B, double* C, bool ta) {
-  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
-    const int i = e / p, j = e % p;
-    double s = 0.0;
-    if (ta)
-      for (int k = 0; k < p; ++k) s += A[k * ld + i] * B[k * ld + j];
-    else
-      for (int k = 0; k < p; ++k) s += A[i * ld + k] * B[k * ld + j];
-    C[i * ld + j] = s;
+// Cout = alpha * op(A) op(B) for PP x PP row-major operands (any memory space), f64 MFMA,
+// 16 x 16 output blocks dealt to the 4 waves. No barrier inside.
+template <int PP>
+__device__ void wg_mm(const double* A, bool ta, const double* B, bool tb, double* Cout, double alpha = 1.0) {
+  constexpr int NBK = PP / 16;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+  for (int blk = w; blk < NBK * NBK; blk += 4) {
+    const int ib = blk / NBK, jb = blk % NBK;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int s = 0; s < PP / 4; ++s) {
+      const int k = 4 * s + g;
+      const double a = ta ? A[k * PP + 16 * ib + c] : A[(16 * ib + c) * PP + k];
+      const double b = tb ? B[(16 * jb + c) * PP + k] : B[k * PP + 16 * jb + c];
+      acc = mfma(a, b, acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Cout[(16 * ib + g + 4 * r) * PP + 16 * jb + c] = alpha * acc[r];
   }
 }
 
-// diag(V^T A V)_i for i < p (A not necessarily symmetric), into out[i].
-__device__ void vtav_diag(int p, int ld, const double* V, const double* A, double* tmp, double* out) {
-  // tmp = A V
-  mm(p, ld, A, V, tmp, false);
-  __syncthreads();
-  for (int i = threadIdx.x; i < p; i += blockDim.x) {
+// out[i] = sign * sum_k V[k][i] T[k][i]  (the diagonal of V^T T), i < PP.
+template <int PP>
+__device__ void col_dots(const double* V, const double* T, double* out, double sign) {
+  for (int i = threadIdx.x; i < PP; i += blockDim.x) {
     double s = 0.0;
-    for (int k = 0; k < p; ++k) s += V[k * ld + i] * tmp[k * ld + i];
-    out[i] = s;
+    for (int k = 0; k < PP; ++k) s += V[k * PP + i] * T[k * PP + i];
+    out[i] = sign * s;
   }
-  __syncthreads();
 }
 
-// Parallel cyclic Jacobi (round-robin pairs, Brent-Luk ordering) for a symmetric p x p
-// matrix A in LDS (stride ld). On return the diagonal of A holds the eigenvalues and V
-// (LDS, stride ld) the eigenvectors as columns. V must hold an orthogonal starting basis
-// (normally I) on entry and is multiplied by the rotations. Returns the sweep count.
+// ---------------------------------------------------------------- Jacobi
+
+// Parallel cyclic Jacobi (round-robin pairs) on the leading p x p block of the symmetric
+// matrix A (LDS, stride ld). On return the diagonal of A holds the eigenvalues and V
+// (LDS, stride ld) has been multiplied by all rotations. A rotation is skipped when its
+// pivot is below eps * ||A||_F or eps * sqrt(|a_uu a_vv|); the sweeps stop when a whole
+// sweep skips every rotation. Returns the number of sweeps.
 __device__ int jacobi(int p, int ld, double* A, double* V, double* cs /* 2*MAXP */, int* uv /* MAXP */,
-                      int* flag) {
+                      int* nrot_s, int* any_s) {
   const int m = p + (p & 1);
   const int half = m / 2;
-  // absolute threshold: eps * ||A||_F (a rotation is skipped when the pivot is below it or
-  // below eps * sqrt(|a_uu a_vv|)); accuracy is then that of a backward-stable solver
   __shared__ double fro;
   if (threadIdx.x < 64) {
     double s = 0.0;
@@ -71,39 +79,48 @@ __device__ int jacobi(int p, int ld, double* A, double* V, double* cs /* 2*MAXP 
   const double athr = EPS * fro;
   int sweep = 0;
   for (; sweep < 40; ++sweep) {
-    if (threadIdx.x == 0) *flag = 0;
-    __syncthreads();
+    if (threadIdx.x == 0) *any_s = 0;
     for (int round = 0; round < m - 1; ++round) {
-      if ((int)threadIdx.x < half) {
+      if (threadIdx.x < 64) {  // wave 0: rotation parameters, compacted to the rotating pairs
         const int i = threadIdx.x;
-        // circle method: position 0 fixed, positions 1..m-1 rotate
-        auto player = [&](int pos) { return pos == 0 ? 0 : ((pos - 1 + round) % (m - 1)) + 1; };
-        int u = player(i), v = player(m - 1 - i);
-        if (u > v) { int t = u; u = v; v = t; }
+        bool rot = false;
         double c = 1.0, s = 0.0;
-        int code = -1;
-        if (v < p) {
-          const double auu = A[u * ld + u], avv = A[v * ld + v], auv = A[u * ld + v];
-          if (fabs(auv) > EPS * sqrt(fabs(auu * avv)) && fabs(auv) > athr && fabs(auv) > 1e-300) {
-            const double tau = (avv - auu) / (2.0 * auv);
-            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
-            code = u * MAXP + v;
-            *flag = 1;
+        int code = 0;
+        if (i < half) {
+          auto player = [&](int pos) { return pos == 0 ? 0 : ((pos - 1 + round) % (m - 1)) + 1; };
+          int u = player(i), v = player(m - 1 - i);
+          if (u > v) { const int t = u; u = v; v = t; }
+          if (v < p) {
+            const double auu = A[u * ld + u], avv = A[v * ld + v], auv = A[u * ld + v];
+            if (fabs(auv) > athr && fabs(auv) > EPS * sqrt(fabs(auu * avv)) && fabs(auv) > 1e-300) {
+              const double tau = (avv - auu) / (2.0 * auv);
+              const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+              c = 1.0 / sqrt(1.0 + t * t);
+              s = t * c;
+              code = u * MAXP + v;
+              rot = true;
+            }
           }
         }
-        cs[2 * i] = c;
-        cs[2 * i + 1] = s;
-        uv[i] = code;
+        const uint64_t mask = __ballot(rot);
+        if (rot) {
+          const int idx = __popcll(mask & ((1ull << i) - 1ull));
+          cs[2 * idx] = c;
+          cs[2 * idx + 1] = s;
+          uv[idx] = code;
+        }
+        if (i == 0) {
+          *nrot_s = __popcll(mask);
+          if (mask) *any_s = 1;
+        }
       }
       __syncthreads();
+      const int nrot = *nrot_s;
+      if (nrot == 0) continue;  // uniform: every thread read the same value after the barrier
       // rows: A <- J^T A
-      for (int e = threadIdx.x; e < half * p; e += blockDim.x) {
+      for (int e = threadIdx.x; e < nrot * p; e += blockDim.x) {
         const int i = e / p, k = e % p;
-        const int code = uv[i];
-        if (code < 0) continue;
-        const int u = code / MAXP, v = code % MAXP;
+        const int u = uv[i] / MAXP, v = uv[i] % MAXP;
         const double c = cs[2 * i], s = cs[2 * i + 1];
         const double au = A[u * ld + k], av = A[v * ld + k];
         A[u * ld + k] = c * au - s * av;
@@ -111,11 +128,9 @@ __device__ int jacobi(int p, int ld, double* A, double* V, double* cs /* 2*MAXP 
       }
       __syncthreads();
       // columns: A <- A J, V <- V J
-      for (int e = threadIdx.x; e < half * p; e += blockDim.x) {
+      for (int e = threadIdx.x; e < nrot * p; e += blockDim.x) {
         const int i = e / p, k = e % p;
-        const int code = uv[i];
-        if (code < 0) continue;
-        const int u = code / MAXP, v = code % MAXP;
+        const int u = uv[i] / MAXP, v = uv[i] % MAXP;
         const double c = cs[2 * i], s = cs[2 * i + 1];
         const double au = A[k * ld + u], av = A[k * ld + v];
         A[k * ld + u] = c * au - s * av;
@@ -126,11 +141,12 @@ __device__ int jacobi(int p, int ld, double* A, double* V, double* cs /* 2*MAXP 
       }
       __syncthreads();
     }
-    if (*flag == 0) break;
+    __syncthreads();
+    if (*any_s == 0) break;
     __syncthreads();
   }
   __syncthreads();
-  return sweep;
+  return sweep + 1;
 }
 
 // ---------------------------------------------------------------- line search (wave 0)
@@ -154,14 +170,15 @@ __device__ double dphi(const Terms& T, int p, double mu) {
 }
 
 // Get_Mu (Algorithm 3, Sec. 5.2, Sec. 6.1): returns mu > 0 or -1 when no usable bracket.
-// Called by wave 0 only; *evals counts phi' evaluations.
-__device__ double get_mu(Terms& T, int p, int* evals) {
+// Called by wave 0 only; p terms (padding terms have b = 0), preal the block size for the
+// activity threshold; *evals counts phi' evaluations.
+__device__ double get_mu(Terms& T, int p, int preal, int* evals) {
   const int l = threadIdx.x & 63;
   const double bl = l < p ? T.b[l] : 0.0;
   const double bmax = wave_max(bl);
   int ev = 0;
   if (!(bmax > 0.0)) { *evals = 0; return -1.0; }
-  const bool act = l < p && bl > p * EPS * bmax;
+  const bool act = l < p && bl > preal * EPS * bmax;
   if (l < p) T.act[l] = act ? 1 : 0;
   wave_sync();
   const bool conv = act && T.z[l] > 0.0;
@@ -221,7 +238,6 @@ __device__ double get_mu(Terms& T, int p, int* evals) {
   // safeguarded by bisection, on phi' over [lo, hi] with flo < 0 < fhi.
   double a = lo, b = hi, c = lo, fa = flo, fb = fhi, fc = flo;
   double d = b - a, e = d;
-  c = a; fc = fa;
   for (int it = 0; it < 200; ++it) {
     if ((fb > 0.0 && fc > 0.0) || (fb < 0.0 && fc < 0.0)) {
       c = a; fc = fa; d = b - a; e = d;
@@ -298,12 +314,18 @@ __global__ __launch_bounds__(WG) void k_after_grad(int PP, const double* __restr
       if (k + 1 > sc->hist_len) sc->hist_len = k + 1;
     }
     double beta = 0.0;
+    if (k == 0 || rho <= 0.5 * sc->rho_best) {
+      sc->rho_best = rho;
+      sc->k_best = k;
+    }
     if (!isfinite(gg)) {
       sc->done = 3;
     } else if (rho <= sc->tol) {
       sc->done = 1;
     } else if (k >= sc->max_iter) {
       sc->done = 2;
+    } else if (sc->stall_window > 0 && k - sc->k_best > sc->stall_window) {
+      sc->done = 4;  // stagnation: the block precision cannot resolve further progress
     } else {
       const bool restart = sc->method == 1 || k == 0 || sc->restart_next ||
                            (sc->k_restart > 0 && k % sc->k_restart == 0) || !(sc->gg_old > 0.0);
@@ -351,61 +373,101 @@ __global__ __launch_bounds__(WG) void k_after_dir(int PP, const double* __restri
   }
 }
 
-__global__ __launch_bounds__(WG) void k_linesearch(int PP, const double* __restrict__ red, double* __restrict__ small,
+// Eigendecomposition P^T P = V diag(b) V^T (Sec. 5.2). Warm start: the previous V, made
+// orthonormal again by one Newton-Schulz step V <- V (3 I - V^T V) / 2, turns S into a
+// nearly diagonal V^T S V when the directions change little from step to step. Writes V
+// (small[S_V]) and b (small[S_VEC ...]).
+template <int PP>
+__global__ __launch_bounds__(WG) void k_eig(double* __restrict__ small, Scalars* __restrict__ sc) {
+  if (sc->done || sc->null_step) return;
+  // this single workgroup shares its CU with the SpMM running concurrently: raise its
+  // waves' issue priority so the latency-bound rotation rounds are not starved
+  __builtin_amdgcn_s_setprio(3);
+  // three PP x (PP + 1) buffers: the products use stride PP, the rotations stride PP + 1
+  // (an odd stride in doubles keeps the column sweeps of the rotations free of LDS bank
+  // conflicts)
+  constexpr int LP = PP + 1;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  double* A = reinterpret_cast<double*>(lds_raw);
+  double* V = A + PP * LP;
+  double* T = V + PP * LP;
+  __shared__ double cs[2 * MAXP];
+  __shared__ int uv[MAXP];
+  __shared__ int nrot, anyr;
+  const int p = sc->p;
+  const bool warm = sc->v_valid != 0;
+  const double* S = small + S_S * PP * PP;
+  double* Vg = small + S_V * PP * PP;
+  if (warm) {
+    wg_mm<PP>(Vg, true, Vg, false, T);  // T = V^T V
+    __syncthreads();
+    for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) T[e] = 0.5 * (((e / PP) == (e % PP) ? 3.0 : 0.0) - T[e]);
+    __syncthreads();
+    wg_mm<PP>(Vg, false, T, false, V);  // V = V (3I - V^T V) / 2
+  } else {
+    for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) V[e] = (e / PP) == (e % PP) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  wg_mm<PP>(S, false, V, false, T);  // T = S V
+  __syncthreads();
+  wg_mm<PP>(V, true, T, false, A);  // A = V^T S V
+  __syncthreads();
+  // re-lay A (into T) and V (into A) with stride LP for the rotations
+  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) T[(e / PP) * LP + e % PP] = A[e];
+  __syncthreads();
+  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) A[(e / PP) * LP + e % PP] = V[e];
+  __syncthreads();
+  double* Ap = T;
+  double* Vp = A;
+  const int sweeps = jacobi(p, LP, Ap, Vp, cs, uv, &nrot, &anyr);
+  double* b = small + S_VEC * PP * PP;
+  for (int i = threadIdx.x; i < PP; i += blockDim.x) b[i] = i < p ? fmax(Ap[i * LP + i], 0.0) : 0.0;
+  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) Vg[e] = Vp[(e / PP) * LP + e % PP];
+  if (threadIdx.x == 0) {
+    sc->v_valid = 1;
+    sc->sweeps = sweeps;
+    sc->n_sweeps += sweeps;
+  }
+}
+
+// Line search and retraction factor (Sec. 5.2, Algorithm 3, Sec. 6.1), from V and b of
+// k_eig and the reduced Grams P^T A P, P^T A X of the SpMM (red).
+template <int PP>
+__global__ __launch_bounds__(WG) void k_linesearch(const double* __restrict__ red, double* __restrict__ small,
                                                    Scalars* __restrict__ sc, double* __restrict__ hist,
                                                    int recompute_ax) {
   if (sc->done || sc->null_step) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  const int p = sc->p;
-  const int ld = p;
-  double* A = reinterpret_cast<double*>(lds_raw);
-  double* V = A + MAXP * MAXP;
-  double* Tm = V + MAXP * MAXP;
-  double* Cc = Tm;                 // p x p scratch
-  double* tmp = Tm + MAXP * MAXP;  // p x p scratch
+  double* V = reinterpret_cast<double*>(lds_raw);
+  double* Mc = V + PP * PP;
+  double* T1 = Mc + PP * PP;
+  double* T2 = T1 + PP * PP;
   __shared__ Terms terms;
-  __shared__ double cs[2 * MAXP];
-  __shared__ int uv[MAXP];
-  __shared__ int flag;
   __shared__ double smu;
   __shared__ int sok;
+  const int p = sc->p;
   const double* PZr = red;
   const double* PYr = red + PP * PP;
-  double* S = small + S_S * PP * PP;
+  const double* S = small + S_S * PP * PP;
   double* C = small + S_C * PP * PP;
-  double* PZ = small + S_PZ * PP * PP;
-  double* PY = small + S_PY * PP * PP;
-  // load S into A (compact stride p), V = I; keep symmetrized P^T A P and raw P^T A X
-  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
-    const int i = e / p, j = e % p;
-    A[e] = S[i * PP + j];
-    V[e] = (i == j) ? 1.0 : 0.0;
-  }
-  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) {
-    const int i = e / PP, j = e % PP;
-    PZ[e] = 0.5 * (PZr[i * PP + j] + PZr[j * PP + i]);
-    PY[e] = PYr[e];
-  }
+  const double* bvec = small + S_VEC * PP * PP;
+  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) V[e] = small[S_V * PP * PP + e];
+  for (int i = threadIdx.x; i < MAXP; i += blockDim.x) terms.b[i] = i < PP ? bvec[i] : 0.0;
   __syncthreads();
-  jacobi(p, ld, A, V, cs, uv, &flag);
-  // line-search diagonals (Sec. 5.2, eq. CG_linesearch_D) in the basis V
-  for (int i = threadIdx.x; i < p; i += blockDim.x) terms.b[i] = fmax(A[i * ld + i], 0.0);
+  // line-search diagonals (Sec. 5.2, eq. CG_linesearch_D) in the basis V; the diagonal of
+  // V^T B V only needs the symmetric part of B, so the raw Grams are used
+  wg_mm<PP>(C, false, V, false, T1);
+  wg_mm<PP>(PZr, false, V, false, T2);
   __syncthreads();
-  // compact copies of C, PZ, PY into Tm-based scratch for the diagonal products
-  for (int e = threadIdx.x; e < p * p; e += blockDim.x) Cc[e] = C[(e / p) * PP + e % p];
+  col_dots<PP>(V, T1, terms.a, 1.0);
+  col_dots<PP>(V, T2, terms.g, 1.0);
+  wg_mm<PP>(PYr, false, V, false, Mc);
   __syncthreads();
-  vtav_diag(p, ld, V, Cc, tmp, terms.a);
-  for (int e = threadIdx.x; e < p * p; e += blockDim.x) Cc[e] = PZ[(e / p) * PP + e % p];
-  __syncthreads();
-  vtav_diag(p, ld, V, Cc, tmp, terms.g);
-  for (int e = threadIdx.x; e < p * p; e += blockDim.x) Cc[e] = PY[(e / p) * PP + e % p];
-  __syncthreads();
-  vtav_diag(p, ld, V, Cc, tmp, terms.z);
-  for (int i = threadIdx.x; i < p; i += blockDim.x) terms.z[i] = -terms.z[i];
+  col_dots<PP>(V, Mc, terms.z, -1.0);
   __syncthreads();
   if (threadIdx.x < 64) {
     int evals = 0;
-    const double mu = get_mu(terms, p, &evals);
+    const double mu = get_mu(terms, PP, p, &evals);
     if (threadIdx.x == 0) {
       smu = mu;
       sok = mu > 0.0 && isfinite(mu);
@@ -426,65 +488,48 @@ __global__ __launch_bounds__(WG) void k_linesearch(int PP, const double* __restr
     return;
   }
   const double mu = smu;
-  // M = V diag((1 + mu^2 b)^{-1/2}) V^T (Sec. 5.2, eq. Xnew_P). The rotations leave V
-  // orthogonal only to about (number of rotations) * eps, which would make X(mu) drift from
-  // orthonormality step after step; one Newton step for the inverse square root of
-  // B = I + mu^2 S, M <- M (3 I - M B M) / 2, restores M B M = I to second order.
-  double* Mc = A;  // compact M (A's eigenvalues are in terms.b already)
-  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
-    const int i = e / p, j = e % p;
-    double s = 0.0;
-    for (int k = 0; k < p; ++k) s += V[i * ld + k] * V[j * ld + k] / sqrt(1.0 + mu * mu * terms.b[k]);
-    Mc[e] = s;
-  }
+  // M = V diag((1 + mu^2 b)^{-1/2}) V^T (Sec. 5.2, eq. Xnew_P). V is orthogonal only to
+  // about (number of rotations) * eps, which would let X(mu) drift from orthonormality
+  // step after step; one Newton step for the inverse square root of B = I + mu^2 S,
+  // M <- M (3 I - M B M) / 2, restores M B M = I to second order.
+  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) T1[e] = V[e] / sqrt(1.0 + mu * mu * terms.b[e % PP]);
   __syncthreads();
-  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {  // Cc = B M
-    const int i = e / p, j = e % p;
-    double s = Mc[e];
-    for (int k = 0; k < p; ++k) s += mu * mu * S[i * PP + k] * Mc[k * p + j];
-    Cc[e] = s;
-  }
+  wg_mm<PP>(T1, false, V, true, Mc);  // Mc = V D V^T
   __syncthreads();
-  mm(p, p, Mc, Cc, tmp, false);  // tmp = M B M
+  wg_mm<PP>(S, false, Mc, false, T1);  // T1 = S M
   __syncthreads();
-  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
-    const int i = e / p, j = e % p;
-    Cc[e] = ((i == j) ? 3.0 : 0.0) - tmp[e];
-  }
+  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) T1[e] = Mc[e] + mu * mu * T1[e];  // B M
   __syncthreads();
-  mm(p, p, Mc, Cc, tmp, false);  // tmp = M (3 I - M B M)
+  wg_mm<PP>(Mc, false, T1, false, T2);  // M B M
+  __syncthreads();
+  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) T2[e] = ((e / PP) == (e % PP) ? 3.0 : 0.0) - T2[e];
+  __syncthreads();
+  wg_mm<PP>(Mc, false, T2, false, T1);  // M (3I - M B M)
   __syncthreads();
   double* M = small + S_M * PP * PP;
-  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
-    const int i = e / p, j = e % p;
-    Mc[e] = 0.25 * (tmp[i * p + j] + tmp[j * p + i]);  // symmetric part of tmp / 2
-  }
-  __syncthreads();
   for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) {
     const int i = e / PP, j = e % PP;
-    M[e] = (i < p && j < p) ? Mc[i * p + j] : 0.0;
+    const double v = 0.25 * (T1[i * PP + j] + T1[j * PP + i]);
+    Mc[e] = v;
+    M[e] = v;
   }
   __syncthreads();
   // next C = M (C - mu (P^T Y + Y^T P) + mu^2 P^T Z) M and next W = X_new^T P = -mu M S
   // (X^T P = 0 for the tangent direction; A X recursion of Sec. 6.1, eq. save_matvec)
-  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
-    const int i = e / p, j = e % p;
-    Cc[e] = C[i * PP + j] - mu * (PY[i * PP + j] + PY[j * PP + i]) + mu * mu * PZ[i * PP + j];
-  }
-  __syncthreads();
-  mm(p, ld, Mc, Cc, tmp, false);
-  __syncthreads();
-  mm(p, ld, tmp, Mc, Cc, false);
-  __syncthreads();
-  double* W = small + S_W * PP * PP;
   for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) {
     const int i = e / PP, j = e % PP;
-    if (i < p && j < p) {
-      C[e] = 0.5 * (Cc[i * p + j] + Cc[j * p + i]);
-      double s = 0.0;
-      for (int k = 0; k < p; ++k) s += Mc[i * p + k] * S[k * PP + j];
-      W[e] = -mu * s;
-    }
+    T2[e] = C[e] - mu * (PYr[e] + PYr[j * PP + i]) + 0.5 * mu * mu * (PZr[e] + PZr[j * PP + i]);
+  }
+  __syncthreads();
+  wg_mm<PP>(Mc, false, T2, false, T1);
+  __syncthreads();
+  wg_mm<PP>(T1, false, Mc, false, T2);
+  double* W = small + S_W * PP * PP;
+  wg_mm<PP>(Mc, false, S, false, W, -mu);
+  __syncthreads();
+  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) {
+    const int i = e / PP, j = e % PP;
+    C[e] = 0.5 * (T2[e] + T2[j * PP + i]);
   }
   if (threadIdx.x == 0) {
     const int k = sc->k;
@@ -576,57 +621,102 @@ __global__ __launch_bounds__(WG) void k_chol_inv(int PP, int p, const double* __
   if (threadIdx.x == 0 && bad) *flag = 1;
 }
 
+// After a Cholesky QR pass X <- X M (M = R^{-1} in small[S_M]): C <- M^T C M, W <- M^T W.
+// If the factorization was flagged as failed, M is reset to the identity instead.
+template <int PP>
+__global__ __launch_bounds__(WG) void k_transform_cw(double* __restrict__ small, int* __restrict__ flag) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  double* T1 = reinterpret_cast<double*>(lds_raw);
+  double* T2 = T1 + PP * PP;
+  double* M = small + S_M * PP * PP;
+  double* C = small + S_C * PP * PP;
+  double* W = small + S_W * PP * PP;
+  if (*flag) {
+    for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) M[e] = (e / PP) == (e % PP) ? 1.0 : 0.0;
+    __syncthreads();
+    if (threadIdx.x == 0) *flag = 0;
+    return;
+  }
+  wg_mm<PP>(C, false, M, false, T1);  // C M
+  wg_mm<PP>(M, true, W, false, T2);   // M^T W
+  __syncthreads();
+  wg_mm<PP>(M, true, T1, false, C);   // M^T C M
+  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) W[e] = T2[e];
+  __syncthreads();
+  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) {
+    const int i = e / PP, j = e % PP;
+    if (i < j) {
+      const double v = 0.5 * (C[i * PP + j] + C[j * PP + i]);
+      C[i * PP + j] = v;
+      C[j * PP + i] = v;
+    }
+  }
+}
+
 // Rayleigh-Ritz: eig of sym(red) (p x p): eigenvalues descending into vals[0..p),
 // eigenvectors as the columns of small[S_M] (stride PP, padding zero).
 __global__ __launch_bounds__(WG) void k_ritz(int PP, int p, const double* __restrict__ red, double* __restrict__ small,
                                              double* __restrict__ vals) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   double* A = reinterpret_cast<double*>(lds_raw);
-  double* V = A + MAXP * MAXP;
+  double* V = A + MAXP * (MAXP + 1);
   __shared__ double cs[2 * MAXP];
   __shared__ int uv[MAXP];
-  __shared__ int flag;
+  __shared__ int nrot, anyr;
   __shared__ int order[MAXP];
+  const int ld = p | 1;  // odd stride: no LDS bank conflicts in the column sweeps
   for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
     const int i = e / p, j = e % p;
-    A[e] = 0.5 * (red[i * PP + j] + red[j * PP + i]);
-    V[e] = (i == j) ? 1.0 : 0.0;
+    A[i * ld + j] = 0.5 * (red[i * PP + j] + red[j * PP + i]);
+    V[i * ld + j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  jacobi(p, p, A, V, cs, uv, &flag);
+  jacobi(p, ld, A, V, cs, uv, &nrot, &anyr);
   if (threadIdx.x == 0) {
     for (int i = 0; i < p; ++i) order[i] = i;
     for (int i = 1; i < p; ++i) {  // insertion sort, descending
       const int o = order[i];
-      const double v = A[o * p + o];
+      const double v = A[o * ld + o];
       int j = i - 1;
-      while (j >= 0 && A[order[j] * p + order[j]] < v) { order[j + 1] = order[j]; --j; }
+      while (j >= 0 && A[order[j] * ld + order[j]] < v) { order[j + 1] = order[j]; --j; }
       order[j + 1] = o;
     }
-    for (int i = 0; i < p; ++i) vals[i] = A[order[i] * p + order[i]];
+    for (int i = 0; i < p; ++i) vals[i] = A[order[i] * ld + order[i]];
   }
   __syncthreads();
   double* M = small + S_M * PP * PP;
   for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) {
     const int i = e / PP, j = e % PP;
-    M[e] = (i < p && j < p) ? V[i * p + order[j]] : 0.0;
+    M[e] = (i < p && j < p) ? V[i * ld + order[j]] : 0.0;
   }
 }
 
 // ---------------------------------------------------------------- launchers
 
-static constexpr int LS_LDS = 4 * MAXP * MAXP * (int)sizeof(double);
-static constexpr int RITZ_LDS = 2 * MAXP * MAXP * (int)sizeof(double);
+static constexpr int RITZ_LDS = 2 * MAXP * (MAXP + 1) * (int)sizeof(double);
+
+template <int PP>
+static hipError_t init_pp() {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_eig<PP>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 3 * PP * (PP + 1) * 8);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_linesearch<PP>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 4 * PP * PP * 8);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_transform_cw<PP>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 2 * PP * PP * 8);
+  return e;
+}
 
 hipError_t Small::init() {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_linesearch),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, LS_LDS);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ritz), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            RITZ_LDS);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_ritz), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     RITZ_LDS);
   if (e == hipSuccess)
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_chol_inv), hipFuncAttributeMaxDynamicSharedMemorySize,
                             RITZ_LDS);
+  if (e == hipSuccess) e = init_pp<16>();
+  if (e == hipSuccess) e = init_pp<32>();
+  if (e == hipSuccess) e = init_pp<64>();
   return e;
 }
 void Small::after_grad(hipStream_t st, int PP, const double* red, double* small, Scalars* sc, double* hist) {
@@ -635,9 +725,20 @@ void Small::after_grad(hipStream_t st, int PP, const double* red, double* small,
 void Small::after_dir(hipStream_t st, int PP, const double* red, double* small, Scalars* sc) {
   hipLaunchKernelGGL(k_after_dir, dim3(1), dim3(WG), 0, st, PP, red, small, sc);
 }
+void Small::eig(hipStream_t st, int PP, double* small, Scalars* sc) {
+  switch (PP) {
+    case 16: k_eig<16><<<1, WG, 3 * 16 * 17 * 8, st>>>(small, sc); break;
+    case 32: k_eig<32><<<1, WG, 3 * 32 * 33 * 8, st>>>(small, sc); break;
+    case 64: k_eig<64><<<1, WG, 3 * 64 * 65 * 8, st>>>(small, sc); break;
+  }
+}
 void Small::linesearch(hipStream_t st, int PP, const double* red, double* small, Scalars* sc, double* hist,
                        int recompute_ax) {
-  hipLaunchKernelGGL(k_linesearch, dim3(1), dim3(WG), LS_LDS, st, PP, red, small, sc, hist, recompute_ax);
+  switch (PP) {
+    case 16: k_linesearch<16><<<1, WG, 4 * 16 * 16 * 8, st>>>(red, small, sc, hist, recompute_ax); break;
+    case 32: k_linesearch<32><<<1, WG, 4 * 32 * 32 * 8, st>>>(red, small, sc, hist, recompute_ax); break;
+    case 64: k_linesearch<64><<<1, WG, 4 * 64 * 64 * 8, st>>>(red, small, sc, hist, recompute_ax); break;
+  }
 }
 void Small::after_update_grams(hipStream_t st, int PP, const double* red, double* small, Scalars* sc) {
   hipLaunchKernelGGL(k_after_update_grams, dim3(1), dim3(WG), 0, st, PP, red, small, sc);
@@ -647,6 +748,13 @@ void Small::after_refresh(hipStream_t st, int PP, const double* red, double* sma
 }
 void Small::chol_inv(hipStream_t st, int PP, int p, const double* red, double* small, int* flag) {
   hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(WG), RITZ_LDS, st, PP, p, red, small, flag);
+}
+void Small::transform_cw(hipStream_t st, int PP, double* small, int* flag) {
+  switch (PP) {
+    case 16: k_transform_cw<16><<<1, WG, 2 * 16 * 16 * 8, st>>>(small, flag); break;
+    case 32: k_transform_cw<32><<<1, WG, 2 * 32 * 32 * 8, st>>>(small, flag); break;
+    case 64: k_transform_cw<64><<<1, WG, 2 * 64 * 64 * 8, st>>>(small, flag); break;
+  }
 }
 void Small::ritz(hipStream_t st, int PP, int p, const double* red, double* small, double* out_vals) {
   hipLaunchKernelGGL(k_ritz, dim3(1), dim3(WG), RITZ_LDS, st, PP, p, red, small, out_vals);

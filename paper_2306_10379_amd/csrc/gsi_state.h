@@ -29,7 +29,13 @@ struct Scalars {
   int32_t max_iter, k_restart, method, p;
   int32_t n_restart, n_refresh, n_null, n_spmm;
   int32_t hist_len, hist_cap;
-  int32_t pad_[2];
+  int32_t v_valid;      // small[S_V] holds the previous eigenvectors of P^T P (warm start)
+  int32_t sweeps;       // Jacobi sweeps of the last eigendecomposition
+  int32_t n_sweeps;     // Jacobi sweeps, summed over the solve
+  int32_t stall_window; // > 0: stop (done = 4) when rho has not halved for this many iterations
+  double rho_best;      // smallest rho so far (halving checkpoints)
+  int32_t k_best;
+  int32_t pad_;
 };
 
 // Offsets (in doubles) of the p x p matrices (stored PP x PP, row-major) in the small buffer.
@@ -45,6 +51,7 @@ enum {
   S_M,       // retraction factor V diag((1 + mu^2 b)^-1/2) V^T
   S_T1,      // temporaries
   S_T2,
+  S_VEC,     // vectors of length PP: b (eigenvalues of P^T P), then scratch
   S_COUNT
 };
 

@@ -24,7 +24,7 @@ EXPORTS = [
     "gsi_set_x0", "gsi_spmm", "gsi_history", "gsi_counters", "gsi_pass_times", "gsi_destroy",
     "gsi_status_str", "gsi_last_error",
 ]
-PASSES = ["grad", "dir", "spmm", "update", "reduce", "small", "linesearch", "refresh"]
+PASSES = ["grad", "dir", "spmm", "update", "reduce", "small", "linesearch", "refresh", "eig", "gram"]
 
 
 class GsiCsr(ctypes.Structure):
@@ -70,7 +70,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gsi_spmm.restype = ctypes.c_int
     L.gsi_history.argtypes = [vp, P(i32), P(dbl), P(dbl), P(dbl), P(dbl), P(dbl)]
     L.gsi_history.restype = ctypes.c_int
-    L.gsi_counters.argtypes = [vp, P(i32), P(i32), P(i32), P(i32), P(i32), P(i32)]
+    L.gsi_counters.argtypes = [vp, P(i32), P(i32), P(i32), P(i32), P(i32), P(i32), P(i32)]
     L.gsi_counters.restype = ctypes.c_int
     L.gsi_pass_times.argtypes = [vp, i32, P(dbl), P(i32)]
     L.gsi_pass_times.restype = ctypes.c_int
@@ -170,9 +170,9 @@ def gsi_history(h, capacity: int):
 
 
 def gsi_counters(h):
-    vals = [ctypes.c_int32() for _ in range(6)]
+    vals = [ctypes.c_int32() for _ in range(7)]
     _check(h, load().gsi_counters(h, *[ctypes.byref(v) for v in vals]))
-    keys = ["iters", "spmm", "restarts", "refreshes", "null_steps", "low_iters"]
+    keys = ["iters", "spmm", "restarts", "refreshes", "null_steps", "low_iters", "eig_sweeps"]
     return {k: v.value for k, v in zip(keys, vals)}
 
 
