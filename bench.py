@@ -40,6 +40,24 @@ def pass_bytes(n, p, nnz, s):
     }
 
 
+def measured_traffic(kernel_tag, json_name):
+    """HBM bytes per launch of a kernel from the rocprofv3 FETCH_SIZE / WRITE_SIZE summary in
+    profiles/ (scaled by the copy calibration), or None when that summary was taken on kernel
+    sources other than the current ones."""
+    path = os.path.join(ROOT, "profiles", json_name)
+    if not os.path.exists(path):
+        return None
+    from paper_2306_10379_amd import profsum
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != profsum.source_hash():
+        return None
+    for k, v in rec["kernels"].items():
+        if k.startswith(kernel_tag):
+            return v["bytes"]
+    return None
+
+
 def cpu_baseline(A, X0, p, tol, gpu_iters, iters=3):
     """The FP64 oracle on a bounded sample: `iters` RCG iterations of the same problem on
     the host cores, scaled to seconds per solve with the GPU's iteration count."""
@@ -76,6 +94,9 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--switch-tol", type=float, default=1e-6)
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="short run for hardware-counter profiling: K float64 iterations without the graph, "
+                         "then a plain 1 GiB device copy (three times) as the counter calibration; no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -94,7 +115,20 @@ def main():
     vals = torch.as_tensor(A.vals, device=dev)
     X0 = torch.as_tensor(X0h, device=dev)
     torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
+
+    if args.profile_steps > 0:
+        s = gsi.Solver((rowptr, colind, vals, A.n), X0, p, tol=0.0, max_iter=args.profile_steps + 5,
+                       use_graph=False)
+        s.step(args.profile_steps)
+        torch.cuda.synchronize()
+        s.close()
+        x = torch.ones(2 ** 27, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log(f"profile run done: {args.profile_steps} iterations, 3 copies of 1 GiB")
+        return
 
     def timed_solves(precision, steps, warmup):
         s = gsi.Solver((rowptr, colind, vals, A.n), X0, p, tol=args.tol, max_iter=20000,
@@ -132,8 +166,10 @@ def main():
     total_ms = sum(v[0] for v in pt.values())
     dom = max(kern, key=lambda k: pt[k][0])
     log("pass times (ms, launches): " + json.dumps(pt))
+    traffic = measured_traffic(f"gsi::k_{dom}<double, {((p + 15) // 16) * 16}",
+                               f"traffic_laplace3d_{N}_p{p}_fp64.json")
     roof = {"bound": "hbm", "achieved": round(kern[dom]["GBps"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(kern[dom]["GBps"] / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+            "frac": round(kern[dom]["GBps"] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
             "bytes_per_launch": nb[dom], "avg_us": round(kern[dom]["avg_us"], 2)}
     spmm_gbs = kern["spmm"]["GBps"]
     s64.close()
