@@ -154,6 +154,34 @@ void gsi_destroy(gsi_handle h);
 const char* gsi_status_str(gsi_status s);
 const char* gsi_last_error(gsi_handle h);
 
+/* ------------------------------------------------------------------------------------------
+ * Batched solve: count independent problems (A[i], p[i], X0[i]) of different sizes solved by
+ * one persistent kernel launch, captured in a HIP graph. Each workgroup takes problems from
+ * an atomic queue (largest n*p first) and runs the whole iteration of one problem with
+ * workgroup barriers only. Options shared by all problems: which, method, precision
+ * (GSI_MIXED_FP32: float32 blocks with float64 p x p solves, stopping at tol or when rho
+ * stops halving for 200 iterations; GSI_FP64: float64 blocks), recompute_ax, k_restart,
+ * max_iter, tol. 1 <= p[i] <= 32, p[i] < n. Arrays A, p, X0 are host arrays of count
+ * entries; the CSR arrays and X0[i] (n x p float64, row-major) are device pointers owned
+ * by the caller and copied. */
+typedef struct gsi_batch* gsi_batch_handle;
+gsi_status gsi_create_batched(gsi_batch_handle* h, int32_t count, const gsi_csr* A, const int32_t* p,
+                              const gsi_options* opt, const double* const* X0, void* hip_stream);
+/* Runs the persistent launch. iters / status: host arrays of count (nullable); status per
+ * problem: 1 converged (rho <= tol), 2 max_iter, 3 breakdown, 4 stopped at the precision
+ * floor (float32 blocks). Returns GSI_BREAKDOWN if any problem broke down, else
+ * GSI_NOT_CONVERGED if any reached max_iter, else GSI_OK. Syncs. Calling it again solves
+ * again from the iterates left by the previous call. */
+gsi_status gsi_solve_batched(gsi_batch_handle h, int32_t* iters, int32_t* status);
+/* Ritz values of problem i (host array of p[i], of A: largest first for which = +1, of -A
+ * for which = -1, i.e. the negated smallest eigenvalues of A, largest first), its final rho
+ * and restart count (any output nullable). Syncs. */
+gsi_status gsi_batched_results(gsi_batch_handle h, int32_t i, double* ritz, double* rho, int32_t* restarts);
+/* Copy the basis of problem i (n x p float64 row-major) to the device pointer X_out. Syncs. */
+gsi_status gsi_batched_get_x(gsi_batch_handle h, int32_t i, double* X_out);
+const char* gsi_batched_last_error(gsi_batch_handle h);
+void gsi_destroy_batched(gsi_batch_handle h);
+
 #ifdef __cplusplus
 }
 #endif

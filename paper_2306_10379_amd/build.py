@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgsi.so")
-SOURCES = ["gsi_kernels.hip", "gsi_small.hip", "gsi_host.hip"]
+SOURCES = ["gsi_kernels.hip", "gsi_small.hip", "gsi_host.hip", "gsi_batched.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # keep the compiler from forming packed FP32 instructions (see the build notes)
@@ -17,7 +17,7 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, jobs: int = 3) -> str:
+def build(verbose: bool = False, jobs: int = 4) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objs = []
     procs = []

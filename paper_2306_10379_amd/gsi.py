@@ -22,7 +22,8 @@ GSI_FP64, GSI_MIXED_FP32 = 0, 1
 EXPORTS = [
     "gsi_options_default", "gsi_create", "gsi_step", "gsi_solve", "gsi_residuals", "gsi_get_x",
     "gsi_set_x0", "gsi_spmm", "gsi_history", "gsi_counters", "gsi_pass_times", "gsi_destroy",
-    "gsi_status_str", "gsi_last_error",
+    "gsi_status_str", "gsi_last_error", "gsi_create_batched", "gsi_solve_batched", "gsi_batched_results",
+    "gsi_batched_get_x", "gsi_batched_last_error", "gsi_destroy_batched",
 ]
 PASSES = ["grad", "dir", "spmm", "update", "reduce", "small", "linesearch", "refresh", "eig", "gram"]
 
@@ -80,6 +81,18 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gsi_status_str.restype = ctypes.c_char_p
     L.gsi_last_error.argtypes = [vp]
     L.gsi_last_error.restype = ctypes.c_char_p
+    L.gsi_create_batched.argtypes = [P(vp), i32, P(GsiCsr), P(i32), P(GsiOptions), P(vp), vp]
+    L.gsi_create_batched.restype = ctypes.c_int
+    L.gsi_solve_batched.argtypes = [vp, P(i32), P(i32)]
+    L.gsi_solve_batched.restype = ctypes.c_int
+    L.gsi_batched_results.argtypes = [vp, i32, P(dbl), P(dbl), P(i32)]
+    L.gsi_batched_results.restype = ctypes.c_int
+    L.gsi_batched_get_x.argtypes = [vp, i32, vp]
+    L.gsi_batched_get_x.restype = ctypes.c_int
+    L.gsi_batched_last_error.argtypes = [vp]
+    L.gsi_batched_last_error.restype = ctypes.c_char_p
+    L.gsi_destroy_batched.argtypes = [vp]
+    L.gsi_destroy_batched.restype = None
     _lib = L
     return L
 
@@ -268,6 +281,117 @@ class Solver:
 
     def close(self):
         gsi_destroy(self.h)
+        self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) is not None:
+                self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------------- batched
+
+
+def _bcheck(h, s, allowed=(GSI_OK,)):
+    if s not in allowed:
+        raise GsiError(s, load().gsi_batched_last_error(h).decode())
+    return s
+
+
+def gsi_create_batched(mats, ps, X0s, opt: GsiOptions, stream=None):
+    """mats: list of (rowptr int32, colind int32, vals float64, n) device tensors; ps: list of
+    block sizes; X0s: list of n x p float64 device tensors."""
+    import torch
+    L = load()
+    count = len(mats)
+    csrs = (GsiCsr * count)()
+    for i, (rp, ci, vv, n) in enumerate(mats):
+        csrs[i] = GsiCsr(n=int(n), nnz=int(ci.numel()), rowptr=_dptr(rp), colind=_dptr(ci), vals=_dptr(vv))
+    parr = (ctypes.c_int32 * count)(*[int(x) for x in ps])
+    xarr = (ctypes.c_void_p * count)(*[_dptr(x) for x in X0s])
+    h = ctypes.c_void_p()
+    st = ctypes.c_void_p(stream if stream is not None else torch.cuda.current_stream().cuda_stream)
+    s = L.gsi_create_batched(ctypes.byref(h), count, csrs, parr, ctypes.byref(opt), xarr, st)
+    if s != GSI_OK:
+        msg = L.gsi_batched_last_error(h).decode() if h.value else L.gsi_status_str(s).decode()
+        if h.value:
+            L.gsi_destroy_batched(h)
+        raise GsiError(s, msg)
+    return h
+
+
+def gsi_solve_batched(h, count: int):
+    iters = (ctypes.c_int32 * count)()
+    status = (ctypes.c_int32 * count)()
+    s = _bcheck(h, load().gsi_solve_batched(h, iters, status), (GSI_OK, GSI_NOT_CONVERGED, GSI_BREAKDOWN))
+    return s, np.array(iters[:]), np.array(status[:])
+
+
+def gsi_batched_results(h, i: int, p: int):
+    ritz = (ctypes.c_double * p)()
+    rho = ctypes.c_double()
+    rs = ctypes.c_int32()
+    _bcheck(h, load().gsi_batched_results(h, int(i), ritz, ctypes.byref(rho), ctypes.byref(rs)))
+    return np.array(ritz[:]), rho.value, rs.value
+
+
+def gsi_batched_get_x(h, i: int, out):
+    return _bcheck(h, load().gsi_batched_get_x(h, int(i), ctypes.c_void_p(_dptr(out))))
+
+
+def gsi_destroy_batched(h):
+    if h is not None and h.value:
+        load().gsi_destroy_batched(h)
+
+
+class BatchedSolver:
+    """Owns a batched handle. mats: list of inputs.CSR (copied to the device); X0s: list of
+    n x p arrays; ps: list of block sizes."""
+
+    def __init__(self, mats, X0s, ps, device="cuda", **opts):
+        import torch
+        self._keep = []
+        dev_mats = []
+        for A in mats:
+            rp = torch.as_tensor(np.asarray(A.rowptr, dtype=np.int32), device=device)
+            ci = torch.as_tensor(np.asarray(A.colind, dtype=np.int32), device=device)
+            vv = torch.as_tensor(np.asarray(A.vals, dtype=np.float64), device=device)
+            dev_mats.append((rp, ci, vv, A.n))
+        xs = [torch.as_tensor(np.ascontiguousarray(X, dtype=np.float64), device=device) for X in X0s]
+        self._keep = [dev_mats, xs]
+        self.ns = [A.n for A in mats]
+        self.ps = [int(x) for x in ps]
+        precision = opts.pop("precision", "fp32")
+        opts["precision"] = {"fp64": GSI_FP64, "fp32": GSI_MIXED_FP32, "mixed": GSI_MIXED_FP32}[precision] \
+            if isinstance(precision, str) else precision
+        method = opts.pop("method", "rcg")
+        opts["method"] = {"rsd": GSI_RSD, "rcg": GSI_RCG}[method] if isinstance(method, str) else method
+        self.opt = options(**opts)
+        self.device = device
+        self.h = gsi_create_batched(dev_mats, self.ps, xs, self.opt)
+
+    def solve(self):
+        return gsi_solve_batched(self.h, len(self.ps))
+
+    def results(self, i):
+        return gsi_batched_results(self.h, i, self.ps[i])
+
+    def get_x(self, i):
+        import torch
+        out = torch.empty((self.ns[i], self.ps[i]), dtype=torch.float64, device=self.device)
+        gsi_batched_get_x(self.h, i, out)
+        return out
+
+    def close(self):
+        gsi_destroy_batched(self.h)
         self.h = None
 
     def __enter__(self):

@@ -22,7 +22,7 @@ import sqlite3
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ["csrc/gsi_kernels.hip", "csrc/gsi_device.h", "csrc/gsi_small.hip"]
+KERNEL_SOURCES = ["csrc/gsi_kernels.hip", "csrc/gsi_device.h", "csrc/gsi_small.hip", "csrc/gsi_small_dev.h"]
 
 
 def source_hash() -> str:

@@ -117,3 +117,48 @@ def test_mixed_precision_reaches_fp64_accuracy():
     nA = 8.0
     bound = (r.rho + ref.rho[-1]) * np.sqrt(8) * nA / delta
     assert O.principal_angles(X, ref.X).max() <= bound
+
+
+def _schrodinger_batch(count, seed, nmin=8, nmax=24, pmin=2, pmax=12):
+    g = I.rng(seed)
+    mats, X0s, ps = [], [], []
+    for i in range(count):
+        N = int(g.integers(nmin, nmax + 1))
+        p = int(g.integers(pmin, pmax + 1))
+        A = I.schrodinger_2d(N, I.random_wells(seed * 1000 + i))
+        mats.append(A)
+        ps.append(p)
+        X0s.append(I.start_block(A.n, p, seed * 1000 + 500 + i))
+    return mats, X0s, ps
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_matches_single_problem_oracle(precision):
+    gsi = _gsi()
+    mats, X0s, ps = _schrodinger_batch(12, 5)
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    print(f"batched {precision}: ns={[A.n for A in mats]} ps={ps}", flush=True)
+    with gsi.BatchedSolver(mats, X0s, ps, which=-1, precision=precision, tol=tol, max_iter=20000) as b:
+        st, iters, status = b.solve()
+        for i, (A, X0, p) in enumerate(zip(mats, X0s, ps)):
+            ritz, rho, _ = b.results(i)
+            theta = -ritz  # the solver ran on -A: its largest Ritz values are -(smallest of A)
+            w = np.linalg.eigh(A.to_dense())[0][:p]
+            if precision == "fp64":
+                assert status[i] == 1, (i, status[i], rho)
+                ref = O.rcg(A, X0, tol=tol, which=-1, max_iter=20000)
+                assert np.max(np.abs(theta - ref.theta) / np.abs(ref.theta)) <= 1e-10
+                assert np.max(np.abs(theta - w) / np.abs(w)) <= 1e-10
+                X = b.get_x(i).cpu().numpy()
+                delta = np.linalg.eigh(A.to_dense())[0][p] - w[-1]
+                nA = O.norm_inf(A.to_scipy())
+                bound = (rho + ref.rho[-1]) * np.sqrt(p) * nA / delta
+                assert O.principal_angles(X, ref.X).max() <= max(bound, 1e-12)
+            else:
+                assert status[i] in (1, 4), (i, status[i], rho)
+                # float32 blocks: Ritz values to float32 accuracy of the eigenvalues of A
+                assert np.max(np.abs(theta - w)) <= 1e-4 * np.max(np.abs(w)) + 1e-3 * rho * nA_est(A)
+
+
+def nA_est(A):
+    return O.norm_inf(A.to_scipy())
