@@ -157,21 +157,27 @@ const char* gsi_last_error(gsi_handle h);
 /* ------------------------------------------------------------------------------------------
  * Batched solve: count independent problems (A[i], p[i], X0[i]) of different sizes solved by
  * one persistent kernel launch, captured in a HIP graph. Each workgroup takes problems from
- * an atomic queue (largest n*p first) and runs the whole iteration of one problem with
- * workgroup barriers only. Options shared by all problems: which, method, precision
- * (GSI_MIXED_FP32: float32 blocks with float64 p x p solves, stopping at tol or when rho
- * stops halving for 200 iterations; GSI_FP64: float64 blocks), recompute_ax, k_restart,
- * max_iter, tol. 1 <= p[i] <= 32, p[i] < n. Arrays A, p, X0 are host arrays of count
- * entries; the CSR arrays and X0[i] (n x p float64, row-major) are device pointers owned
- * by the caller and copied. */
+ * an atomic queue (largest n*p first) and runs the whole iteration of one problem (Sec. 5,
+ * Algorithm 4, with the same readings as gsi_solve) with workgroup barriers only. Options
+ * shared by all problems: which, method, precision, recompute_ax, k_restart, max_iter, tol,
+ * switch_tol. GSI_FP64: float64 blocks throughout. GSI_MIXED_FP32: float32 blocks with
+ * float64 p x p solves until rho <= max(switch_tol, tol) or until rho has not halved for 200
+ * iterations, then the iterate, previous gradient and previous direction are widened to
+ * float64 and the iteration continues to tol without a restart. 1 <= p[i] <= 32, p[i] < n.
+ * Arrays A, p, X0 are host arrays of count entries; the CSR arrays (float64 values) and
+ * X0[i] (n x p float64, row-major) are device pointers owned by the caller and copied.
+ * Errors: GSI_EINVAL (bad sizes, invalid CSR, non-finite values, problem index reported by
+ * gsi_batched_last_error), GSI_ENOMEM, GSI_EDEVICE. The handle is returned even on failure
+ * (for the message) and must be destroyed. */
 typedef struct gsi_batch* gsi_batch_handle;
 gsi_status gsi_create_batched(gsi_batch_handle* h, int32_t count, const gsi_csr* A, const int32_t* p,
                               const gsi_options* opt, const double* const* X0, void* hip_stream);
-/* Runs the persistent launch. iters / status: host arrays of count (nullable); status per
- * problem: 1 converged (rho <= tol), 2 max_iter, 3 breakdown, 4 stopped at the precision
- * floor (float32 blocks). Returns GSI_BREAKDOWN if any problem broke down, else
- * GSI_NOT_CONVERGED if any reached max_iter, else GSI_OK. Syncs. Calling it again solves
- * again from the iterates left by the previous call. */
+/* Runs the persistent launch; every call solves from the X0 given at creation. iters /
+ * status: host arrays of count (nullable); iters counts all iterations of both phases;
+ * status per problem: 1 converged (rho <= tol), 2 max_iter, 3 breakdown. Returns
+ * GSI_BREAKDOWN if any problem broke down, else GSI_NOT_CONVERGED if any reached max_iter,
+ * else GSI_OK; GSI_EDEVICE if a team barrier waited longer than 30 s (the launch is then
+ * abandoned by every workgroup; status 5). Syncs. */
 gsi_status gsi_solve_batched(gsi_batch_handle h, int32_t* iters, int32_t* status);
 /* Ritz values of problem i (host array of p[i], of A: largest first for which = +1, of -A
  * for which = -1, i.e. the negated smallest eigenvalues of A, largest first), its final rho
@@ -179,6 +185,25 @@ gsi_status gsi_solve_batched(gsi_batch_handle h, int32_t* iters, int32_t* status
 gsi_status gsi_batched_results(gsi_batch_handle h, int32_t i, double* ritz, double* rho, int32_t* restarts);
 /* Copy the basis of problem i (n x p float64 row-major) to the device pointer X_out. Syncs. */
 gsi_status gsi_batched_get_x(gsi_batch_handle h, int32_t i, double* X_out);
+/* Per-problem timeline of the last solve, read from the device wall clock, in microseconds
+ * from the earliest start: start, switch to float64 (= start without a float32 phase) and
+ * end; iters_low: iterations of the float32 phase; team: workgroups that worked on the
+ * problem at the end (1 unless idle workgroups were recruited, see below). Host arrays of
+ * count, each nullable. Syncs.
+ *
+ * Teams: once every problem has started, a problem of at least 32 row tiles of 64 rows
+ * that is still running recruits idle workgroups every 32 iterations, up to 4 at a time
+ * and up to 16 in all with at least 16 tiles each. The members split the tiles, add their partial
+ * Grams and sums in member order and repeat the p x p work, so all hold the same state.
+ * Float64 results of a problem that stayed with one workgroup repeat bit for bit; with a
+ * team they depend on the team size, which depends on timing, and agree to rounding. */
+gsi_status gsi_batched_timeline(gsi_batch_handle h, double* begin_us, double* switch_us, double* end_us,
+                                int32_t* iters_low, int32_t* team);
+/* Per-problem time per pass of the last solve in microseconds: host array of count x
+ * GSI_NPASS, entry [i * GSI_NPASS + GSI_PASS_*] (GSI_PASS_REFRESH also holds the Cholesky
+ * QR of the start block and the first A X, GSI_PASS_SMALL the p x p work outside the
+ * eigendecomposition and line search). Syncs. */
+gsi_status gsi_batched_pass_times(gsi_batch_handle h, double* us);
 const char* gsi_batched_last_error(gsi_batch_handle h);
 void gsi_destroy_batched(gsi_batch_handle h);
 

@@ -21,6 +21,8 @@ constexpr int TR = 64;       // rows per workgroup tile (4 waves x 16 rows)
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef float f2 __attribute__((ext_vector_type(2)));
 
 template <typename T> struct Vec4;
 template <> struct Vec4<double> { typedef d4 type; };
@@ -46,6 +48,24 @@ template <typename T> struct AL {
   __device__ __forceinline__ static int kappa(int s, int g) { return 4 * E * (s / E) + E * g + (s % E); }
 };
 
+// Global-memory accesses through pointers the compiler cannot trace to a kernel argument
+// (loaded from memory, or parameters of out-of-line functions) compile to flat_*
+// instructions, which count on the LDS counter too, so that every wait for an LDS read
+// drains all loads in flight. gld / gst access through a global-address-space pointer
+// (global_* instructions); to_lds does the same for LDS pointers.
+template <typename T>
+__device__ __forceinline__ T gld(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ void gst(T* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+template <typename T>
+__device__ __forceinline__ T* to_lds(T* p) {
+  return (T*)((__attribute__((address_space(3))) T*)p);
+}
+
 // ---------------------------------------------------------------- tile I/O (per wave)
 
 template <typename T, int PP>
@@ -65,7 +85,7 @@ __device__ __forceinline__ void load_rl(const T* __restrict__ B, int64_t row0, i
     const bool ok = row < n;
     const T* p = B + (ok ? row : 0) * PP + c;
 #pragma unroll
-    for (int cb = 0; cb < PP / 16; ++cb) v[cb][r] = ok ? p[16 * cb] : T(0);
+    for (int cb = 0; cb < PP / 16; ++cb) v[cb][r] = ok ? gld(p + 16 * cb) : T(0);
   }
 }
 
@@ -78,7 +98,7 @@ __device__ __forceinline__ void store_rl(T* __restrict__ B, int64_t row0, int64_
     if (row < n) {
       T* p = B + row * PP + c;
 #pragma unroll
-      for (int cb = 0; cb < PP / 16; ++cb) p[16 * cb] = v[cb][r];
+      for (int cb = 0; cb < PP / 16; ++cb) gst(p + 16 * cb, v[cb][r]);
     }
   }
 }
@@ -94,11 +114,11 @@ __device__ __forceinline__ void load_al(const T* __restrict__ B, int64_t row0, i
 #pragma unroll
   for (int t = 0; t < PP / (4 * E); ++t) {
     if constexpr (E == 2) {
-      double2 q = ok ? *reinterpret_cast<const double2*>(p + 4 * E * t) : make_double2(0.0, 0.0);
+      const d2 q = ok ? gld(reinterpret_cast<const d2*>(p + 4 * E * t)) : d2{0.0, 0.0};
       a[E * t + 0] = q.x;
       a[E * t + 1] = q.y;
     } else {
-      float4 q = ok ? *reinterpret_cast<const float4*>(p + 4 * E * t) : make_float4(0.f, 0.f, 0.f, 0.f);
+      const f4 q = ok ? gld(reinterpret_cast<const f4*>(p + 4 * E * t)) : f4{0.f, 0.f, 0.f, 0.f};
       a[E * t + 0] = q.x;
       a[E * t + 1] = q.y;
       a[E * t + 2] = q.z;

@@ -23,7 +23,7 @@ EXPORTS = [
     "gsi_options_default", "gsi_create", "gsi_step", "gsi_solve", "gsi_residuals", "gsi_get_x",
     "gsi_set_x0", "gsi_spmm", "gsi_history", "gsi_counters", "gsi_pass_times", "gsi_destroy",
     "gsi_status_str", "gsi_last_error", "gsi_create_batched", "gsi_solve_batched", "gsi_batched_results",
-    "gsi_batched_get_x", "gsi_batched_last_error", "gsi_destroy_batched",
+    "gsi_batched_get_x", "gsi_batched_timeline", "gsi_batched_pass_times", "gsi_batched_last_error", "gsi_destroy_batched",
 ]
 PASSES = ["grad", "dir", "spmm", "update", "reduce", "small", "linesearch", "refresh", "eig", "gram"]
 
@@ -89,6 +89,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gsi_batched_results.restype = ctypes.c_int
     L.gsi_batched_get_x.argtypes = [vp, i32, vp]
     L.gsi_batched_get_x.restype = ctypes.c_int
+    L.gsi_batched_timeline.argtypes = [vp, P(dbl), P(dbl), P(dbl), P(i32), P(i32)]
+    L.gsi_batched_timeline.restype = ctypes.c_int
+    L.gsi_batched_pass_times.argtypes = [vp, P(dbl)]
+    L.gsi_batched_pass_times.restype = ctypes.c_int
     L.gsi_batched_last_error.argtypes = [vp]
     L.gsi_batched_last_error.restype = ctypes.c_char_p
     L.gsi_destroy_batched.argtypes = [vp]
@@ -347,6 +351,24 @@ def gsi_batched_get_x(h, i: int, out):
     return _bcheck(h, load().gsi_batched_get_x(h, int(i), ctypes.c_void_p(_dptr(out))))
 
 
+def gsi_batched_timeline(h, count: int):
+    """Per-problem (begin_us, switch_us, end_us, iters_low, team) of the last solve."""
+    b = (ctypes.c_double * count)()
+    w = (ctypes.c_double * count)()
+    e = (ctypes.c_double * count)()
+    lo = (ctypes.c_int32 * count)()
+    tm = (ctypes.c_int32 * count)()
+    _bcheck(h, load().gsi_batched_timeline(h, b, w, e, lo, tm))
+    return np.array(b[:]), np.array(w[:]), np.array(e[:]), np.array(lo[:]), np.array(tm[:])
+
+
+def gsi_batched_pass_times(h, count: int):
+    """count x len(PASSES) microseconds per pass of the last solve."""
+    us = (ctypes.c_double * (count * len(PASSES)))()
+    _bcheck(h, load().gsi_batched_pass_times(h, us))
+    return np.array(us[:]).reshape(count, len(PASSES))
+
+
 def gsi_destroy_batched(h):
     if h is not None and h.value:
         load().gsi_destroy_batched(h)
@@ -383,6 +405,12 @@ class BatchedSolver:
 
     def results(self, i):
         return gsi_batched_results(self.h, i, self.ps[i])
+
+    def timeline(self):
+        return gsi_batched_timeline(self.h, len(self.ps))
+
+    def pass_times(self):
+        return gsi_batched_pass_times(self.h, len(self.ps))
 
     def get_x(self, i):
         import torch
