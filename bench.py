@@ -81,6 +81,54 @@ def cpu_baseline(A, X0, p, tol, gpu_iters, iters=3):
                       f"extrapolated to the GPU's {gpu_iters} iterations"}
 
 
+def batched_leg(args, gsi, inputs, torch):
+    """Many small problems in one persistent launch: the whole batch to rho <= tol with float32
+    blocks then float64 refinement, and with float64 blocks, against the plain float64 path
+    solving problems one by one (a stratified sample, scaled to the batch)."""
+    count = args.batch
+    log(f"building the Schroedinger batch ({count} problems)")
+    mats, X0s, ps = inputs.schrodinger_batch(count, seed=2024)
+    res = {"workload": f"{count} 2D Schroedinger operators -Laplacian + V (grid side U{{32..160}}, 1-6 Gaussian "
+                       f"wells), p U{{4..32}} smallest, rho <= {args.tol:g}, one persistent launch in a HIP graph",
+           "problems": count, "sum_n": int(sum(A.n for A in mats)),
+           "sum_np": int(sum(A.n * p for A, p in zip(mats, ps)))}
+    for prec in ("mixed", "fp64"):
+        with gsi.BatchedSolver(mats, X0s, ps, which=-1, precision=prec, tol=args.tol, max_iter=30000,
+                               switch_tol=1e-5) as b:
+            times = []
+            for i in range(2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, iters, status = b.solve()
+                dt = time.perf_counter() - t0
+                log(f"batched {prec} solve {i}: {dt:.3f} s, iterations {int(iters.sum())}, max {int(iters.max())}")
+                times.append(dt)
+            *_, team = b.timeline()
+            res[prec] = {"s": round(min(times), 3), "iters_total": int(iters.sum()), "iters_max": int(iters.max()),
+                         "converged": int((status == 1).sum()), "largest_team": int(team.max()),
+                         "problems_with_team": int((team > 1).sum())}
+    # plain float64 path, problems one by one: every (count / sample)-th problem
+    step = max(1, count // max(1, args.plain_sample))
+    sample = list(range(0, count, step))
+    tot, its = 0.0, 0
+    for j in sample:
+        s = gsi.Solver(mats[j], X0s[j], ps[j], which=-1, precision="fp64", tol=args.tol, max_iter=30000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, it = s.solve()
+        torch.cuda.synchronize()
+        tot += time.perf_counter() - t0
+        its += it
+        s.close()
+    est = tot * count / len(sample)
+    log(f"plain float64, one by one: {len(sample)} problems {tot:.2f} s ({its} iterations) -> {est:.1f} s for {count}")
+    res["plain_fp64_one_by_one_s"] = round(est, 2)
+    res["plain_sample"] = f"every {step}th problem ({len(sample)} of {count}) solved alone, time scaled by {count / len(sample):g}"
+    res["speedup_mixed_vs_plain"] = round(est / res["mixed"]["s"], 2)
+    res["speedup_fp64_vs_plain"] = round(est / res["fp64"]["s"], 2)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +142,10 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--switch-tol", type=float, default=1e-6)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch", type=int, default=512)
+    ap.add_argument("--plain-sample", type=int, default=32,
+                    help="problems of the batch solved one by one on the plain float64 path")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="short run for hardware-counter profiling: K float64 iterations without the graph, "
                          "then a plain 1 GiB device copy (three times) as the counter calibration; no JSON")
@@ -184,6 +236,8 @@ def main():
                  "ritz_rel_err_vs_fp64": float(np.max(np.abs(ritz32 - ritz64) / np.abs(ritz64))),
                  "rho": rho32}
 
+    batched = None if args.no_batched else batched_leg(args, gsi, inputs, torch)
+
     cpu = None
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample")
@@ -216,6 +270,7 @@ def main():
                     for k, v in kern.items()},
         "pass_share": {k: round(v[0] / total_ms, 4) for k, v in pt.items() if total_ms > 0},
         "mixed_fp32": mixed,
+        "batched": batched,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

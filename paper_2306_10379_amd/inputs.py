@@ -158,6 +158,24 @@ def schrodinger_2d(N: int, wells: Wells | None) -> CSR:
     return A
 
 
+def schrodinger_batch(count: int = 512, seed: int = 2024, sides: tuple[int, int] = (32, 160),
+                      blocks: tuple[int, int] = (4, 32), wells: tuple[int, int] = (1, 6)):
+    """A batch of 2D Schroedinger operators H = -Laplacian + V of uneven sizes: grid side N
+    uniform in `sides`, block size p uniform in `blocks`, V a sum of `wells` Gaussian wells
+    (depth U(-20, 0), width U(0.02, 0.2), centre U([0,1]^2)); each with its own N(0,1)
+    start block. Returns (mats, X0s, ps)."""
+    g = rng(seed)
+    mats, X0s, ps = [], [], []
+    for i in range(count):
+        N = int(g.integers(sides[0], sides[1] + 1))
+        p = int(g.integers(blocks[0], blocks[1] + 1))
+        A = schrodinger_2d(N, random_wells(seed * 10_000 + i, count=wells))
+        mats.append(A)
+        ps.append(p)
+        X0s.append(start_block(A.n, p, seed * 10_000 + 5_000 + i))
+    return mats, X0s, ps
+
+
 def spiked_sparse(n: int, half_degree: int, p: int, seed: int, gap: float = 1e-3,
                   spike_max: float = 3.0) -> CSR:
     """Sparse symmetric random matrix with uniform-random columns plus diagonal spikes.

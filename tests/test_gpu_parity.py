@@ -225,3 +225,39 @@ def test_batched_repeat_solves_from_x0():
 
 def nA_est(A):
     return O.norm_inf(A.to_scipy())
+
+
+def test_batched_full_schrodinger_batch():
+    """The whole 512-problem batch of the benchmark, mixed precision: every problem's basis
+    has orthonormal columns, an independently recomputed residual at the tolerance and Ritz
+    values equal to the eigenvalues of X^T A X; sampled problems (the two cheapest and one
+    solved by a team) match the oracle."""
+    gsi = _gsi()
+    mats, X0s, ps = I.schrodinger_batch(512, seed=2024)
+    tol = 1e-8
+    print("full batch: 512 problems, mixed", flush=True)
+    with gsi.BatchedSolver(mats, X0s, ps, which=-1, precision="mixed", tol=tol, max_iter=30000,
+                           switch_tol=1e-5) as b:
+        st, iters, status = b.solve()
+        *_, team = b.timeline()
+        assert np.all(status == 1)
+        print(f"iterations {iters.sum()}, teams {np.bincount(team)}", flush=True)
+        for i, (A, p) in enumerate(zip(mats, ps)):
+            S = A.to_scipy()
+            X = b.get_x(i).cpu().numpy()
+            ritz, rho, _ = b.results(i)
+            AX = S @ X
+            Cx = X.T @ AX
+            R = AX - X @ (0.5 * (Cx + Cx.T))
+            nA = O.norm_inf(S)
+            assert np.linalg.norm(X.T @ X - np.eye(p)) <= 1e-12 * p
+            assert np.linalg.norm(R) / (np.sqrt(p) * nA) <= 1.05 * tol + 1e-14, i
+            assert np.allclose(np.sort(-ritz), np.linalg.eigvalsh(0.5 * (Cx + Cx.T)), rtol=1e-12, atol=1e-12 * nA)
+        cost = np.array([A.n * p for A, p in zip(mats, ps)]) * iters
+        teamed = [i for i in np.argsort(cost) if team[i] > 1]
+        for i in list(np.argsort(cost)[:2]) + teamed[:1]:
+            A, X0, p = mats[i], X0s[i], ps[i]
+            print(f"oracle sample {i}: n={A.n} p={p} iters={iters[i]} team={team[i]}", flush=True)
+            ref = O.rcg(A, X0, tol=tol, which=-1, max_iter=30000)
+            ritz, rho, _ = b.results(i)
+            assert np.max(np.abs(-ritz - ref.theta) / np.abs(ref.theta)) <= 1e-9
