@@ -7,13 +7,16 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "gsi.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(gsi_[a-z0-9_]+)\s*\(", text)))
+    names = set()
+    for header in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(header).read(), flags=re.S)
+        names |= set(re.findall(r"\b((?:gsi|fno)_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
@@ -29,7 +32,8 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(gsi.LIB_PATH)
     missing = [name for name in declared_functions() if not hasattr(lib, name)]
     assert not missing, missing
-    assert sorted(gsi.EXPORTS) == declared_functions()
+    from paper_2306_10379_amd import fno
+    assert sorted(gsi.EXPORTS + fno.EXPORTS) == declared_functions()
 
 
 def test_binding_fails_loudly_without_library(tmp_path):
@@ -41,3 +45,16 @@ def test_binding_fails_loudly_without_library(tmp_path):
             gsi.load(str(tmp_path / "missing.so"))
     finally:
         gsi._lib = saved
+
+
+def test_network_parameter_count_matches_reference():
+    """fno_param_count is host arithmetic (no device call): it must equal the reference's
+    count for the documented layout and reject invalid configurations."""
+    from oracle import fno_oracle as F
+    from paper_2306_10379_amd import fno
+    L = fno.load()
+    for cfg in [F.Config(), F.Config(N=16, m=6, w=5, L=2, p=4), F.Config(N=32, m=11, w=7, L=0, p=9)]:
+        c = fno.FnoConfig(cfg.N, cfg.m, cfg.w, cfg.L, cfg.p, 4)
+        assert L.fno_param_count(ctypes.byref(c)) == F.param_count(cfg)
+    for bad in [(20, 6, 5, 2, 4, 1), (16, 40, 5, 2, 4, 1), (16, 6, 33, 2, 4, 1), (16, 6, 5, 2, 0, 1)]:
+        assert L.fno_param_count(ctypes.byref(fno.FnoConfig(*bad))) == -1
