@@ -143,6 +143,11 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--switch-tol", type=float, default=1e-6)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--warm", action="store_true",
+                    help="also run the learned warm-start leg (256 x 256 Schroedinger operators, 8 wells, p = 32: "
+                         "training data from the method's own solves, training, held-out comparison; ~8 minutes)")
+    ap.add_argument("--warm-train", type=int, default=144)
+    ap.add_argument("--warm-test", type=int, default=24)
     ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--plain-sample", type=int, default=32,
                     help="problems of the batch solved one by one on the plain float64 path")
@@ -237,6 +242,12 @@ def main():
                  "rho": rho32}
 
     batched = None if args.no_batched else batched_leg(args, gsi, inputs, torch)
+    warm = None
+    if args.warm:
+        from paper_2306_10379_amd import warmstart
+        warm = warmstart.run_experiment(N=256, p=32, ntrain=args.warm_train, ntest=args.warm_test, epochs=30, batch=16,
+                                        lr=3e-3, tol=args.tol, nsingle=3, chunk=48, chunk_test=12,
+                                        compare_prior=False, warm_max_iter=20000, log=log)
 
     cpu = None
     if not args.no_cpu:
@@ -271,6 +282,7 @@ def main():
         "pass_share": {k: round(v[0] / total_ms, 4) for k, v in pt.items() if total_ms > 0},
         "mixed_fp32": mixed,
         "batched": batched,
+        "warm_start": warm,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

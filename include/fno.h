@@ -11,9 +11,13 @@
  * accumulation (the p x p loss algebra in float64):
  *   In  = [V / 20, x, y]                       x = (col + 1)/(N + 1), y = (row + 1)/(N + 1)
  *   U_0 = W_lift In + b_lift                   pointwise 3 -> w
- *   U_{l+1} = gelu(K_l(U_l) + W_l U_l + b_l)   l = 0 .. L-1, gelu(t) = t Phi(t)
- *   Y   = K_out(U_L) + W_out U_L + b_out       w -> p, no activation
+ *   U_{l+1} = gelu(K_l(U_l) + W_l U_l + b_l)   l = 0 .. L-1, gelu(t) = t Phi_n(t), Phi_n the normal CDF
+ *   Y   = Phi + K_out(U_L) + W_out U_L + b_out w -> p, no activation
  *   K(U)[o] = S^T (sum_c R[o][c] .* (S U[c] S^T)) S, S[k][i] = sqrt(2/(N+1)) sin(pi (k+1)(i+1)/(N+1)), k < m
+ *   Phi: fixed prior, column a = sqrt(n) times the a-th lowest Dirichlet mode of the grid
+ *   Laplacian s_l(row) s_k(col), s_k(i) = sqrt(2/(N+1)) sin(pi k (i+1)/(N+1)), ordered by
+ *   k^2 + l^2, then k: the exact eigenvectors for V = 0, so the network learns the correction
+ *   the potential makes (a zero output layer returns the free modes).
  * Loss per sample with Y read as n x p (n = N^2, column a = channel a) and target X*
  * (orthonormal n x p): p - Tr((Y^T Y)^-1 (X*^T Y)^T (X*^T Y)), the sum of squared sines of the
  * principal angles between span(Y) and span(X*); a batch loss is the mean.
@@ -52,7 +56,8 @@ typedef struct {
 int64_t fno_param_count(const fno_config* cfg);
 
 /* Creates the network with parameters drawn from a seeded normal distribution (b = 0; W_lift
- * std 1/sqrt(3); R, W, R_out, W_out std 1/sqrt(w)) and Adam moments at zero. *h is set even
+ * std 1/sqrt(3); hidden R, W std 1/sqrt(w); the output layer R_out, W_out, b_out zero, so
+ * that the untrained network returns the prior) and Adam moments at zero. *h is set even
  * on failure (for the message) and must be destroyed. */
 gsi_status fno_create(fno_handle* h, const fno_config* cfg, uint64_t seed, void* hip_stream);
 

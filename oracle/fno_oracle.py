@@ -15,11 +15,16 @@ Architecture (widths w, sine modes m, L hidden layers, p outputs):
   inputs  In = [V / 20, x, y]                        (3 channels; x varies along a grid row)
   lift    U_0 = W_lift In + b_lift                   (pointwise, 3 -> w)
   layer l U_{l+1} = gelu(K_l(U_l) + W_l U_l + b_l)   (l = 0 .. L-1; w -> w)
-  output  Y = K_out(U_L) + W_out U_L + b_out         (w -> p, no activation)
+  output  Y = Phi + K_out(U_L) + W_out U_L + b_out   (w -> p, no activation)
   K(U)[o] = S^T ( sum_c R[o, c] * (S U[c] S^T) ) S   (elementwise product over the m x m
             sine coefficients), S[k, i] = sqrt(2/(N+1)) sin(pi (k+1)(i+1)/(N+1)), k < m:
             the first m rows of the orthonormal type-I sine transform.
-  gelu(t) = t Phi(t) with Phi the standard normal distribution function.
+  gelu(t) = t Phi_n(t) with Phi_n the standard normal distribution function.
+  Phi: fixed prior, column a = sqrt(n) times the a-th lowest Dirichlet mode of the grid
+       Laplacian, phi_{k,l}[row r][col c] = s_l(r) s_k(c) with s_k(i) = sqrt(2/(N+1))
+       sin(pi k (i+1)/(N+1)), ordered by k^2 + l^2, then k. These are the exact eigenvectors
+       of the 5-point Laplacian, i.e. the answer for V = 0, so the network learns the
+       correction that the potential makes; with a zero output layer it returns Phi.
 Loss of one sample, with Y read as an n x p matrix (n = N^2) and X* the target orthonormal
 basis: loss = p - Tr(G^-1 B^T B), G = Y^T Y, B = X*^T Y, i.e. the squared Frobenius norm of
 the projection of X* off span(Y) = the sum of squared sines of the principal angles. A batch
@@ -99,6 +104,19 @@ def gelu(t: torch.Tensor) -> torch.Tensor:
     return 0.5 * t * (1.0 + torch.erf(t / np.sqrt(2.0)))
 
 
+def prior_modes(N: int, p: int):
+    """(k, l) of the p lowest Dirichlet modes, ordered by k^2 + l^2, then k."""
+    K = int(np.ceil(np.sqrt(2 * p))) + 2
+    return sorted(((k, l) for k in range(1, K + 1) for l in range(1, K + 1)), key=lambda t: (t[0] ** 2 + t[1] ** 2, t[0]))[:p]
+
+
+def prior(N: int, p: int) -> torch.Tensor:
+    """Phi as (p, N, N): sqrt(n) times the unit-norm sampled modes."""
+    i = torch.arange(1, N + 1, dtype=torch.float64)
+    s = lambda k: np.sqrt(2.0 / (N + 1)) * torch.sin(np.pi * k * i / (N + 1))
+    return torch.stack([N * torch.outer(s(l), s(k)) for k, l in prior_modes(N, p)])
+
+
 def forward(flat: torch.Tensor, V: torch.Tensor, cfg: Config) -> torch.Tensor:
     """Returns Y as (B, p, N, N): channel a of sample b is column a of its n x p block."""
     P = unflatten(flat, cfg)
@@ -106,7 +124,7 @@ def forward(flat: torch.Tensor, V: torch.Tensor, cfg: Config) -> torch.Tensor:
     U = pointwise(features(V, cfg.N), P["W_lift"], P["b_lift"])
     for l in range(cfg.L):
         U = gelu(spectral(U, P[f"R{l}"], S) + pointwise(U, P[f"W{l}"], P[f"b{l}"]))
-    return spectral(U, P["R_out"], S) + pointwise(U, P["W_out"], P["b_out"])
+    return prior(cfg.N, cfg.p)[None] + spectral(U, P["R_out"], S) + pointwise(U, P["W_out"], P["b_out"])
 
 
 def as_blocks(Y: torch.Tensor) -> torch.Tensor:

@@ -191,9 +191,11 @@ __global__ void k_lift(const float* V, int N, int w, const float* W, const float
     gst(U0 + (b * w + c) * n + j, gld(bias + c) + gld(W + 3 * c) * f0 + gld(W + 3 * c + 1) * f1 + gld(W + 3 * c + 2) * f2);
 }
 
-// s = Vs[b][o] + sum_c W[o][c] U[b][c] + bias[o]; Pre = s (if given); Out = act ? gelu(s) : s.
+// s = Vs[b][o] + sum_c W[o][c] U[b][c] + bias[o] (+ add[o], the same for every sample);
+// Pre = s (if given); Out = act ? gelu(s) : s.
 __global__ __launch_bounds__(WG) void k_point_fwd(const float* Vs, const float* U, const float* W, const float* bias,
-                                                  float* Pre, float* Out, int O, int C, int64_t n, int B, int act) {
+                                                  const float* add, float* Pre, float* Out, int O, int C, int64_t n,
+                                                  int B, int act) {
   __shared__ float sW[32 * 32 + 32];
   for (int e = threadIdx.x; e < O * C; e += WG) sW[e] = gld(W + e);
   for (int e = threadIdx.x; e < O; e += WG) sW[1024 + e] = gld(bias + e);
@@ -205,7 +207,7 @@ __global__ __launch_bounds__(WG) void k_point_fwd(const float* Vs, const float* 
 #pragma unroll
   for (int c = 0; c < 32; ++c) u[c] = c < C ? gld(U + (b * C + c) * n + j) : 0.f;
   for (int o = 0; o < O; ++o) {
-    float s = gld(Vs + (b * O + o) * n + j) + sW[1024 + o];
+    float s = gld(Vs + (b * O + o) * n + j) + sW[1024 + o] + (add ? gld(add + o * n + j) : 0.f);
 #pragma unroll
     for (int c = 0; c < 32; ++c)
       if (c < C) s += sW[o * C + c] * u[c];
@@ -460,7 +462,7 @@ struct fno_net {
   std::vector<int64_t> oR, oW, ob;  // L + 1 entries, the last is the output layer
   float *params = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr;
   int64_t step = 0;
-  float *S = nullptr, *St = nullptr, *ones = nullptr;
+  float *S = nullptr, *St = nullptr, *ones = nullptr, *prior = nullptr;
   float *In = nullptr, *Y = nullptr, *Xc = nullptr, *dY = nullptr, *dPre = nullptr, *dUa = nullptr, *dUb = nullptr;
   float *Wt = nullptr, *Vh = nullptr, *dUh = nullptr, *Zt = nullptr, *Vs = nullptr, *part = nullptr;
   std::vector<float*> act, pre, uh;
@@ -538,7 +540,7 @@ void forward(fno_net* h, const float* V, int B) {
     k_mix_fwd<<<blocks((int64_t)B * O * MP * MP), WG, 0, h->st>>>(h->params + h->oR[l], h->uh[l], h->Vh, B, O, w, m, MP);
     inv_transform(h, h->Vh, B * O, h->Vs, 0.f);
     k_point_fwd<<<blocks(B * n), WG, 0, h->st>>>(h->Vs, h->act[l], h->params + h->oW[l], h->params + h->ob[l],
-                                                 l < L ? h->pre[l] : nullptr, l < L ? h->act[l + 1] : h->Y, O, w, n,
+                                                 l < L ? nullptr : h->prior, l < L ? h->pre[l] : nullptr, l < L ? h->act[l + 1] : h->Y, O, w, n,
                                                  B, l < L ? 1 : 0);
   }
 }
@@ -626,6 +628,7 @@ gsi_status fno_create(fno_handle* out, const fno_config* cfg, uint64_t seed, voi
   h->S = nalloc<float>(h, (size_t)MP * N, e);
   h->St = nalloc<float>(h, (size_t)N * MP, e);
   h->ones = nalloc<float>(h, n, e);
+  h->prior = nalloc<float>(h, (size_t)p * n, e);
   h->In = nalloc<float>(h, B * 3 * n, e);
   for (int l = 0; l <= L; ++l) h->act.push_back(nalloc<float>(h, B * w * n, e));
   for (int l = 0; l < L; ++l) h->pre.push_back(nalloc<float>(h, B * w * n, e));
@@ -658,20 +661,39 @@ gsi_status fno_create(fno_handle* out, const fno_config* cfg, uint64_t seed, voi
       S[(size_t)k * N + i] = (float)v;
       St[(size_t)i * MP + k] = (float)v;
     }
+  // prior: sqrt(n) times the p lowest Dirichlet modes s_l(row) s_k(col), by k^2 + l^2, then k
+  std::vector<float> prior((size_t)p * n);
+  {
+    std::vector<std::pair<int, int>> modes;
+    const int K = (int)ceil(sqrt(2.0 * p)) + 2;
+    for (int k = 1; k <= K; ++k)
+      for (int l = 1; l <= K; ++l) modes.push_back({k, l});
+    std::stable_sort(modes.begin(), modes.end(), [](const std::pair<int, int>& x, const std::pair<int, int>& y) {
+      const int ex = x.first * x.first + x.second * x.second, ey = y.first * y.first + y.second * y.second;
+      return ex != ey ? ex < ey : x.first < y.first;
+    });
+    for (int a = 0; a < p; ++a) {
+      const int k = modes[a].first, l = modes[a].second;
+      for (int r = 0; r < N; ++r)
+        for (int c2 = 0; c2 < N; ++c2)
+          prior[(size_t)a * n + (size_t)r * N + c2] =
+              (float)((double)N * sc * sin(M_PI * l * (r + 1.0) / (N + 1.0)) * sc * sin(M_PI * k * (c2 + 1.0) / (N + 1.0)));
+    }
+  }
   Rng rng{seed};
   auto fill = [&](int64_t o, int64_t cnt, double sd) {
     for (int64_t i = 0; i < cnt; ++i) prm[o + i] = (float)(sd * rng.normal());
   };
   fill(h->oWl, 3 * w, 1.0 / sqrt(3.0));
-  for (int l = 0; l <= L; ++l) {
-    const int64_t O = l < L ? w : p;
-    fill(h->oR[l], O * w * m * m, 1.0 / sqrt((double)w));
-    fill(h->oW[l], O * w, 1.0 / sqrt((double)w));
+  for (int l = 0; l < L; ++l) {  // the output layer starts at zero: the network starts at the prior
+    fill(h->oR[l], (int64_t)w * w * m * m, 1.0 / sqrt((double)w));
+    fill(h->oW[l], (int64_t)w * w, 1.0 / sqrt((double)w));
   }
   e = hipMemcpyAsync(h->S, S.data(), S.size() * 4, hipMemcpyHostToDevice, h->st);
   if (e == hipSuccess) e = hipMemcpyAsync(h->St, St.data(), St.size() * 4, hipMemcpyHostToDevice, h->st);
   if (e == hipSuccess) e = hipMemcpyAsync(h->ones, ones.data(), ones.size() * 4, hipMemcpyHostToDevice, h->st);
   if (e == hipSuccess) e = hipMemcpyAsync(h->params, prm.data(), prm.size() * 4, hipMemcpyHostToDevice, h->st);
+  if (e == hipSuccess) e = hipMemcpyAsync(h->prior, prior.data(), prior.size() * 4, hipMemcpyHostToDevice, h->st);
   if (e == hipSuccess) e = hipMemsetAsync(h->m1, 0, h->count * 4, h->st);
   if (e == hipSuccess) e = hipMemsetAsync(h->m2, 0, h->count * 4, h->st);
   if (e == hipSuccess) e = hipMemsetAsync(h->grad, 0, h->count * 4, h->st);

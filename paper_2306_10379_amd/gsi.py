@@ -387,7 +387,8 @@ class BatchedSolver:
             ci = torch.as_tensor(np.asarray(A.colind, dtype=np.int32), device=device)
             vv = torch.as_tensor(np.asarray(A.vals, dtype=np.float64), device=device)
             dev_mats.append((rp, ci, vv, A.n))
-        xs = [torch.as_tensor(np.ascontiguousarray(X, dtype=np.float64), device=device) for X in X0s]
+        xs = [X.to(device=device, dtype=torch.float64).contiguous() if torch.is_tensor(X)
+              else torch.as_tensor(np.ascontiguousarray(X, dtype=np.float64), device=device) for X in X0s]
         self._keep = [dev_mats, xs]
         self.ns = [A.n for A in mats]
         self.ps = [int(x) for x in ps]

@@ -66,14 +66,33 @@ def test_features_order_matches_the_operator_grid():
     assert f[1, 3, 2] == pytest.approx(3.0 / 6.0) and f[2, 3, 2] == pytest.approx(4.0 / 6.0)
 
 
-def test_zero_network_outputs_the_output_bias():
+def test_zero_network_outputs_the_prior_plus_output_bias():
     cfg = TINY
     flat = np.zeros(F.param_count(cfg))
     bo = np.arange(1, cfg.p + 1, dtype=np.float64)
     flat[-cfg.p:] = bo
     V = np.random.default_rng(1).standard_normal((2, cfg.N * cfg.N))
     Y = F.predict(flat, V, cfg)
-    assert np.allclose(Y, np.broadcast_to(bo, Y.shape))
+    Phi = F.as_blocks(F.prior(cfg.N, cfg.p)[None])[0].numpy()
+    assert np.allclose(Y, (Phi + bo)[None])
+
+
+def test_prior_is_the_lowest_eigenvectors_of_the_grid_laplacian():
+    # the p prior columns are eigenvectors of the 5-point Dirichlet Laplacian whose
+    # eigenvalues are its p smallest (closed form 4/h^2 (sin^2(k pi h/2) + sin^2(l pi h/2)))
+    from paper_2306_10379_amd import inputs as I
+    N, p = 14, 11
+    A = I.laplacian_2d(N).to_dense() * (N + 1) ** 2
+    Phi = F.as_blocks(F.prior(N, p)[None])[0].numpy()
+    assert np.allclose(Phi.T @ Phi, N * N * np.eye(p), atol=1e-9)
+    lam = np.sort(np.linalg.eigvalsh(A))
+    h = 1.0 / (N + 1)
+    for a, (k, l) in enumerate(F.prior_modes(N, p)):
+        mu = 4 / h ** 2 * (np.sin(k * np.pi * h / 2) ** 2 + np.sin(l * np.pi * h / 2) ** 2)
+        assert np.allclose(A @ Phi[:, a], mu * Phi[:, a], atol=1e-8 * N * mu)
+    theta = np.sort([4 / h ** 2 * (np.sin(k * np.pi * h / 2) ** 2 + np.sin(l * np.pi * h / 2) ** 2)
+                     for k, l in F.prior_modes(N, p)])
+    assert np.allclose(theta, lam[:p], rtol=1e-12)
 
 
 def test_loss_is_sum_of_squared_principal_angle_sines():
