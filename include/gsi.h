@@ -45,10 +45,15 @@ typedef enum { GSI_RSD = 1, GSI_RCG = 2 } gsi_method;
 
 typedef enum {
   GSI_FP64 = 0,        /* every step in float64 */
-  GSI_MIXED_FP32 = 1   /* SpMM, Gram and update passes in float32 (float32 accumulation) with
+  GSI_MIXED_FP32 = 1,  /* SpMM, Gram and update passes in float32 (float32 accumulation) with
                           float64 small solves, until rho <= switch_tol or rho stops halving
                           for 200 iterations; then the float64 phase continues the
                           conjugate-gradient recursion to tol */
+  GSI_MIXED_BF16 = 2   /* as GSI_MIXED_FP32, but the iteration's SpMM reads bfloat16 matrix
+                          values and a bfloat16 copy of P (written by the direction pass,
+                          rounded to nearest even) with float32 accumulation and a float32
+                          result: half the gather bytes of float32 (the explicit A X
+                          refreshes keep float32 values) */
 } gsi_precision;
 
 /* Full symmetric CSR (both triangles stored), int32 row pointers and column indices,
@@ -120,6 +125,13 @@ gsi_status gsi_spmm(gsi_handle h, const double* W, double* Z);
 /* Per-iteration history, host arrays of length >= count (nullable): rho, phi, mu, beta_pr
  * and ||G||_inf / ||G_0||_inf per recorded iterate. Returns the number of records in
  * *count (at most the capacity passed in *count). Syncs. */
+/* Z = A W (device, n x p float64 row-major in and out) in the handle's low-phase precision:
+ * float32 values, W rounded to float32, float32 accumulation (GSI_MIXED_FP32), or bfloat16
+ * values and W rounded to bfloat16 (nearest even), float32 accumulation (GSI_MIXED_BF16);
+ * A is the operator solved (negated for which = -1). GSI_EUNSUPPORTED for a float64
+ * handle. For checking the low-precision SpMM; uses the handle's scratch blocks, so call it
+ * between solves. */
+gsi_status gsi_spmm_lowp(gsi_handle h, const double* W, double* Z);
 gsi_status gsi_history(gsi_handle h, int32_t* count, double* rho, double* phi, double* mu,
                        double* beta_pr, double* ginf_rel);
 

@@ -23,6 +23,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
 typedef float f2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 
 template <typename T> struct Vec4;
 template <> struct Vec4<double> { typedef d4 type; };
@@ -65,6 +66,15 @@ template <typename T>
 __device__ __forceinline__ T* to_lds(T* p) {
   return (T*)((__attribute__((address_space(3))) T*)p);
 }
+
+// bfloat16 (the upper 16 bits of a float32): rounding to nearest, ties to even, and
+// widening. NaN stays NaN (quiet bit forced).
+__device__ __forceinline__ uint16_t bf16_round(float f) {
+  const uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x0040u);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_widen(uint32_t b) { return __uint_as_float(b << 16); }
 
 // ---------------------------------------------------------------- tile I/O (per wave)
 

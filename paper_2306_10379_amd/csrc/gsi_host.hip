@@ -7,6 +7,8 @@
 // identical for all iterations, needs no host round trip and is captured once in a HIP
 // graph. The host only polls the convergence flag every check_every iterations.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -51,24 +53,31 @@ struct Engine {
   int p = 0, PP = 0, nb = 0;
   T *X = nullptr, *Y = nullptr, *G0 = nullptr, *G1 = nullptr, *P0 = nullptr, *P1 = nullptr, *Z = nullptr;
   T* vals = nullptr;
+  uint16_t* vals16 = nullptr;  // bfloat16 values and bfloat16 copy of P (bfloat16 mode only)
+  uint16_t* P16 = nullptr;
   double* small = nullptr;
   Scalars* sc = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   bool explicit_grams = false;
 
-  bool alloc(Dev& d, int64_t n_, int p_, int nb_, int64_t nnz) {
+  bool alloc(Dev& d, int64_t n_, int p_, int nb_, int64_t nnz, bool bf16 = false) {
     n = n_; p = p_; PP = round16(p_); nb = nb_;
     // whole TR-row tiles; the rows past n stay zero (cleared once here, never written)
     const size_t blk = (size_t)((n + TR - 1) / TR * TR) * PP;
     X = d.alloc<T>(blk); Y = d.alloc<T>(blk); G0 = d.alloc<T>(blk); G1 = d.alloc<T>(blk);
     P0 = d.alloc<T>(blk); P1 = d.alloc<T>(blk); Z = d.alloc<T>(blk);
     vals = d.alloc<T>((size_t)nnz);
+    if (bf16) {
+      vals16 = d.alloc<uint16_t>((size_t)nnz);
+      P16 = d.alloc<uint16_t>(blk);
+    }
     small = d.alloc<double>((size_t)S_COUNT * PP * PP + 8 * PP);
     sc = d.alloc<Scalars>(1);
     if (d.err != hipSuccess) return false;
     for (T* b : {X, Y, G0, G1, P0, P1, Z})
       if (hipMemset(b, 0, blk * sizeof(T)) != hipSuccess) return false;
+    if (P16 && hipMemset(P16, 0, blk * sizeof(uint16_t)) != hipSuccess) return false;
     return true;
   }
   void destroy_graph() {
@@ -97,6 +106,7 @@ struct gsi_ctx {
   Engine<double> e64;
   Engine<float> e32;
   bool mixed = false;
+  bool bf16 = false;      // mixed phase with bfloat16 SpMM values and inputs
   int phase = 0;          // 0: float64 engine active; 1: float32 engine active (mixed mode)
   int low_iters = 0;      // accepted iterations of the float32 phase
   int low_spmm = 0, low_restarts = 0, low_refresh = 0, low_null = 0, low_sweeps = 0;
@@ -264,7 +274,7 @@ void launch_iteration(gsi_ctx* h, Engine<T>& e, double* hist) {
     }
     {
       PassTimer t(h, GSI_PASS_DIR);
-      Kernels<T, PP>::dir(h->st, e.nb, e.n, e.X, e.G0, e.G1, e.P0, e.P1, e.small, e.sc, h->partials);
+      Kernels<T, PP>::dir(h->st, e.nb, e.n, e.X, e.G0, e.G1, e.P0, e.P1, e.small, e.sc, h->partials, e.P16);
     }
     reduce(h, e.nb, P2 + 1, P2 + 1, e.sc, 1);
     {
@@ -286,7 +296,14 @@ void launch_iteration(gsi_ctx* h, Engine<T>& e, double* hist) {
     if (!h->timing) (void)hipEventRecord(h->ev_join, h->st2);
     {
       PassTimer t(h, GSI_PASS_SPMM);
-      Kernels<T, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.P0, e.P1, e.Z, e.sc, 1);
+      if constexpr (std::is_same<T, float>::value) {
+        if (e.P16)
+          Kernels<T, PP>::spmm16(h->st, e.n, h->rowptr, h->colind, e.vals16, e.P16, e.Z, e.sc, 1);
+        else
+          Kernels<T, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.P0, e.P1, e.Z, e.sc, 1);
+      } else {
+        Kernels<T, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.P0, e.P1, e.Z, e.sc, 1);
+      }
     }
     {
       PassTimer t(h, GSI_PASS_GRAM);
@@ -513,14 +530,16 @@ gsi_status gsi_create(gsi_handle* out, const gsi_csr* A, const gsi_options* opt,
   if (opt->p > MAXP) return bail(GSI_EUNSUPPORTED, "p above 64 is not built");
   if (opt->which != 1 && opt->which != -1) return bail(GSI_EINVAL, "which must be +1 or -1");
   if (opt->method != GSI_RSD && opt->method != GSI_RCG) return bail(GSI_EINVAL, "unknown method");
-  if (opt->precision != GSI_FP64 && opt->precision != GSI_MIXED_FP32) return bail(GSI_EINVAL, "unknown precision");
+  if (opt->precision != GSI_FP64 && opt->precision != GSI_MIXED_FP32 && opt->precision != GSI_MIXED_BF16)
+    return bail(GSI_EINVAL, "unknown precision");
   if (!(opt->tol >= 0.0) || opt->max_iter < 0) return bail(GSI_EINVAL, "bad tol or max_iter");
   if (!X0) return bail(GSI_EINVAL, "X0 is required");
   h->n = A->n;
   h->nnz = A->nnz;
   h->p = opt->p;
   h->PP = round16(opt->p);
-  h->mixed = opt->precision == GSI_MIXED_FP32;
+  h->mixed = opt->precision == GSI_MIXED_FP32 || opt->precision == GSI_MIXED_BF16;
+  h->bf16 = opt->precision == GSI_MIXED_BF16;
   const int64_t ntiles = (h->n + TR - 1) / TR;
   int dev = 0;
   hipDeviceProp_t prop;
@@ -539,7 +558,7 @@ gsi_status gsi_create(gsi_handle* out, const gsi_csr* A, const gsi_options* opt,
   h->flags = d.alloc<int>(4);
   if (d.err != hipSuccess) { d.release(); return bail(GSI_ENOMEM, "device allocation failed"); }
   if (!h->e64.alloc(d, h->n, h->p, h->nb, h->nnz)) { d.release(); return bail(GSI_ENOMEM, "device allocation failed"); }
-  if (h->mixed && !h->e32.alloc(d, h->n, h->p, h->nb, h->nnz)) {
+  if (h->mixed && !h->e32.alloc(d, h->n, h->p, h->nb, h->nnz, h->bf16)) {
     d.release();
     return bail(GSI_ENOMEM, "device allocation failed");
   }
@@ -583,6 +602,7 @@ gsi_status gsi_create(gsi_handle* out, const gsi_csr* A, const gsi_options* opt,
   const double sign = opt->which > 0 ? 1.0 : -1.0;
   launch_convert<double, double>(st, h->nnz, A->vals, h->e64.vals, sign);
   if (h->mixed) launch_convert<double, float>(st, h->nnz, A->vals, h->e32.vals, sign);
+  if (h->bf16) launch_to_bf16(st, h->nnz, A->vals, h->e32.vals16, sign);
   h->e64.explicit_grams = opt->explicit_c != 0;
   h->e32.explicit_grams = opt->explicit_c != 0;
   s = start(h, X0);
@@ -689,6 +709,29 @@ gsi_status gsi_spmm(gsi_handle h, const double* W, double* Z) {
   });
   launch_unpack<double>(h->st, h->n, h->p, h->PP, e.Z, Z);
   return hip_check(h, hipGetLastError(), "spmm");
+}
+
+gsi_status gsi_spmm_lowp(gsi_handle h, const double* W, double* Z) {
+  if (!h || !W || !Z) return GSI_EINVAL;
+  if (!h->mixed) {
+    h->err = "gsi_spmm_lowp needs a mixed-precision handle";
+    return GSI_EUNSUPPORTED;
+  }
+  Engine<float>& e = h->e32;
+  const int64_t rows = (h->n + TR - 1) / TR * TR;
+  dispatch_pp<float>(e.PP, [&](auto PPc) {
+    constexpr int PP = decltype(PPc)::value;
+    if (h->bf16) {
+      launch_pack<double>(h->st, h->n, h->p, h->PP, W, h->e64.G0, 1.0);
+      launch_to_bf16(h->st, rows * PP, h->e64.G0, e.P16, 1.0);
+      Kernels<float, PP>::spmm16(h->st, e.n, h->rowptr, h->colind, e.vals16, e.P16, e.Z, e.sc, 0);
+    } else {
+      launch_pack<float>(h->st, h->n, h->p, h->PP, W, e.G0, 1.0);
+      Kernels<float, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.G0, e.G0, e.Z, e.sc, 0);
+    }
+  });
+  launch_unpack<float>(h->st, h->n, h->p, h->PP, e.Z, Z);
+  return hip_check(h, hipGetLastError(), "spmm_lowp");
 }
 
 gsi_status gsi_history(gsi_handle h, int32_t* count, double* rho, double* phi, double* mu, double* beta_pr,

@@ -19,8 +19,9 @@ struct Kernels {
   static hipError_t init();
   static void grad(hipStream_t st, int nb, int64_t n, const T* X, const T* Y, T* G0, T* G1, const double* small,
                    const Scalars* sc, double* partials);
+  // P16 (nullable): bfloat16 copy of P written beside it
   static void dir(hipStream_t st, int nb, int64_t n, const T* X, const T* G0, const T* G1, T* P0, T* P1,
-                  const double* small, const Scalars* sc, double* partials);
+                  const double* small, const Scalars* sc, double* partials, uint16_t* P16 = nullptr);
   static void update(hipStream_t st, int nb, int64_t n, T* X, T* Y, const T* P0, const T* P1, const T* Z,
                      const double* small, const Scalars* sc, double* partials, bool grams);
   static void spmm(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind, const T* vals,
@@ -29,6 +30,9 @@ struct Kernels {
   static void gram(hipStream_t st, int nb, int64_t n, const T* A0, const T* A1, const T* B1, const T* B2,
                    const Scalars* sc, int mode, double* partials);
   static void product(hipStream_t st, int nb, int64_t n, const T* IN, T* OUT, const double* M);
+  // Z = A W with bfloat16 values and W, float32 accumulation and output
+  static void spmm16(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind, const uint16_t* vals,
+                     const uint16_t* W, float* Z, const Scalars* sc, int mode);
   static void colres(hipStream_t st, int nb, int64_t n, const T* X, const T* Y, const double* theta,
                      double* partials);
 };
@@ -36,6 +40,7 @@ struct Kernels {
 void launch_reduce(hipStream_t st, const double* partials, int nb, int64_t nv, int64_t max_from, double* out,
                    const Scalars* sc, int cond);
 void launch_set_sym(hipStream_t st, int PP, const double* red, double* dst);
+void launch_to_bf16(hipStream_t st, int64_t count, const double* src, uint16_t* dst, double scale);
 template <typename T>
 void launch_pack(hipStream_t st, int64_t n, int p, int PP, const double* src, T* dst, double scale);
 template <typename T>

@@ -108,7 +108,7 @@ template <typename T, int PP>
 __global__ __launch_bounds__(WG) void k_dir(int64_t n, const T* __restrict__ X, const T* __restrict__ G0,
                                             const T* __restrict__ G1, T* __restrict__ P0, T* __restrict__ P1,
                                             const double* __restrict__ small, const Scalars* __restrict__ sc,
-                                            double* __restrict__ partials) {
+                                            double* __restrict__ partials, uint16_t* __restrict__ P16) {
   if (sc->done) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* sK = reinterpret_cast<T*>(lds_raw);
@@ -151,6 +151,17 @@ __global__ __launch_bounds__(WG) void k_dir(int64_t n, const T* __restrict__ X, 
         for (int r = 0; r < 4; ++r) p[cb][r] = g[cb][r] - acc[cb][r];
     }
     store_rl<T, PP>(P, row0, n, p);
+    if (P16) {
+      // bfloat16 copy of P for the SpMM of the bfloat16 mode
+      const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = row0 + rowof<T>(g, r);
+        if (row < n)
+#pragma unroll
+          for (int cb = 0; cb < PP / 16; ++cb) gst(P16 + row * PP + 16 * cb + c, bf16_round((float)p[cb][r]));
+      }
+    }
 #pragma unroll
     for (int cb = 0; cb < PP / 16; ++cb)
 #pragma unroll
@@ -325,6 +336,60 @@ __global__ __launch_bounds__(WG) void k_spmm(int64_t n, const int32_t* __restric
     } else {
       *reinterpret_cast<float4*>(zr) = make_float4(acc[0], acc[1], acc[2], acc[3]);
     }
+  }
+}
+
+// Z (float32) = A W with bfloat16 values and a bfloat16 W, float32 accumulation (the
+// products of two bfloat16 numbers are exact in float32). Same tiling and modes as k_spmm;
+// a lane owns 8 consecutive columns (one 16-byte gather per nonzero).
+template <int PP>
+__global__ __launch_bounds__(WG) void k_spmm16(int64_t n, const int32_t* __restrict__ rowptr,
+                                               const int32_t* __restrict__ colind, const uint16_t* __restrict__ vals,
+                                               const uint16_t* __restrict__ W, float* __restrict__ Z,
+                                               const Scalars* __restrict__ sc, int mode) {
+  if (spmm_skip(sc, mode)) return;
+  constexpr int EPL = 8;
+  constexpr int LPR = PP / EPL;  // lanes per row
+  constexpr int RPB = WG / LPR;  // rows per block pass
+  constexpr int U = 8;           // nonzeros per batch
+  const int64_t ntiles = (n + TR - 1) / TR;
+  const int64_t t = xcd_tile(ntiles);
+  if (t >= ntiles) return;
+  constexpr int PASSES = (TR + RPB - 1) / RPB;  // at PP = 16 a pass spans 128 rows: half the lanes idle
+  const int sub = threadIdx.x / LPR, lane = threadIdx.x % LPR;
+#pragma unroll
+  for (int pass = 0; pass < PASSES; ++pass) {
+    const int64_t row = t * TR + pass * RPB + sub;
+    if (pass * RPB + sub >= TR || row >= n) continue;
+    float acc[EPL];
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) acc[e] = 0.f;
+    const int32_t j0 = rowptr[row], j1 = rowptr[row + 1];
+    for (int32_t j = j0; j < j1; j += U) {
+      int32_t col[U];
+      float v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool ok = j + u < j1;
+        col[u] = ok ? colind[j + u] : 0;
+        v[u] = ok ? bf16_widen(vals[j + u]) : 0.f;
+      }
+      u4 x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) x[u] = gld(reinterpret_cast<const u4*>(W + (int64_t)col[u] * PP + EPL * lane));
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t w4[4] = {x[u][0], x[u][1], x[u][2], x[u][3]};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          acc[2 * q] += v[u] * bf16_widen(w4[q] & 0xffffu);
+          acc[2 * q + 1] += v[u] * bf16_widen(w4[q] >> 16);
+        }
+      }
+    }
+    float* zr = Z + row * PP + EPL * lane;
+    *reinterpret_cast<float4*>(zr) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    *reinterpret_cast<float4*>(zr + 4) = make_float4(acc[4], acc[5], acc[6], acc[7]);
   }
 }
 
@@ -539,6 +604,12 @@ __global__ void k_convert(int64_t count, const TS* __restrict__ src, TD* __restr
   if (i < count) dst[i] = (TD)(scale * (double)src[i]);
 }
 
+// dst = bfloat16(float32(scale * src)) (round to nearest even at each narrowing).
+__global__ void k_to_bf16(int64_t count, const double* __restrict__ src, uint16_t* __restrict__ dst, double scale) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = bf16_round((float)(scale * src[i]));
+}
+
 // CSR checks and ||A||_inf: partial max of absolute row sums per workgroup, error flags:
 // bit 0 rowptr not monotone / out of range, bit 1 column index out of range, bit 2
 // non-finite value, bit 3 columns not sorted within a row.
@@ -623,8 +694,15 @@ void Kernels<T, PP>::grad(hipStream_t st, int nb, int64_t n, const T* X, const T
 }
 template <typename T, int PP>
 void Kernels<T, PP>::dir(hipStream_t st, int nb, int64_t n, const T* X, const T* G0, const T* G1, T* P0, T* P1,
-                         const double* small, const Scalars* sc, double* partials) {
-  k_dir<T, PP><<<nb, WG, lds_bytes<T, PP>(Pass::Dir), st>>>(n, X, G0, G1, P0, P1, small, sc, partials);
+                         const double* small, const Scalars* sc, double* partials, uint16_t* P16) {
+  k_dir<T, PP><<<nb, WG, lds_bytes<T, PP>(Pass::Dir), st>>>(n, X, G0, G1, P0, P1, small, sc, partials, P16);
+}
+template <typename T, int PP>
+void Kernels<T, PP>::spmm16(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind,
+                            const uint16_t* vals, const uint16_t* W, float* Z, const Scalars* sc, int mode) {
+  const int64_t ntiles = (n + TR - 1) / TR;
+  const int64_t grid = 8 * ((ntiles + 7) / 8);
+  k_spmm16<PP><<<dim3((unsigned)grid), dim3(WG), 0, st>>>(n, rowptr, colind, vals, W, Z, sc, mode);
 }
 template <typename T, int PP>
 void Kernels<T, PP>::update(hipStream_t st, int nb, int64_t n, T* X, T* Y, const T* P0, const T* P1, const T* Z,
@@ -691,6 +769,9 @@ template <typename TS, typename TD>
 void launch_convert(hipStream_t st, int64_t count, const TS* src, TD* dst, double scale) {
   hipLaunchKernelGGL((k_convert<TS, TD>), dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count, src, dst,
                      scale);
+}
+void launch_to_bf16(hipStream_t st, int64_t count, const double* src, uint16_t* dst, double scale) {
+  hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count, src, dst, scale);
 }
 void launch_csr_check(hipStream_t st, int nb, int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colind,
                       const double* vals, double* partial_max, int* flags) {

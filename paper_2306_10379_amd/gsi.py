@@ -17,11 +17,11 @@ LIB_PATH = os.path.join(_HERE, "libgsi.so")
 
 GSI_OK, GSI_EINVAL, GSI_ENOMEM, GSI_EDEVICE, GSI_NOT_CONVERGED, GSI_BREAKDOWN, GSI_EUNSUPPORTED = range(7)
 GSI_RSD, GSI_RCG = 1, 2
-GSI_FP64, GSI_MIXED_FP32 = 0, 1
+GSI_FP64, GSI_MIXED_FP32, GSI_MIXED_BF16 = 0, 1, 2
 
 EXPORTS = [
     "gsi_options_default", "gsi_create", "gsi_step", "gsi_solve", "gsi_residuals", "gsi_get_x",
-    "gsi_set_x0", "gsi_spmm", "gsi_history", "gsi_counters", "gsi_pass_times", "gsi_destroy",
+    "gsi_set_x0", "gsi_spmm", "gsi_spmm_lowp", "gsi_history", "gsi_counters", "gsi_pass_times", "gsi_destroy",
     "gsi_status_str", "gsi_last_error", "gsi_create_batched", "gsi_solve_batched", "gsi_batched_results",
     "gsi_batched_get_x", "gsi_batched_timeline", "gsi_batched_pass_times", "gsi_batched_last_error", "gsi_destroy_batched",
 ]
@@ -69,6 +69,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gsi_set_x0.restype = ctypes.c_int
     L.gsi_spmm.argtypes = [vp, vp, vp]
     L.gsi_spmm.restype = ctypes.c_int
+    L.gsi_spmm_lowp.argtypes = [vp, vp, vp]
+    L.gsi_spmm_lowp.restype = ctypes.c_int
     L.gsi_history.argtypes = [vp, P(i32), P(dbl), P(dbl), P(dbl), P(dbl), P(dbl)]
     L.gsi_history.restype = ctypes.c_int
     L.gsi_counters.argtypes = [vp, P(i32), P(i32), P(i32), P(i32), P(i32), P(i32), P(i32)]
@@ -177,6 +179,10 @@ def gsi_spmm(h, W, Z):
     return _check(h, load().gsi_spmm(h, ctypes.c_void_p(_dptr(W)), ctypes.c_void_p(_dptr(Z))))
 
 
+def gsi_spmm_lowp(h, W, Z):
+    return _check(h, load().gsi_spmm_lowp(h, ctypes.c_void_p(_dptr(W)), ctypes.c_void_p(_dptr(Z))))
+
+
 def gsi_history(h, capacity: int):
     cnt = ctypes.c_int32(capacity)
     arrs = [(ctypes.c_double * max(capacity, 1))() for _ in range(5)]
@@ -235,7 +241,8 @@ class Solver:
         method = opts.pop("method", "rcg")
         precision = opts.pop("precision", "fp64")
         opts["method"] = {"rsd": GSI_RSD, "rcg": GSI_RCG}[method] if isinstance(method, str) else method
-        opts["precision"] = {"fp64": GSI_FP64, "mixed": GSI_MIXED_FP32, "fp32": GSI_MIXED_FP32}[precision] \
+        opts["precision"] = {"fp64": GSI_FP64, "mixed": GSI_MIXED_FP32, "fp32": GSI_MIXED_FP32,
+                             "bf16": GSI_MIXED_BF16}[precision] \
             if isinstance(precision, str) else precision
         for b in ("recompute_ax", "use_graph", "explicit_c"):
             if b in opts:
@@ -266,6 +273,13 @@ class Solver:
         import torch
         Z = torch.empty_like(W)
         gsi_spmm(self.h, W.contiguous(), Z)
+        torch.cuda.synchronize()
+        return Z
+
+    def spmm_lowp(self, W):
+        import torch
+        Z = torch.empty_like(W)
+        gsi_spmm_lowp(self.h, W.contiguous(), Z)
         torch.cuda.synchronize()
         return Z
 

@@ -261,3 +261,49 @@ def test_batched_full_schrodinger_batch():
             ref = O.rcg(A, X0, tol=tol, which=-1, max_iter=30000)
             ritz, rho, _ = b.results(i)
             assert np.max(np.abs(-ritz - ref.theta) / np.abs(ref.theta)) <= 1e-9
+
+
+def _round_bf16(x):
+    """float64 -> float32 -> bfloat16 (round to nearest, ties to even), returned as float64."""
+    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("p", [8, 20, 64])
+def test_spmm_bf16_matches_rounded_operator(p):
+    """The low-precision SpMM of the bfloat16 mode: values and the block rounded to bfloat16,
+    products exact in float32, float32 accumulation. Reference: the same roundings in NumPy,
+    exact products and sums in float64; bound: float32 accumulation of at most 32 terms."""
+    gsi = _gsi()
+    A = I.spiked_sparse(3000, 12, max(p, 2), 3)
+    W = I.start_block(A.n, p, 4)
+    print(f"bf16 spmm n={A.n} nnz={A.nnz} p={p}", flush=True)
+    with gsi.Solver(A, W, p, max_iter=1, precision="bf16") as s:
+        Z = s.spmm_lowp(dev(W)).cpu().numpy()
+    S16 = A.to_scipy().copy()
+    S16.data = _round_bf16(S16.data)
+    W16 = _round_bf16(W)
+    ref = S16 @ W16
+    absS = S16.copy()
+    absS.data = np.abs(absS.data)
+    bound = 32 * 2.0 ** -24 * (absS @ np.abs(W16)) + 1e-30
+    assert np.all(np.abs(Z - ref) <= bound)
+    # and the rounding is what it claims: far from the float64 product
+    assert np.max(np.abs(Z - A.to_scipy() @ W)) > 1e-5 * np.max(np.abs(ref))
+
+
+def test_mixed_bf16_reaches_fp64_accuracy():
+    """Spiked sparse matrix with random columns (the C3 family, small): bfloat16 SpMM phase,
+    then float64 refinement to rho <= 1e-10; Ritz values equal the oracle's to 1e-10."""
+    A = I.spiked_sparse(6000, 12, 16, 5, gap=2e-2)
+    print(f"bf16 mixed n={A.n} nnz={A.nnz} p=16", flush=True)
+    ref, r, X, hist = _solve_both(A, 16, 6, precision="bf16", switch_tol=1e-4)
+    assert r.status == 0
+    assert r.counters["low_iters"] > 0
+    assert np.max(np.abs(r.ritz - ref.theta) / np.abs(ref.theta)) <= 1e-10
+    w = np.sort(scipy.sparse.linalg.eigsh(A.to_scipy(), k=18, which="LA", tol=1e-13)[0])[::-1]
+    delta = w[15] - w[16]
+    nA = O.norm_inf(A.to_scipy())
+    bound = (r.rho + ref.rho[-1]) * np.sqrt(16) * nA / delta
+    assert O.principal_angles(X, ref.X).max() <= max(bound, 1e-10)
