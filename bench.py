@@ -81,6 +81,55 @@ def cpu_baseline(A, X0, p, tol, gpu_iters, iters=3):
                       f"extrapolated to the GPU's {gpu_iters} iterations"}
 
 
+def c3_leg(args, gsi, inputs, torch):
+    """Random-column sparse matrix: time to tol per precision and the SpMM's rates. The
+    SpMM of a random-column matrix gathers a P row per nonzero with no reuse, so besides the
+    compulsory bytes (matrix once, P once, Z once) the gather bytes nnz * p * element size are
+    reported; the measured HBM bytes come from rocprofv3 (profiles/)."""
+    n, p = 1 << 22, 64
+    log(f"building the spiked sparse matrix n={n}, 24 random nonzeros per row")
+    A = inputs.spiked_sparse(n, 12, p, 7)
+    X0 = inputs.start_block(n, p, 8)
+    dev = torch.device("cuda:0")
+    rowptr = torch.as_tensor(A.rowptr.astype(np.int32), device=dev)
+    colind = torch.as_tensor(A.colind, device=dev)
+    vals = torch.as_tensor(A.vals, device=dev)
+    X0d = torch.as_tensor(X0, device=dev)
+    del X0
+    res = {"workload": f"spiked sparse symmetric, n={n}, nnz={A.nnz} (uniform random columns, B + B^T, "
+                       f"N(0,1)/sqrt(24) values, {p} diagonal spikes, gap 1e-3 above the bulk edge), p={p} largest, "
+                       f"rho <= {args.tol:g}", "n": n, "nnz": int(A.nnz), "p": p}
+    for prec, sw in (("fp64", 1e-6), ("bf16", 1e-4), ("fp32", 1e-6)):
+        s = gsi.Solver((rowptr, colind, vals, n), X0d, p, tol=args.tol, max_iter=20000, precision=prec,
+                       check_every=50, switch_tol=sw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        status, iters = s.solve()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        c = s.counters()
+        log(f"c3 {prec}: {dt:.2f} s, {iters} iterations (low-precision {c['low_iters']}), status {status}")
+        # SpMM duration in the first phase: 20 iterations with per-pass events
+        s.set_x0(X0d)
+        s.pass_times(1)
+        s.step(20)
+        pt = s.pass_times(0)
+        ms, cnt = pt["spmm"]
+        es_in = {"fp64": 8, "fp32": 4, "bf16": 2}[prec]
+        es_val = es_in
+        es_out = 8 if prec == "fp64" else 4
+        avg = ms / max(cnt, 1) * 1e-3
+        compulsory = A.nnz * (es_val + 4) + 4 * (n + 1) + n * p * (es_in + es_out)
+        gathers = A.nnz * p * es_in
+        res[prec] = {"s": round(dt, 3), "iters": iters, "low_iters": c["low_iters"], "status": status,
+                     "spmm_us": round(avg * 1e6, 1), "spmm_compulsory_GBps": round(compulsory / avg / 1e9, 1),
+                     "spmm_gather_GBps": round((gathers + compulsory - n * p * es_in) / avg / 1e9, 1)}
+        s.close()
+    res["speedup_bf16_vs_fp64"] = round(res["fp64"]["s"] / res["bf16"]["s"], 3)
+    res["speedup_fp32_vs_fp64"] = round(res["fp64"]["s"] / res["fp32"]["s"], 3)
+    return res
+
+
 def batched_leg(args, gsi, inputs, torch):
     """Many small problems in one persistent launch: the whole batch to rho <= tol with float32
     blocks then float64 refinement, and with float64 blocks, against the plain float64 path
@@ -146,6 +195,9 @@ def main():
     ap.add_argument("--warm", action="store_true",
                     help="also run the learned warm-start leg (256 x 256 Schroedinger operators, 8 wells, p = 32: "
                          "training data from the method's own solves, training, held-out comparison; ~8 minutes)")
+    ap.add_argument("--c3", action="store_true",
+                    help="also run the random-sparse leg: spiked sparse matrix n = 2^22, 24 random nonzeros per "
+                         "row, p = 64 (float64, float32-mixed and bfloat16-mixed solves, SpMM rates; ~4 minutes)")
     ap.add_argument("--warm-train", type=int, default=144)
     ap.add_argument("--warm-test", type=int, default=24)
     ap.add_argument("--batch", type=int, default=512)
@@ -242,6 +294,7 @@ def main():
                  "rho": rho32}
 
     batched = None if args.no_batched else batched_leg(args, gsi, inputs, torch)
+    c3 = c3_leg(args, gsi, inputs, torch) if args.c3 else None
     warm = None
     if args.warm:
         from paper_2306_10379_amd import warmstart
@@ -282,6 +335,7 @@ def main():
         "pass_share": {k: round(v[0] / total_ms, 4) for k, v in pt.items() if total_ms > 0},
         "mixed_fp32": mixed,
         "batched": batched,
+        "random_sparse": c3,
         "warm_start": warm,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -103,6 +103,7 @@ struct gsi_ctx {
   int* flags = nullptr;
   int hist_cap = 0;
   double nA = 0.0;
+  int64_t plane_tiles = 0;  // banded SpMM tile order (0: one slab per XCD)
   Engine<double> e64;
   Engine<float> e32;
   bool mixed = false;
@@ -248,7 +249,7 @@ gsi_status init_state(gsi_ctx* h, Engine<T>& e, double tol, int max_iter, int hi
                     "small reset"));
   dispatch_pp<T>(e.PP, [&](auto PPc) {
     constexpr int PP = decltype(PPc)::value;
-    Kernels<T, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.X, e.X, e.Y, e.sc, 0);
+    Kernels<T, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.X, e.X, e.Y, e.sc, 0, h->plane_tiles);
     Kernels<T, PP>::gram(h->st, e.nb, e.n, e.X, e.X, e.Y, nullptr, e.sc, 0, h->partials);
     reduce(h, e.nb, (int64_t)PP * PP, (int64_t)PP * PP, e.sc, 0);
     launch_set_sym(h->st, PP, h->red, e.small + S_C * PP * PP);
@@ -298,11 +299,11 @@ void launch_iteration(gsi_ctx* h, Engine<T>& e, double* hist) {
       PassTimer t(h, GSI_PASS_SPMM);
       if constexpr (std::is_same<T, float>::value) {
         if (e.P16)
-          Kernels<T, PP>::spmm16(h->st, e.n, h->rowptr, h->colind, e.vals16, e.P16, e.Z, e.sc, 1);
+          Kernels<T, PP>::spmm16(h->st, e.n, h->rowptr, h->colind, e.vals16, e.P16, e.Z, e.sc, 1, h->plane_tiles);
         else
-          Kernels<T, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.P0, e.P1, e.Z, e.sc, 1);
+          Kernels<T, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.P0, e.P1, e.Z, e.sc, 1, h->plane_tiles);
       } else {
-        Kernels<T, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.P0, e.P1, e.Z, e.sc, 1);
+        Kernels<T, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.P0, e.P1, e.Z, e.sc, 1, h->plane_tiles);
       }
     }
     {
@@ -327,7 +328,7 @@ void launch_iteration(gsi_ctx* h, Engine<T>& e, double* hist) {
     }
     {
       PassTimer t(h, GSI_PASS_REFRESH);
-      Kernels<T, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.X, e.X, e.Y, e.sc, 2);
+      Kernels<T, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.X, e.X, e.Y, e.sc, 2, h->plane_tiles);
       Kernels<T, PP>::gram(h->st, e.nb, e.n, e.X, e.X, e.Y, nullptr, e.sc, 2, h->partials);
     }
     reduce(h, e.nb, P2, P2, e.sc, 2);
@@ -581,11 +582,11 @@ gsi_status gsi_create(gsi_handle* out, const gsi_csr* A, const gsi_options* opt,
   if (s != GSI_OK) return bail(s, h->err);
   // validate the CSR and compute ||A||_inf
   const int cb = 256;
-  launch_csr_check(st, cb, h->n, h->nnz, A->rowptr, A->colind, A->vals, h->dvec, h->flags);
+  launch_csr_check(st, cb, h->n, h->nnz, A->rowptr, A->colind, A->vals, h->dvec, h->flags, h->dvec + cb);
   launch_finite(st, h->n * (int64_t)h->p, X0, h->flags + 1);
-  std::vector<double> pm(cb);
+  std::vector<double> pm(2 * cb);
   int fl[2] = {0, 0};
-  s = hip_check(h, hipMemcpyAsync(pm.data(), h->dvec, sizeof(double) * cb, hipMemcpyDeviceToHost, st), "norm");
+  s = hip_check(h, hipMemcpyAsync(pm.data(), h->dvec, sizeof(double) * 2 * cb, hipMemcpyDeviceToHost, st), "norm");
   if (s == GSI_OK) s = hip_check(h, hipMemcpyAsync(fl, h->flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st), "flags");
   if (s == GSI_OK) s = hip_check(h, hipStreamSynchronize(st), "validate");
   if (s != GSI_OK) return bail(s, h->err);
@@ -595,10 +596,19 @@ gsi_status gsi_create(gsi_handle* out, const gsi_csr* A, const gsi_options* opt,
   if (fl[0] & 4) return bail(GSI_BREAKDOWN, "non-finite matrix value");
   if (fl[1]) return bail(GSI_BREAKDOWN, "non-finite value in X0");
   (void)hipMemsetAsync(h->flags, 0, 4 * sizeof(int), st);
-  double nA = 0.0;
-  for (double v : pm) nA = v > nA ? v : nA;
+  double nA = 0.0, band = 0.0;
+  for (int i = 0; i < cb; ++i) {
+    nA = pm[i] > nA ? pm[i] : nA;
+    band = pm[cb + i] > band ? pm[cb + i] : band;
+  }
   if (!(nA > 0.0)) return bail(GSI_EINVAL, "zero matrix");
   h->nA = nA;
+  // banded SpMM tile order when the rows reach at least 64 tiles away and the matrix spans
+  // at least 4 such planes (3D grids); otherwise one contiguous slab per XCD
+  {
+    const int64_t pt = ((int64_t)band + TR - 1) / TR, ntiles = (h->n + TR - 1) / TR;
+    h->plane_tiles = (pt >= 64 && 4 * pt <= ntiles) ? pt : 0;
+  }
   const double sign = opt->which > 0 ? 1.0 : -1.0;
   launch_convert<double, double>(st, h->nnz, A->vals, h->e64.vals, sign);
   if (h->mixed) launch_convert<double, float>(st, h->nnz, A->vals, h->e32.vals, sign);
@@ -640,7 +650,7 @@ gsi_status gsi_residuals(gsi_handle h, double* ritz, double* col_res, double* rh
   double* theta = h->dvec;
   dispatch_pp<double>(e.PP, [&](auto PPc) {
     constexpr int PP = decltype(PPc)::value;
-    Kernels<double, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.X, e.X, e.Y, e.sc, 0);
+    Kernels<double, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.X, e.X, e.Y, e.sc, 0, h->plane_tiles);
     Kernels<double, PP>::gram(h->st, e.nb, e.n, e.X, e.X, e.Y, nullptr, e.sc, 0, h->partials);
     reduce(h, e.nb, (int64_t)PP * PP, (int64_t)PP * PP, e.sc, 0);
     Small::ritz(h->st, PP, p, h->red, e.small, theta);
@@ -705,7 +715,7 @@ gsi_status gsi_spmm(gsi_handle h, const double* W, double* Z) {
   launch_pack<double>(h->st, h->n, h->p, h->PP, W, e.G0, 1.0);
   dispatch_pp<double>(e.PP, [&](auto PPc) {
     constexpr int PP = decltype(PPc)::value;
-    Kernels<double, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.G0, e.G0, e.Z, e.sc, 0);
+    Kernels<double, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.G0, e.G0, e.Z, e.sc, 0, h->plane_tiles);
   });
   launch_unpack<double>(h->st, h->n, h->p, h->PP, e.Z, Z);
   return hip_check(h, hipGetLastError(), "spmm");
@@ -724,10 +734,10 @@ gsi_status gsi_spmm_lowp(gsi_handle h, const double* W, double* Z) {
     if (h->bf16) {
       launch_pack<double>(h->st, h->n, h->p, h->PP, W, h->e64.G0, 1.0);
       launch_to_bf16(h->st, rows * PP, h->e64.G0, e.P16, 1.0);
-      Kernels<float, PP>::spmm16(h->st, e.n, h->rowptr, h->colind, e.vals16, e.P16, e.Z, e.sc, 0);
+      Kernels<float, PP>::spmm16(h->st, e.n, h->rowptr, h->colind, e.vals16, e.P16, e.Z, e.sc, 0, h->plane_tiles);
     } else {
       launch_pack<float>(h->st, h->n, h->p, h->PP, W, e.G0, 1.0);
-      Kernels<float, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.G0, e.G0, e.Z, e.sc, 0);
+      Kernels<float, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.G0, e.G0, e.Z, e.sc, 0, h->plane_tiles);
     }
   });
   launch_unpack<float>(h->st, h->n, h->p, h->PP, e.Z, Z);

@@ -24,15 +24,16 @@ struct Kernels {
                   const double* small, const Scalars* sc, double* partials, uint16_t* P16 = nullptr);
   static void update(hipStream_t st, int nb, int64_t n, T* X, T* Y, const T* P0, const T* P1, const T* Z,
                      const double* small, const Scalars* sc, double* partials, bool grams);
+  // plane_tiles > 0: banded tile order (see spmm_tile in gsi_kernels.hip); 0: one slab per XCD
   static void spmm(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind, const T* vals,
-                   const T* W0, const T* W1, T* Z, const Scalars* sc, int mode);
+                   const T* W0, const T* W1, T* Z, const Scalars* sc, int mode, int64_t plane_tiles = 0);
   // A^T B1 (and A^T B2 when B2 != nullptr); mode as for spmm (mode 1 picks A0/A1 by parity)
   static void gram(hipStream_t st, int nb, int64_t n, const T* A0, const T* A1, const T* B1, const T* B2,
                    const Scalars* sc, int mode, double* partials);
   static void product(hipStream_t st, int nb, int64_t n, const T* IN, T* OUT, const double* M);
   // Z = A W with bfloat16 values and W, float32 accumulation and output
   static void spmm16(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind, const uint16_t* vals,
-                     const uint16_t* W, float* Z, const Scalars* sc, int mode);
+                     const uint16_t* W, float* Z, const Scalars* sc, int mode, int64_t plane_tiles = 0);
   static void colres(hipStream_t st, int nb, int64_t n, const T* X, const T* Y, const double* theta,
                      double* partials);
 };
@@ -48,7 +49,8 @@ void launch_unpack(hipStream_t st, int64_t n, int p, int PP, const T* src, doubl
 template <typename TS, typename TD>
 void launch_convert(hipStream_t st, int64_t count, const TS* src, TD* dst, double scale);
 void launch_csr_check(hipStream_t st, int nb, int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colind,
-                      const double* vals, double* partial_max, int* flags);
+                      const double* vals, double* partial_max, int* flags,
+                      double* partial_band = nullptr);
 void launch_finite(hipStream_t st, int64_t count, const double* x, int* flags);
 
 // Single-workgroup p x p solves (gsi_small.hip). All read/write the small buffer and the

@@ -281,11 +281,33 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t ntiles) {
   return (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
 }
 
+// Tile of this workgroup (ntiles or more: none). plane_tiles == 0: the XCDs (blockIdx mod 8)
+// each sweep one contiguous slab (xcd_tile). plane_tiles > 0 (a banded matrix whose rows
+// reach about plane_tiles tiles away, e.g. the neighbouring planes of a 3D grid): the rows
+// are cut into planes of plane_tiles tiles, each plane is dealt to the 8 XCDs as 8 chunks
+// and every XCD sweeps its chunk of one plane after the other, so that the rows its current
+// chunk reaches in the previous and next plane are still in that XCD's L2.
+__device__ __forceinline__ int64_t spmm_tile(int64_t ntiles, int64_t plane_tiles) {
+  if (plane_tiles <= 0) return xcd_tile(ntiles);
+  const int64_t chunk = (plane_tiles + 7) / 8;
+  const int64_t x = blockIdx.x & 7, i = blockIdx.x >> 3;
+  const int64_t local = x * chunk + i % chunk;
+  if (local >= plane_tiles) return ntiles;
+  return (i / chunk) * plane_tiles + local;
+}
+
+// Workgroups of an SpMM launch (8 per XCD round; see spmm_tile).
+inline int64_t spmm_grid(int64_t ntiles, int64_t plane_tiles) {
+  if (plane_tiles <= 0) return 8 * ((ntiles + 7) / 8);
+  const int64_t chunk = (plane_tiles + 7) / 8, planes = (ntiles + plane_tiles - 1) / plane_tiles;
+  return 8 * chunk * planes;
+}
+
 template <typename T, int PP>
 __global__ __launch_bounds__(WG) void k_spmm(int64_t n, const int32_t* __restrict__ rowptr,
                                              const int32_t* __restrict__ colind, const T* __restrict__ vals,
                                              const T* __restrict__ W0, const T* __restrict__ W1, T* __restrict__ Z,
-                                             const Scalars* __restrict__ sc, int mode) {
+                                             const Scalars* __restrict__ sc, int mode, int64_t plane_tiles) {
   if (spmm_skip(sc, mode)) return;
   const T* W = (mode == 1 && (sc->k & 1)) ? W1 : W0;
   constexpr int EPL = 4;
@@ -293,7 +315,7 @@ __global__ __launch_bounds__(WG) void k_spmm(int64_t n, const int32_t* __restric
   constexpr int RPB = WG / LPR;  // rows per block pass
   constexpr int U = 8;           // nonzeros per batch
   const int64_t ntiles = (n + TR - 1) / TR;
-  const int64_t t = xcd_tile(ntiles);
+  const int64_t t = spmm_tile(ntiles, plane_tiles);
   if (t >= ntiles) return;
   const int sub = threadIdx.x / LPR, lane = threadIdx.x % LPR;
 #pragma unroll
@@ -346,14 +368,14 @@ template <int PP>
 __global__ __launch_bounds__(WG) void k_spmm16(int64_t n, const int32_t* __restrict__ rowptr,
                                                const int32_t* __restrict__ colind, const uint16_t* __restrict__ vals,
                                                const uint16_t* __restrict__ W, float* __restrict__ Z,
-                                               const Scalars* __restrict__ sc, int mode) {
+                                               const Scalars* __restrict__ sc, int mode, int64_t plane_tiles) {
   if (spmm_skip(sc, mode)) return;
   constexpr int EPL = 8;
   constexpr int LPR = PP / EPL;  // lanes per row
   constexpr int RPB = WG / LPR;  // rows per block pass
   constexpr int U = 8;           // nonzeros per batch
   const int64_t ntiles = (n + TR - 1) / TR;
-  const int64_t t = xcd_tile(ntiles);
+  const int64_t t = spmm_tile(ntiles, plane_tiles);
   if (t >= ntiles) return;
   constexpr int PASSES = (TR + RPB - 1) / RPB;  // at PP = 16 a pass spans 128 rows: half the lanes idle
   const int sub = threadIdx.x / LPR, lane = threadIdx.x % LPR;
@@ -615,9 +637,12 @@ __global__ void k_to_bf16(int64_t count, const double* __restrict__ src, uint16_
 // non-finite value, bit 3 columns not sorted within a row.
 __global__ void k_csr_check(int64_t n, int64_t nnz, const int32_t* __restrict__ rowptr,
                             const int32_t* __restrict__ colind, const double* __restrict__ vals,
-                            double* __restrict__ partial_max, int* __restrict__ flags) {
+                            double* __restrict__ partial_max, int* __restrict__ flags,
+                            double* __restrict__ partial_band) {
   __shared__ double red[WG];
+  __shared__ int64_t redb[WG];
   double m = 0.0;
+  int64_t band = 0;
   int f = 0;
   for (int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x; row < n; row += (int64_t)gridDim.x * WG) {
     const int64_t j0 = rowptr[row], j1 = rowptr[row + 1];
@@ -629,6 +654,8 @@ __global__ void k_csr_check(int64_t n, int64_t nnz, const int32_t* __restrict__ 
       if (c < 0 || c >= n) f |= 2;
       if (c <= prev) f |= 8;
       prev = c;
+      const int64_t d = (int64_t)c - row;
+      band = (d < 0 ? -d : d) > band ? (d < 0 ? -d : d) : band;
       const double v = vals[j];
       if (!isfinite(v)) f |= 4;
       s += fabs(v);
@@ -637,12 +664,19 @@ __global__ void k_csr_check(int64_t n, int64_t nnz, const int32_t* __restrict__ 
   }
   if (f) atomicOr(flags, f);
   red[threadIdx.x] = m;
+  redb[threadIdx.x] = band;
   __syncthreads();
   for (int o = WG / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    if (threadIdx.x < o) {
+      red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+      redb[threadIdx.x] = redb[threadIdx.x] > redb[threadIdx.x + o] ? redb[threadIdx.x] : redb[threadIdx.x + o];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial_max[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) {
+    partial_max[blockIdx.x] = red[0];
+    if (partial_band) partial_band[blockIdx.x] = (double)redb[0];
+  }
 }
 
 // Non-finite check of a dense block: sets flags bit 0.
@@ -699,10 +733,10 @@ void Kernels<T, PP>::dir(hipStream_t st, int nb, int64_t n, const T* X, const T*
 }
 template <typename T, int PP>
 void Kernels<T, PP>::spmm16(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind,
-                            const uint16_t* vals, const uint16_t* W, float* Z, const Scalars* sc, int mode) {
-  const int64_t ntiles = (n + TR - 1) / TR;
-  const int64_t grid = 8 * ((ntiles + 7) / 8);
-  k_spmm16<PP><<<dim3((unsigned)grid), dim3(WG), 0, st>>>(n, rowptr, colind, vals, W, Z, sc, mode);
+                            const uint16_t* vals, const uint16_t* W, float* Z, const Scalars* sc, int mode,
+                            int64_t plane_tiles) {
+  const int64_t grid = spmm_grid((n + TR - 1) / TR, plane_tiles);
+  k_spmm16<PP><<<dim3((unsigned)grid), dim3(WG), 0, st>>>(n, rowptr, colind, vals, W, Z, sc, mode, plane_tiles);
 }
 template <typename T, int PP>
 void Kernels<T, PP>::update(hipStream_t st, int nb, int64_t n, T* X, T* Y, const T* P0, const T* P1, const T* Z,
@@ -714,10 +748,10 @@ void Kernels<T, PP>::update(hipStream_t st, int nb, int64_t n, T* X, T* Y, const
 }
 template <typename T, int PP>
 void Kernels<T, PP>::spmm(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind, const T* vals,
-                          const T* W0, const T* W1, T* Z, const Scalars* sc, int mode) {
-  const int64_t ntiles = (n + TR - 1) / TR;
-  const int64_t grid = 8 * ((ntiles + 7) / 8);
-  k_spmm<T, PP><<<dim3((unsigned)grid), dim3(WG), 0, st>>>(n, rowptr, colind, vals, W0, W1, Z, sc, mode);
+                          const T* W0, const T* W1, T* Z, const Scalars* sc, int mode, int64_t plane_tiles) {
+  const int64_t grid = spmm_grid((n + TR - 1) / TR, plane_tiles);
+  k_spmm<T, PP><<<dim3((unsigned)grid), dim3(WG), 0, st>>>(n, rowptr, colind, vals, W0, W1, Z, sc, mode,
+                                                          plane_tiles);
 }
 template <typename T, int PP>
 void Kernels<T, PP>::gram(hipStream_t st, int nb, int64_t n, const T* A0, const T* A1, const T* B1, const T* B2,
@@ -774,8 +808,9 @@ void launch_to_bf16(hipStream_t st, int64_t count, const double* src, uint16_t* 
   hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count, src, dst, scale);
 }
 void launch_csr_check(hipStream_t st, int nb, int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colind,
-                      const double* vals, double* partial_max, int* flags) {
-  hipLaunchKernelGGL(k_csr_check, dim3(nb), dim3(WG), 0, st, n, nnz, rowptr, colind, vals, partial_max, flags);
+                      const double* vals, double* partial_max, int* flags, double* partial_band) {
+  hipLaunchKernelGGL(k_csr_check, dim3(nb), dim3(WG), 0, st, n, nnz, rowptr, colind, vals, partial_max, flags,
+                     partial_band);
 }
 void launch_finite(hipStream_t st, int64_t count, const double* x, int* flags) {
   hipLaunchKernelGGL(k_finite, dim3(1024), dim3(256), 0, st, count, x, flags);
