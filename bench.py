@@ -192,6 +192,9 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--switch-tol", type=float, default=1e-6)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--legs-only", action="store_true",
+                    help="skip the 3D Laplacian headline and run only the requested extra legs (for profiling); "
+                         "prints a JSON line with those legs only")
     ap.add_argument("--warm", action="store_true",
                     help="also run the learned warm-start leg (256 x 256 Schroedinger operators, 8 wells, p = 32: "
                          "training data from the method's own solves, training, held-out comparison; ~8 minutes)")
@@ -204,8 +207,11 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=32,
                     help="problems of the batch solved one by one on the plain float64 path")
     ap.add_argument("--profile-steps", type=int, default=0,
-                    help="short run for hardware-counter profiling: K float64 iterations without the graph, "
+                    help="short run for hardware-counter profiling: K iterations without the graph, "
                          "then a plain 1 GiB device copy (three times) as the counter calibration; no JSON")
+    ap.add_argument("--profile-matrix", choices=["laplace3d", "spiked"], default="laplace3d",
+                    help="matrix of the profiling run: the 3D Laplacian of --grid, or the random-sparse leg's matrix")
+    ap.add_argument("--profile-precision", choices=["fp64", "fp32", "bf16"], default="fp64")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -215,9 +221,14 @@ def main():
     from paper_2306_10379_amd import gsi, inputs
 
     N, p = args.grid, args.p
-    log(f"building 3D Laplacian {N}^3, p={p}")
-    A = inputs.laplacian_3d(N)
-    X0h = inputs.start_block(A.n, p, args.seed)
+    if args.profile_steps > 0 and args.profile_matrix == "spiked":
+        log("building the spiked sparse matrix n=2^22 for profiling")
+        A = inputs.spiked_sparse(1 << 22, 12, p, 7)
+        X0h = inputs.start_block(A.n, p, 8)
+    else:
+        log(f"building 3D Laplacian {N}^3, p={p}")
+        A = inputs.laplacian_3d(N)
+        X0h = inputs.start_block(A.n, p, args.seed)
     dev = torch.device("cuda:0")
     rowptr = torch.as_tensor(A.rowptr.astype(np.int32), device=dev)
     colind = torch.as_tensor(A.colind, device=dev)
@@ -227,7 +238,7 @@ def main():
 
     if args.profile_steps > 0:
         s = gsi.Solver((rowptr, colind, vals, A.n), X0, p, tol=0.0, max_iter=args.profile_steps + 5,
-                       use_graph=False)
+                       use_graph=False, precision=args.profile_precision, switch_tol=0.0)
         s.step(args.profile_steps)
         torch.cuda.synchronize()
         s.close()
@@ -236,7 +247,8 @@ def main():
         for _ in range(3):
             y.copy_(x)
         torch.cuda.synchronize()
-        log(f"profile run done: {args.profile_steps} iterations, 3 copies of 1 GiB")
+        log(f"profile run done: {args.profile_steps} iterations ({args.profile_matrix}, {args.profile_precision}), "
+            f"3 copies of 1 GiB")
         return
 
     def timed_solves(precision, steps, warmup):
@@ -256,6 +268,12 @@ def main():
         info = s.counters()
         ritz, res, rho, phi = s.residuals()
         return s, times, iters, info, ritz, rho
+
+    if args.legs_only:
+        out = {"batched": None if args.no_batched else batched_leg(args, gsi, inputs, torch),
+               "random_sparse": c3_leg(args, gsi, inputs, torch) if args.c3 else None}
+        print(json.dumps(out), flush=True)
+        return
 
     # plain float64 solve (the headline), then mixed precision
     s64, t64, it64, c64, ritz64, rho64 = timed_solves("fp64", args.steps, args.warmup)

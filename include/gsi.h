@@ -47,7 +47,7 @@ typedef enum {
   GSI_FP64 = 0,        /* every step in float64 */
   GSI_MIXED_FP32 = 1,  /* SpMM, Gram and update passes in float32 (float32 accumulation) with
                           float64 small solves, until rho <= switch_tol or rho stops halving
-                          for 200 iterations; then the float64 phase continues the
+                          for stall_window iterations; then the float64 phase continues the
                           conjugate-gradient recursion to tol */
   GSI_MIXED_BF16 = 2   /* as GSI_MIXED_FP32, but the iteration's SpMM reads bfloat16 matrix
                           values and a bfloat16 copy of P (written by the direction pass,
@@ -76,16 +76,18 @@ typedef struct {
   int32_t k_restart;    /* restart the CG direction every k_restart iterations (0 = never) */
   int32_t max_iter;     /* iteration cap (accepted steps) */
   double tol;           /* stop when rho = ||G||_F / (sqrt(p) ||A||_inf) <= tol */
-  double switch_tol;    /* GSI_MIXED_FP32: rho at which the float64 refinement phase starts */
+  double switch_tol;    /* mixed precision: rho at which the float64 refinement phase starts */
   int32_t check_every;  /* gsi_solve polls the convergence flag every this many iterations */
   int32_t use_graph;    /* capture the per-iteration launch sequence in a HIP graph */
   int32_t explicit_c;   /* 1: form C = X^T A X and W = X^T P_old by Gram passes in the retraction
                            pass; 0: carry them by the p x p recursion C <- M (C - mu (P^T Y +
                            Y^T P) + mu^2 P^T Z) M, W <- -mu M P^T P */
+  int32_t stall_window; /* mixed precision: the low-precision phase also ends when rho has not
+                           halved for this many iterations (its rounding floor); >= 1 */
 } gsi_options;
 
 /* Fill *opt with defaults: p=8, which=+1, RCG, FP64, recursion, no restart, max_iter=10000,
- * tol=1e-8, switch_tol=1e-5, check_every=25, use_graph=1, explicit_c=0. */
+ * tol=1e-8, switch_tol=1e-5, check_every=25, use_graph=1, explicit_c=0, stall_window=60. */
 void gsi_options_default(gsi_options* opt);
 
 /* Create a solver for A with options opt, starting block X0 (n x p float64, device; its
@@ -172,9 +174,9 @@ const char* gsi_last_error(gsi_handle h);
  * an atomic queue (largest n*p first) and runs the whole iteration of one problem (Sec. 5,
  * Algorithm 4, with the same readings as gsi_solve) with workgroup barriers only. Options
  * shared by all problems: which, method, precision, recompute_ax, k_restart, max_iter, tol,
- * switch_tol. GSI_FP64: float64 blocks throughout. GSI_MIXED_FP32: float32 blocks with
- * float64 p x p solves until rho <= max(switch_tol, tol) or until rho has not halved for 200
- * iterations, then the iterate, previous gradient and previous direction are widened to
+ * switch_tol, stall_window. GSI_FP64: float64 blocks throughout. GSI_MIXED_FP32: float32
+ * blocks with float64 p x p solves until rho <= max(switch_tol, tol) or until rho has not
+ * halved for stall_window iterations, then the iterate, previous gradient and previous direction are widened to
  * float64 and the iteration continues to tol without a restart. 1 <= p[i] <= 32, p[i] < n.
  * Arrays A, p, X0 are host arrays of count entries; the CSR arrays (float64 values) and
  * X0[i] (n x p float64, row-major) are device pointers owned by the caller and copied.

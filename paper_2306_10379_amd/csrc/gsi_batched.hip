@@ -1245,7 +1245,7 @@ gsi_status gsi_create_batched(gsi_batch_handle* out, int32_t count, const gsi_cs
   ctl.method = opt->method;
   ctl.k_restart = opt->k_restart;
   ctl.max_iter = opt->max_iter;
-  ctl.stall_window = 200;
+  ctl.stall_window = opt->stall_window > 0 ? opt->stall_window : 60;
   ctl.recompute_ax = opt->recompute_ax;
   ctl.mixed = b->mixed;
   ctl.tol = opt->tol;

@@ -447,10 +447,10 @@ gsi_status start(gsi_ctx* h, const double* X0) {
   if (h->mixed) {
     launch_pack<float>(h->st, h->n, h->p, h->PP, X0, h->e32.X, 1.0);
     GSI_TRY(cholqr2(h, h->e32));
-    // the float32 phase also ends when rho has not halved for 200 iterations (its rounding
-    // floor); the float64 phase then continues
+    // the low-precision phase also ends when rho has not halved for stall_window iterations
+    // (its rounding floor); the float64 phase then continues
     GSI_TRY(init_state(h, h->e32, h->opt.switch_tol > h->opt.tol ? h->opt.switch_tol : h->opt.tol,
-                       h->opt.max_iter, 0, nullptr, 200));
+                       h->opt.max_iter, 0, nullptr, h->opt.stall_window > 0 ? h->opt.stall_window : 60));
     h->phase = 1;
   } else {
     launch_pack<double>(h->st, h->n, h->p, h->PP, X0, h->e64.X, 1.0);
@@ -479,6 +479,7 @@ void gsi_options_default(gsi_options* o) {
   o->switch_tol = 1e-5;
   o->check_every = 25;
   o->use_graph = 1;
+  o->stall_window = 60;
 }
 
 const char* gsi_status_str(gsi_status s) {

@@ -37,7 +37,8 @@ class GsiOptions(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("which", ctypes.c_int32), ("method", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("recompute_ax", ctypes.c_int32), ("k_restart", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("switch_tol", ctypes.c_double),
-                ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("explicit_c", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("explicit_c", ctypes.c_int32),
+                ("stall_window", ctypes.c_int32)]
 
 
 _lib = None
