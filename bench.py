@@ -141,9 +141,18 @@ def batched_leg(args, gsi, inputs, torch):
                        f"wells), p U{{4..32}} smallest, rho <= {args.tol:g}, one persistent launch in a HIP graph",
            "problems": count, "sum_n": int(sum(A.n for A in mats)),
            "sum_np": int(sum(A.n * p for A, p in zip(mats, ps)))}
+    policy = None
     for prec in ("mixed", "fp64"):
         with gsi.BatchedSolver(mats, X0s, ps, which=-1, precision=prec, tol=args.tol, max_iter=30000,
                                switch_tol=1e-5) as b:
+            if args.tune and policy is None:
+                from paper_2306_10379_amd import tuning
+                policy, ttimes = tuning.tune(b, log=log)
+                res["tuning"] = {"best": list(policy),
+                                 "seconds": {",".join(map(str, k)): round(v, 3) for k, v in ttimes.items()},
+                                 "knobs": "tiles per member, recruits per check, iterations between checks"}
+            elif policy is not None:
+                b.set_tuning(*policy)
             times = []
             for i in range(2):
                 torch.cuda.synchronize()
@@ -192,6 +201,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--switch-tol", type=float, default=1e-6)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--tune", action="store_true",
+                    help="time the batched solve under candidate team policies first and use the fastest")
     ap.add_argument("--legs-only", action="store_true",
                     help="skip the 3D Laplacian headline and run only the requested extra legs (for profiling); "
                          "prints a JSON line with those legs only")

@@ -48,7 +48,11 @@ typedef enum {
   GSI_MIXED_FP32 = 1,  /* SpMM, Gram and update passes in float32 (float32 accumulation) with
                           float64 small solves, until rho <= switch_tol or rho stops halving
                           for stall_window iterations; then the float64 phase continues the
-                          conjugate-gradient recursion to tol */
+                          conjugate-gradient recursion to tol. Its SpMM reads float32 copies
+                          of A and P with float64 products and sums (the rounding of A and P
+                          enters the A X recursion at u32 times the step, which shrinks with
+                          the gradient); gsi_solve confirms convergence with A X and X^T A X
+                          formed in float64 before it returns */
   GSI_MIXED_BF16 = 2   /* as GSI_MIXED_FP32, but the iteration's SpMM reads bfloat16 matrix
                           values and a bfloat16 copy of P (written by the direction pass,
                           rounded to nearest even) with float32 accumulation and a float32
@@ -205,14 +209,21 @@ gsi_status gsi_batched_get_x(gsi_batch_handle h, int32_t i, double* X_out);
  * problem at the end (1 unless idle workgroups were recruited, see below). Host arrays of
  * count, each nullable. Syncs.
  *
- * Teams: once every problem has started, a problem of at least 32 row tiles of 64 rows
- * that is still running recruits idle workgroups every 32 iterations, up to 4 at a time
- * and up to 16 in all with at least 16 tiles each. The members split the tiles, add their partial
+ * Teams: once every problem has started, a running problem recruits idle workgroups by
+ * the team policy of gsi_batched_set_tuning (by default every 32 iterations, up to 4 at a
+ * time, up to 16 members with at least 16 row tiles of 64 rows each). The members split the tiles, add their partial
  * Grams and sums in member order and repeat the p x p work, so all hold the same state.
  * Float64 results of a problem that stayed with one workgroup repeat bit for bit; with a
  * team they depend on the team size, which depends on timing, and agree to rounding. */
 gsi_status gsi_batched_timeline(gsi_batch_handle h, double* begin_us, double* switch_us, double* end_us,
                                 int32_t* iters_low, int32_t* team);
+/* Team policy of the following solves (defaults 16, 4, 32): a problem recruits idle
+ * workgroups every check_every iterations, at most recruit_step at a time, up to one member
+ * per tiles_per_member row tiles of 64 rows (and at most 16 members). tiles_per_member >= 4,
+ * 1 <= recruit_step <= 15, check_every >= 1, else GSI_EINVAL. The values are what
+ * paper_2306_10379_amd/tuning.py measures and picks per batch shape. Syncs. */
+gsi_status gsi_batched_set_tuning(gsi_batch_handle h, int32_t tiles_per_member, int32_t recruit_step,
+                                  int32_t check_every);
 /* Per-problem time per pass of the last solve in microseconds: host array of count x
  * GSI_NPASS, entry [i * GSI_NPASS + GSI_PASS_*] (GSI_PASS_REFRESH also holds the Cholesky
  * QR of the start block and the first A X, GSI_PASS_SMALL the p x p work outside the

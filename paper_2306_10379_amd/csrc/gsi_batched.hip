@@ -32,9 +32,10 @@ namespace gsi {
 
 constexpr int NBLK = 7;      // X, Y, G0, G1, P0, P1, Z
 constexpr int TMAX = 16;     // largest team of workgroups on one problem
-constexpr int TPM = 16;      // fewest 64-row tiles per team member
-constexpr int ESC_EVERY = 32;  // iterations between checks for idle workgroups to recruit
-constexpr int GROW_STEP = 4;   // most workgroups recruited at one check
+constexpr int TPM_MIN = 4;   // fewest 64-row tiles per team member that storage is sized for
+// default team policy (gsi_batched_set_tuning changes it): fewest tiles per member,
+// workgroups recruited at one check, iterations between checks
+constexpr int TPM_DEF = 16, GROW_DEF = 4, ESC_DEF = 32;
 
 struct BatchProblem {
   int64_t n;
@@ -48,7 +49,8 @@ struct BatchProblem {
   double* xch;              // 2 x TMAX x (2 PP^2 + 8) exchange slots (tmax > 1 only)
   double nA;                // ||A||_inf
   double* ritz;             // p outputs (Ritz values of the operator solved)
-  int32_t tmax, team;       // largest team allowed / team size reached
+  int32_t tmax, team;       // largest team allowed this solve / team size reached
+  int32_t tcap, tiles;      // member storage allocated; row tiles
   int32_t iters, iters_low, status, restarts, null_steps, pad;
   double rho;
   int64_t t_begin, t_switch, t_end;  // device wall clock
@@ -73,6 +75,7 @@ struct BatchCtl {
   int32_t active;        // problems not finished
   int32_t abort;         // set on a team wait timeout: every workgroup leaves
   int32_t method, k_restart, max_iter, stall_window, recompute_ax, mixed, pad;
+  int32_t tpm, grow_step, esc_every, pad2;  // team policy
   double tol, switch_tol;
   int64_t timeout_ticks;  // longest wait at a team barrier (wall-clock ticks)
   const int32_t* order;   // stage-1 queue order (problem indices)
@@ -719,15 +722,15 @@ __device__ __noinline__ int solve_phase(BatchProblem& pr, BatchCtl* ctl, int idx
   const int k_first = join ? -1 : k;
   int k_check = join ? k : -1;
   for (;;) {
-    // every ESC_EVERY iterations, once the stage-1 queue has drained, the first member
+    // every esc_every iterations, once the stage-1 queue has drained, the first member
     // recruits idle workgroups; a team meets at a barrier to learn the outcome, then the
     // enlarged team meets the recruits, which copy the first member's p x p state
-    if (k % ESC_EVERY == 0 && k != k_check && tm.t < pr.tmax) {
+    if (k % ctl->esc_every == 0 && k != k_check && tm.t < pr.tmax) {
       k_check = k;
       if (threadIdx.x == 0 && tm.rank == 0) {
         int want = 0;
         if (ld_acq(&ctl->headA) >= ctl->count && !ld_acq(&ctl->abort)) {
-          const int room = pr.tmax - tm.t < GROW_STEP ? pr.tmax - tm.t : GROW_STEP;
+          const int room = pr.tmax - tm.t < ctl->grow_step ? pr.tmax - tm.t : ctl->grow_step;
           int cur = ld_acq(&ctl->idle);
           while (cur > 0) {
             const int w = cur < room ? cur : room;
@@ -1035,6 +1038,10 @@ __global__ __launch_bounds__(WG) void k_batched(BatchProblem* __restrict__ probs
     __syncthreads();
     if (idx < 0) return;
     BatchProblem pr = probs[idx];
+    {
+      const int cap = pr.tiles / ctl->tpm;
+      pr.tmax = cap < 1 ? 1 : (cap < pr.tcap ? cap : pr.tcap);
+    }
     int64_t tk[GSI_NPASS];
     for (int i = 0; i < GSI_NPASS; ++i) tk[i] = 0;
     if (rank > 0) {
@@ -1194,9 +1201,10 @@ gsi_status gsi_create_batched(gsi_batch_handle* out, int32_t count, const gsi_cs
       }
     }
     const int64_t nt = (n + TR - 1) / TR;
-    pr.tmax = (int)std::max<int64_t>(1, std::min<int64_t>(TMAX, nt / TPM));
-    pr.small = balloc<double>(b, (size_t)pr.tmax * S_COUNT * PP * PP, e);
-    if (pr.tmax > 1) pr.xch = balloc<double>(b, (size_t)2 * TMAX * (2 * PP * PP + 8), e);
+    pr.tiles = (int32_t)nt;
+    pr.tcap = (int)std::max<int64_t>(1, std::min<int64_t>(TMAX, nt / TPM_MIN));
+    pr.small = balloc<double>(b, (size_t)pr.tcap * S_COUNT * PP * PP, e);
+    if (pr.tcap > 1) pr.xch = balloc<double>(b, (size_t)2 * TMAX * (2 * PP * PP + 8), e);
     if (e != hipSuccess) { b->err = "allocation failed"; return GSI_ENOMEM; }
     if (e == hipSuccess) e = hipMemsetAsync(x0, 0, blk * sizeof(double), b->st);
     if (e == hipSuccess) e = hipMemcpyAsync(rp, A[i].rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, b->st);
@@ -1250,6 +1258,9 @@ gsi_status gsi_create_batched(gsi_batch_handle* out, int32_t count, const gsi_cs
   ctl.mixed = b->mixed;
   ctl.tol = opt->tol;
   ctl.switch_tol = opt->switch_tol;
+  ctl.tpm = TPM_DEF;
+  ctl.grow_step = GROW_DEF;
+  ctl.esc_every = ESC_DEF;
   ctl.order = dorder;
   ctl.qB = qB;
   ctl.readyB = readyB;
@@ -1335,6 +1346,22 @@ gsi_status gsi_batched_get_x(gsi_batch_handle b, int32_t i, double* X_out) {
   launch_unpack<double>(b->st, pr.n, pr.p, pr.PP, (const double*)pr.blk[1][0], X_out);
   hipError_t e = hipStreamSynchronize(b->st);
   if (e != hipSuccess) { b->err = std::string("get_x: ") + hipGetErrorString(e); return GSI_EDEVICE; }
+  return GSI_OK;
+}
+
+gsi_status gsi_batched_set_tuning(gsi_batch_handle b, int32_t tiles_per_member, int32_t recruit_step,
+                                  int32_t check_every) {
+  if (!b || tiles_per_member < TPM_MIN || recruit_step < 1 || recruit_step > TMAX - 1 || check_every < 1) {
+    if (b) b->err = "tuning: tiles_per_member >= 4, 1 <= recruit_step <= 15, check_every >= 1";
+    return GSI_EINVAL;
+  }
+  BatchCtl ctl;
+  hipError_t e = hipMemcpy(&ctl, b->dctl, sizeof(ctl), hipMemcpyDeviceToHost);
+  ctl.tpm = tiles_per_member;
+  ctl.grow_step = recruit_step;
+  ctl.esc_every = check_every;
+  if (e == hipSuccess) e = hipMemcpy(b->dctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice);
+  if (e != hipSuccess) { b->err = std::string("tuning: ") + hipGetErrorString(e); return GSI_EDEVICE; }
   return GSI_OK;
 }
 

@@ -55,6 +55,9 @@ struct Engine {
   T* vals = nullptr;
   uint16_t* vals16 = nullptr;  // bfloat16 values and bfloat16 copy of P (bfloat16 mode only)
   uint16_t* P16 = nullptr;
+  // float64 engine of a mixed solve: float32 values and a float32 copy of P for the SpMM
+  const float* vals32 = nullptr;
+  float* P32 = nullptr;
   double* small = nullptr;
   Scalars* sc = nullptr;
   hipGraph_t graph = nullptr;
@@ -275,7 +278,7 @@ void launch_iteration(gsi_ctx* h, Engine<T>& e, double* hist) {
     }
     {
       PassTimer t(h, GSI_PASS_DIR);
-      Kernels<T, PP>::dir(h->st, e.nb, e.n, e.X, e.G0, e.G1, e.P0, e.P1, e.small, e.sc, h->partials, e.P16);
+      Kernels<T, PP>::dir(h->st, e.nb, e.n, e.X, e.G0, e.G1, e.P0, e.P1, e.small, e.sc, h->partials, e.P16, e.P32);
     }
     reduce(h, e.nb, P2 + 1, P2 + 1, e.sc, 1);
     {
@@ -303,7 +306,10 @@ void launch_iteration(gsi_ctx* h, Engine<T>& e, double* hist) {
         else
           Kernels<T, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.P0, e.P1, e.Z, e.sc, 1, h->plane_tiles);
       } else {
-        Kernels<T, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.P0, e.P1, e.Z, e.sc, 1, h->plane_tiles);
+        if (e.P32)
+          Kernels<T, PP>::spmm_fin(h->st, e.n, h->rowptr, h->colind, e.vals32, e.P32, e.Z, e.sc, 1, h->plane_tiles);
+        else
+          Kernels<T, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.P0, e.P1, e.Z, e.sc, 1, h->plane_tiles);
       }
     }
     {
@@ -375,7 +381,8 @@ void reorthonormalize(gsi_ctx* h, Engine<T>& e) {
 }
 
 template <typename T>
-gsi_status run_until_done(gsi_ctx* h, Engine<T>& e, double* hist, Scalars* out, bool reorth = false) {
+gsi_status run_until_done(gsi_ctx* h, Engine<T>& e, double* hist, Scalars* out, bool reorth = false,
+                          bool verify = false) {
   // in timing mode poll every iteration so that no launch after convergence is timed
   const int every = h->timing ? 1 : (h->opt.check_every > 0 ? h->opt.check_every : 25);
   for (;;) {
@@ -383,6 +390,21 @@ gsi_status run_until_done(gsi_ctx* h, Engine<T>& e, double* hist, Scalars* out, 
     GSI_TRY(hip_check(h, hipMemcpyAsync(out, e.sc, sizeof(Scalars), hipMemcpyDeviceToHost, h->st), "poll"));
     GSI_TRY(hip_check(h, hipStreamSynchronize(h->st), "iterate"));
     if (h->timing) collect_times(h);
+    if (out->done == 1 && verify) {
+      // the AX recursion used float32-input SpMMs: confirm with A X and C in float64 and
+      // let the next gradient pass test rho again (once; max_iter or a breakdown end at once)
+      verify = false;
+      dispatch_pp<T>(e.PP, [&](auto PPc) {
+        constexpr int PP = decltype(PPc)::value;
+        Kernels<T, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.X, e.X, e.Y, e.sc, 0, h->plane_tiles);
+        Kernels<T, PP>::gram(h->st, e.nb, e.n, e.X, e.X, e.Y, nullptr, e.sc, 0, h->partials);
+        reduce(h, e.nb, (int64_t)PP * PP, (int64_t)PP * PP, e.sc, 0);
+        launch_set_sym(h->st, PP, h->red, e.small + S_C * PP * PP);
+      });
+      out->done = 0;
+      GSI_TRY(hip_check(h, hipMemcpyAsync(e.sc, out, sizeof(Scalars), hipMemcpyHostToDevice, h->st), "resume"));
+      continue;
+    }
     if (out->done) return GSI_OK;
     if (reorth) reorthonormalize(h, e);
   }
@@ -434,6 +456,10 @@ gsi_status switch_to_fp64(gsi_ctx* h) {
                                         hipMemcpyDeviceToDevice, h->st),
                       "carry W"));
   }
+  // the float64 phase's SpMM reads float32 copies of A and P (the float32 blocks are free now)
+  h->e64.vals32 = h->e32.vals;
+  h->e64.P32 = h->e32.Z;
+  h->e64.destroy_graph();
   h->phase = 0;
   return hip_check(h, hipStreamSynchronize(h->st), "switch");
 }
@@ -442,6 +468,8 @@ gsi_status start(gsi_ctx* h, const double* X0) {
   // pack X0 into the active engine, orthonormalize, form A X and reset the state
   h->e64.destroy_graph();
   h->e32.destroy_graph();
+  h->e64.vals32 = nullptr;
+  h->e64.P32 = nullptr;
   h->low_iters = h->low_spmm = h->low_restarts = h->low_refresh = h->low_null = h->low_sweeps = 0;
   h->hist_off = 0;
   if (h->mixed) {
@@ -636,7 +664,7 @@ gsi_status gsi_solve(gsi_handle h, int32_t* iters_out) {
     GSI_TRY(run_until_done(h, h->e32, h->hist, &s, true));
     GSI_TRY(switch_to_fp64(h));
   }
-  GSI_TRY(run_until_done(h, h->e64, h->hist + (size_t)h->hist_off * H_FIELDS, &s));
+  GSI_TRY(run_until_done(h, h->e64, h->hist + (size_t)h->hist_off * H_FIELDS, &s, false, h->e64.P32 != nullptr));
   if (iters_out) *iters_out = s.k;
   if (s.done == 1) return GSI_OK;
   if (s.done == 2) return fail(h, GSI_NOT_CONVERGED, "max_iter reached");

@@ -19,9 +19,10 @@ struct Kernels {
   static hipError_t init();
   static void grad(hipStream_t st, int nb, int64_t n, const T* X, const T* Y, T* G0, T* G1, const double* small,
                    const Scalars* sc, double* partials);
-  // P16 (nullable): bfloat16 copy of P written beside it
+  // P16 / P32 (nullable): bfloat16 / float32 copy of P written beside it
   static void dir(hipStream_t st, int nb, int64_t n, const T* X, const T* G0, const T* G1, T* P0, T* P1,
-                  const double* small, const Scalars* sc, double* partials, uint16_t* P16 = nullptr);
+                  const double* small, const Scalars* sc, double* partials, uint16_t* P16 = nullptr,
+                  float* P32 = nullptr);
   static void update(hipStream_t st, int nb, int64_t n, T* X, T* Y, const T* P0, const T* P1, const T* Z,
                      const double* small, const Scalars* sc, double* partials, bool grams);
   // plane_tiles > 0: banded tile order (see spmm_tile in gsi_kernels.hip); 0: one slab per XCD
@@ -34,6 +35,9 @@ struct Kernels {
   // Z = A W with bfloat16 values and W, float32 accumulation and output
   static void spmm16(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind, const uint16_t* vals,
                      const uint16_t* W, float* Z, const Scalars* sc, int mode, int64_t plane_tiles = 0);
+  // Z (float64) = A W from float32 values and W, float64 products and accumulation
+  static void spmm_fin(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind, const float* vals,
+                       const float* W, double* Z, const Scalars* sc, int mode, int64_t plane_tiles = 0);
   static void colres(hipStream_t st, int nb, int64_t n, const T* X, const T* Y, const double* theta,
                      double* partials);
 };

@@ -108,7 +108,8 @@ template <typename T, int PP>
 __global__ __launch_bounds__(WG) void k_dir(int64_t n, const T* __restrict__ X, const T* __restrict__ G0,
                                             const T* __restrict__ G1, T* __restrict__ P0, T* __restrict__ P1,
                                             const double* __restrict__ small, const Scalars* __restrict__ sc,
-                                            double* __restrict__ partials, uint16_t* __restrict__ P16) {
+                                            double* __restrict__ partials, uint16_t* __restrict__ P16,
+                                            float* __restrict__ P32) {
   if (sc->done) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* sK = reinterpret_cast<T*>(lds_raw);
@@ -160,6 +161,17 @@ __global__ __launch_bounds__(WG) void k_dir(int64_t n, const T* __restrict__ X, 
         if (row < n)
 #pragma unroll
           for (int cb = 0; cb < PP / 16; ++cb) gst(P16 + row * PP + 16 * cb + c, bf16_round((float)p[cb][r]));
+      }
+    }
+    if (P32) {
+      // float32 copy of P for the float32-input SpMM of a mixed solve's float64 phase
+      const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = row0 + rowof<T>(g, r);
+        if (row < n)
+#pragma unroll
+          for (int cb = 0; cb < PP / 16; ++cb) gst(P32 + row * PP + 16 * cb + c, (float)p[cb][r]);
       }
     }
 #pragma unroll
@@ -412,6 +424,52 @@ __global__ __launch_bounds__(WG) void k_spmm16(int64_t n, const int32_t* __restr
     float* zr = Z + row * PP + EPL * lane;
     *reinterpret_cast<float4*>(zr) = make_float4(acc[0], acc[1], acc[2], acc[3]);
     *reinterpret_cast<float4*>(zr + 4) = make_float4(acc[4], acc[5], acc[6], acc[7]);
+  }
+}
+
+// Z (float64) = A W from float32 values and a float32 W: each product of two float32 numbers
+// is exact in float64 and the sum is float64, so the only error is the rounding of A and W
+// to float32 (half the gather bytes of float64). Same tiling and modes as k_spmm.
+template <int PP>
+__global__ __launch_bounds__(WG) void k_spmm_fin(int64_t n, const int32_t* __restrict__ rowptr,
+                                                 const int32_t* __restrict__ colind, const float* __restrict__ vals,
+                                                 const float* __restrict__ W, double* __restrict__ Z,
+                                                 const Scalars* __restrict__ sc, int mode, int64_t plane_tiles) {
+  if (spmm_skip(sc, mode)) return;
+  constexpr int EPL = 4;
+  constexpr int LPR = PP / EPL;  // lanes per row
+  constexpr int RPB = WG / LPR;  // rows per block pass
+  constexpr int U = 8;           // nonzeros per batch
+  const int64_t ntiles = (n + TR - 1) / TR;
+  const int64_t t = spmm_tile(ntiles, plane_tiles);
+  if (t >= ntiles) return;
+  const int sub = threadIdx.x / LPR, lane = threadIdx.x % LPR;
+#pragma unroll
+  for (int pass = 0; pass < TR / RPB; ++pass) {
+    const int64_t row = t * TR + pass * RPB + sub;
+    if (row >= n) continue;
+    double acc[EPL] = {0.0, 0.0, 0.0, 0.0};
+    const int32_t j0 = rowptr[row], j1 = rowptr[row + 1];
+    for (int32_t j = j0; j < j1; j += U) {
+      int32_t col[U];
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool ok = j + u < j1;
+        col[u] = ok ? colind[j + u] : 0;
+        v[u] = ok ? (double)vals[j + u] : 0.0;
+      }
+      f4 x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) x[u] = gld(reinterpret_cast<const f4*>(W + (int64_t)col[u] * PP + EPL * lane));
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) acc[e] += v[u] * (double)x[u][e];
+    }
+    double* zr = Z + row * PP + EPL * lane;
+    *reinterpret_cast<double2*>(zr) = make_double2(acc[0], acc[1]);
+    *reinterpret_cast<double2*>(zr + 2) = make_double2(acc[2], acc[3]);
   }
 }
 
@@ -728,8 +786,15 @@ void Kernels<T, PP>::grad(hipStream_t st, int nb, int64_t n, const T* X, const T
 }
 template <typename T, int PP>
 void Kernels<T, PP>::dir(hipStream_t st, int nb, int64_t n, const T* X, const T* G0, const T* G1, T* P0, T* P1,
-                         const double* small, const Scalars* sc, double* partials, uint16_t* P16) {
-  k_dir<T, PP><<<nb, WG, lds_bytes<T, PP>(Pass::Dir), st>>>(n, X, G0, G1, P0, P1, small, sc, partials, P16);
+                         const double* small, const Scalars* sc, double* partials, uint16_t* P16, float* P32) {
+  k_dir<T, PP><<<nb, WG, lds_bytes<T, PP>(Pass::Dir), st>>>(n, X, G0, G1, P0, P1, small, sc, partials, P16, P32);
+}
+template <typename T, int PP>
+void Kernels<T, PP>::spmm_fin(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind,
+                              const float* vals, const float* W, double* Z, const Scalars* sc, int mode,
+                              int64_t plane_tiles) {
+  const int64_t grid = spmm_grid((n + TR - 1) / TR, plane_tiles);
+  k_spmm_fin<PP><<<dim3((unsigned)grid), dim3(WG), 0, st>>>(n, rowptr, colind, vals, W, Z, sc, mode, plane_tiles);
 }
 template <typename T, int PP>
 void Kernels<T, PP>::spmm16(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind,

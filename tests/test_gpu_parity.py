@@ -105,6 +105,14 @@ def test_ragged_shapes_smallest_and_largest(n, p, seed):
         assert O.principal_angles(X, ref.X).max() <= 1e-7
 
 
+def _true_rho(A, X):
+    """rho of a basis recomputed from scratch in float64: ||A X - X sym(X^T A X)||_F / (sqrt(p) ||A||_inf)."""
+    S = A.to_scipy()
+    AX = S @ X
+    C = X.T @ AX
+    return np.linalg.norm(AX - X @ (0.5 * (C + C.T))) / (np.sqrt(X.shape[1]) * O.norm_inf(S))
+
+
 def test_mixed_precision_reaches_fp64_accuracy():
     A = I.laplacian_2d(32)
     lam = laplacian_spectrum(32, 32)[:8]
@@ -112,6 +120,9 @@ def test_mixed_precision_reaches_fp64_accuracy():
     ref, r, X, hist = _solve_both(A, 8, 0, precision="mixed", switch_tol=1e-5)
     assert r.status == 0
     assert r.counters["low_iters"] > 0
+    # the float64 phase's SpMM reads float32 copies; the residual of the returned basis,
+    # recomputed here in float64, meets the tolerance
+    assert _true_rho(A, X) <= 1.05e-10
     assert np.max(np.abs(r.ritz - lam) / lam) <= 1e-10
     # both bases lie within Davis-Kahan distance ||G||_F / delta of the exact eigenspace
     delta = laplacian_spectrum(32, 32)[7] - laplacian_spectrum(32, 32)[8]
@@ -301,9 +312,35 @@ def test_mixed_bf16_reaches_fp64_accuracy():
     ref, r, X, hist = _solve_both(A, 16, 6, precision="bf16", switch_tol=1e-4)
     assert r.status == 0
     assert r.counters["low_iters"] > 0
+    assert _true_rho(A, X) <= 1.05e-10
     assert np.max(np.abs(r.ritz - ref.theta) / np.abs(ref.theta)) <= 1e-10
     w = np.sort(scipy.sparse.linalg.eigsh(A.to_scipy(), k=18, which="LA", tol=1e-13)[0])[::-1]
     delta = w[15] - w[16]
     nA = O.norm_inf(A.to_scipy())
     bound = (r.rho + ref.rho[-1]) * np.sqrt(16) * nA / delta
     assert O.principal_angles(X, ref.X).max() <= max(bound, 1e-10)
+
+
+def test_batched_team_policy_setter_and_results_unchanged():
+    """The team policy changes who works on a problem, not what is computed: a batch with a
+    team-forming problem gives oracle-equal Ritz values under two policies; invalid policies
+    are rejected."""
+    gsi = _gsi()
+    mats, X0s, ps = _schrodinger_batch(3, 13, nmin=10, nmax=14, pmin=3, pmax=6)
+    big = I.schrodinger_2d(72, I.random_wells(13_777, count=(4, 6)))
+    mats.insert(0, big)
+    ps.insert(0, 12)
+    X0s.insert(0, I.start_block(big.n, 12, 13_778))
+    ref = O.rcg(big, X0s[0], tol=1e-10, which=-1, max_iter=20000)
+    with gsi.BatchedSolver(mats, X0s, ps, which=-1, precision="fp64", tol=1e-10, max_iter=20000) as b:
+        with pytest.raises(gsi.GsiError):
+            b.set_tuning(2, 4, 32)
+        for policy in [(4, 8, 8), (32, 1, 64)]:
+            b.set_tuning(*policy)
+            _, iters, status = b.solve()
+            *_, team = b.timeline()
+            print(f"policy {policy}: team {team}", flush=True)
+            assert np.all(status == 1)
+            assert team[0] <= max(1, min(16, (big.n + 63) // 64 // policy[0]))
+            ritz, rho, _ = b.results(0)
+            assert np.max(np.abs(-ritz - ref.theta) / np.abs(ref.theta)) <= 1e-10
