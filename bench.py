@@ -130,6 +130,45 @@ def c3_leg(args, gsi, inputs, torch):
     return res
 
 
+def laplacian3d_top(N, count):
+    """The `count` largest eigenvalues of the 7-point Dirichlet Laplacian on N^3, descending
+    (sums of three 1D eigenvalues 4 sin^2(k pi / (2 (N + 1))))."""
+    k = np.arange(1, N + 1)
+    l1 = np.sort(4.0 * np.sin(k * np.pi / (2.0 * (N + 1))) ** 2)[::-1]
+    t = l1[:min(N, 16)]
+    lam = np.sort((t[:, None, None] + t[None, :, None] + t[None, None, :]).ravel())[::-1]
+    return lam[:count], 3.0 * l1[-1]
+
+
+def si_leg(args, gsi, torch, rowptr, colind, vals, n, X0, ritz_ref, rcg_spmm):
+    """Chebyshev-filtered subspace iteration (Algorithm 1 with the filter of eq. optimal_poly)
+    on the same operator and start block as the RCG headline, with the filter interval from
+    the closed-form spectrum: [lambda_min, the largest eigenvalue below lambda_p] (lambda_p
+    is degenerate at p = 64, so the cut sits below its cluster), normalized at lambda_1.
+    Exact bounds are the best case for the filter; a practical run would estimate them."""
+    N, p = args.grid, args.p
+    lam, lmin = laplacian3d_top(N, p + 16)
+    lp = lam[p - 1]
+    hi = float(lam[lam < lp - 1e-12 * lp][0])
+    out = {"filter_interval": [float(lmin), hi], "normalized_at": float(lam[0])}
+    for d in args.si_degrees:
+        s = gsi.Solver((rowptr, colind, vals, n), X0, p, method="si", tol=args.tol, max_iter=5000,
+                       cheb_degree=d, cheb_lo=float(lmin), cheb_hi=hi, cheb_top=float(lam[0]))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        status, iters = s.solve()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        c = s.counters()
+        ritz, res, rho, phi = s.residuals()
+        log(f"si chebyshev degree {d}: {dt:.2f} s, {iters} outer iterations, {c['spmm']} SpMMs, status {status}")
+        out[f"degree_{d}"] = {"s": round(dt, 3), "outer_iters": iters, "spmm": c["spmm"], "status": status,
+                              "spmm_vs_rcg": round(c["spmm"] / max(rcg_spmm, 1), 3), "rho": rho,
+                              "ritz_rel_err_vs_rcg": float(np.max(np.abs(ritz - ritz_ref) / np.abs(ritz_ref)))}
+        s.close()
+    return out
+
+
 def batched_leg(args, gsi, inputs, torch):
     """Many small problems in one persistent launch: the whole batch to rho <= tol with float32
     blocks then float64 refinement, and with float64 blocks, against the plain float64 path
@@ -212,6 +251,9 @@ def main():
     ap.add_argument("--c3", action="store_true",
                     help="also run the random-sparse leg: spiked sparse matrix n = 2^22, 24 random nonzeros per "
                          "row, p = 64 (float64, float32-mixed and bfloat16-mixed solves, SpMM rates; ~4 minutes)")
+    ap.add_argument("--no-si", action="store_true",
+                    help="skip the Chebyshev-filtered subspace iteration on the headline workload")
+    ap.add_argument("--si-degrees", type=int, nargs="*", default=[64, 128])
     ap.add_argument("--warm-train", type=int, default=144)
     ap.add_argument("--warm-test", type=int, default=24)
     ap.add_argument("--batch", type=int, default=512)
@@ -322,6 +364,10 @@ def main():
                  "ritz_rel_err_vs_fp64": float(np.max(np.abs(ritz32 - ritz64) / np.abs(ritz64))),
                  "rho": rho32}
 
+    si = None
+    if not args.no_si and args.si_degrees:
+        si = si_leg(args, gsi, torch, rowptr, colind, vals, A.n, X0, ritz64, c64["spmm"])
+
     batched = None if args.no_batched else batched_leg(args, gsi, inputs, torch)
     c3 = c3_leg(args, gsi, inputs, torch) if args.c3 else None
     warm = None
@@ -363,6 +409,7 @@ def main():
                     for k, v in kern.items()},
         "pass_share": {k: round(v[0] / total_ms, 4) for k, v in pt.items() if total_ms > 0},
         "mixed_fp32": mixed,
+        "si_chebyshev": si,
         "batched": batched,
         "random_sparse": c3,
         "warm_start": warm,

@@ -41,7 +41,16 @@ typedef enum {
   GSI_EUNSUPPORTED = 6    /* option combination not built (e.g. p above the supported maximum) */
 } gsi_status;
 
-typedef enum { GSI_RSD = 1, GSI_RCG = 2 } gsi_method;
+typedef enum {
+  GSI_RSD = 1,  /* Riemannian steepest descent with exact line search (Algorithm 2) */
+  GSI_RCG = 2,  /* Riemannian nonlinear CG, Polak-Ribiere, exact line search (Algorithm 4) */
+  GSI_SI = 3    /* subspace iteration with a polynomial filter (Algorithm 1): per iteration
+                   X_hat = p_d(A) X, Cholesky QR, Rayleigh-Ritz X <- Q U, A X <- (A Q) U; the
+                   filter is the monomial (cheb_degree 0) or the Chebyshev polynomial of
+                   eq. optimal_poly over [cheb_lo, cheb_hi] normalized at cheb_top. Float64,
+                   stopping test as for the other methods; gsi_step runs outer iterations
+                   synchronously */
+} gsi_method;
 
 typedef enum {
   GSI_FP64 = 0,        /* every step in float64 */
@@ -88,10 +97,18 @@ typedef struct {
                            Y^T P) + mu^2 P^T Z) M, W <- -mu M P^T P */
   int32_t stall_window; /* mixed precision: the low-precision phase also ends when rho has not
                            halved for this many iterations (its rounding floor); >= 1 */
+  int32_t cheb_degree;  /* GSI_SI: 0 monomial filter p(t) = t; d >= 1 Chebyshev filter of degree d
+                           (d products with A per outer iteration) */
+  double cheb_lo;       /* GSI_SI with d >= 1: interval [cheb_lo, cheb_hi] of the unwanted
+                           eigenvalues of the operator solved (-A when which = -1), i.e.
+                           [lambda_n, lambda_{p+1}] of eq. optimal_poly, and an estimate */
+  double cheb_hi;       /* cheb_top > cheb_hi of its largest eigenvalue (the normalization */
+  double cheb_top;      /* point that keeps the filtered block bounded) */
 } gsi_options;
 
 /* Fill *opt with defaults: p=8, which=+1, RCG, FP64, recursion, no restart, max_iter=10000,
- * tol=1e-8, switch_tol=1e-5, check_every=25, use_graph=1, explicit_c=0, stall_window=60. */
+ * tol=1e-8, switch_tol=1e-5, check_every=25, use_graph=1, explicit_c=0, stall_window=60,
+ * cheb_degree=0. */
 void gsi_options_default(gsi_options* opt);
 
 /* Create a solver for A with options opt, starting block X0 (n x p float64, device; its
@@ -123,6 +140,15 @@ gsi_status gsi_get_x(gsi_handle h, double* X_out);
 /* Replace the iterate by span(X0) (n x p float64 device block; orthonormalized inside) and
  * reset the iteration state: a warm start (Sec. 2.3: restarting from a previous subspace). */
 gsi_status gsi_set_x0(gsi_handle h, const double* X0);
+
+/* Subspace tracking (Sec. 1 and 2.3: sequences of related eigenproblems, where a method that
+ * can start from the previous subspace pays only for the change): replace the matrix values
+ * by vals (device array of nnz float64 in the CSR order and sparsity pattern given at
+ * creation), recompute ||A||_inf, and restart the iteration from the current basis, which
+ * stays the iterate (orthonormalized again; the solver state is reset as by gsi_set_x0).
+ * Errors: GSI_EINVAL (null), GSI_BREAKDOWN (a non-finite value; the handle keeps the old
+ * values), GSI_EDEVICE. */
+gsi_status gsi_set_values(gsi_handle h, const double* vals);
 
 /* Z = A_op W for the handle's operator (A, or -A when which = -1), W and Z n x p float64
  * device blocks. The same SpMM kernel the iteration uses. Asynchronous. */

@@ -355,6 +355,63 @@ def subspace_iteration(A, X0, tol: float = 1e-10, max_iter: int = 100000, which:
     return _finish(A_op, X, which, res)
 
 
+def chebyshev_filter(A_op, X: np.ndarray, Y: np.ndarray, degree: int, lo: float, hi: float, top: float) -> np.ndarray:
+    """p_d(A) X with p_d(t) = C_d((t - c)/h) / C_d((top - c)/h), c = (lo + hi)/2, h = (hi - lo)/2
+    (Sec. 2.3, eq. optimal_poly: the unwanted eigenvalues [lambda_n, lambda_{p+1}] of the
+    operator map to [-1, 1]; the division by the value at `top`, an estimate of lambda_1,
+    keeps the block bounded). Three-term recurrence of the Chebyshev polynomials with that
+    normalization carried step by step (Zhou and Saad 2007); Y = A X is given."""
+    c, h = 0.5 * (lo + hi), 0.5 * (hi - lo)
+    sigma1 = h / (top - c)
+    prev = X
+    cur = (sigma1 / h) * (Y - c * X)
+    sigma = sigma1
+    for _ in range(2, degree + 1):
+        sigma_new = 1.0 / (2.0 / sigma1 - sigma)
+        nxt = (2.0 * sigma_new / h) * (A_op @ cur - c * cur) - sigma * sigma_new * prev
+        prev, cur, sigma = cur, nxt, sigma_new
+    return cur
+
+
+def chebyshev_si(A, X0, degree: int, lo: float, hi: float, top: float, tol: float = 1e-10,
+                 max_iter: int = 100000, which: int = 1) -> SolveResult:
+    """Subspace iteration with the Chebyshev filter of eq. optimal_poly (Algorithm 1): filter,
+    QR, Rayleigh-Ritz C = Q^T A Q = U Lambda U^T, X <- Q U, A X <- (A Q) U; stop on
+    ||(I - X X^T) A X||. lo, hi, top refer to the operator solved (-A when which = -1).
+    degree 1 is the shifted monomial filter."""
+    A = as_operator(A)
+    A_op = A if which > 0 else -A
+    X = orthonormalize(np.asarray(X0, dtype=np.float64))
+    n, p = X.shape
+    nA = norm_inf(A)
+    res = SolveResult(X=X, theta=np.zeros(p), iters=0, converged=False)
+    Y = A_op @ X
+    res.spmm += 1
+    k = 0
+    while True:
+        G, C = gradient(X, Y)
+        rho = np.linalg.norm(G) / (np.sqrt(p) * nA)
+        res.rho.append(rho)
+        res.phi.append(-0.5 * float(np.trace(C)))
+        if rho <= tol:
+            res.converged = True
+            break
+        if k >= max_iter:
+            break
+        Xh = chebyshev_filter(A_op, X, Y, degree, lo, hi, top)
+        res.spmm += degree - 1
+        Q = orthonormalize(Xh)
+        AQ = A_op @ Q
+        res.spmm += 1
+        w, U = np.linalg.eigh(sym(Q.T @ AQ))
+        U = U[:, ::-1]
+        X = Q @ U
+        Y = AQ @ U
+        k += 1
+    res.iters = k
+    return _finish(A_op, X, which, res)
+
+
 def cholesky_qr2(X: np.ndarray) -> np.ndarray:
     """Two passes of Cholesky QR: R = chol(X^T X), X <- X R^{-1} (used to orthonormalize a
     drifted or warm-started block; the result spans the same space)."""
@@ -362,3 +419,17 @@ def cholesky_qr2(X: np.ndarray) -> np.ndarray:
         R = np.linalg.cholesky(sym(X.T @ X)).T
         X = np.linalg.solve(R.T, X.T).T
     return X
+
+
+def track(mats, X0, tol: float = 1e-10, max_iter: int = 10000, which: int = 1, method: str = "rcg"):
+    """Subspace tracking over a sequence of matrices A_0, A_1, ... (Sec. 1 and 2.3: related
+    eigenproblems solved one after another, each started from the previous converged
+    subspace). A_0 starts from X0; A_t from the basis returned for A_{t-1}. Returns the list
+    of SolveResults."""
+    out = []
+    X = np.asarray(X0, dtype=np.float64)
+    for A in mats:
+        r = rcg(A, X, tol=tol, max_iter=max_iter, method=method, which=which)
+        out.append(r)
+        X = r.X
+    return out

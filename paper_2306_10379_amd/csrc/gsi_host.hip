@@ -111,6 +111,9 @@ struct gsi_ctx {
   Engine<float> e32;
   bool mixed = false;
   bool bf16 = false;      // mixed phase with bfloat16 SpMM values and inputs
+  // subspace iteration (GSI_SI): outer iterations, products with A, rho history
+  int si_k = 0, si_spmm = 0, si_done = 0;
+  std::vector<double> si_rho;
   int phase = 0;          // 0: float64 engine active; 1: float32 engine active (mixed mode)
   int low_iters = 0;      // accepted iterations of the float32 phase
   int low_spmm = 0, low_restarts = 0, low_refresh = 0, low_null = 0, low_sweeps = 0;
@@ -464,12 +467,130 @@ gsi_status switch_to_fp64(gsi_ctx* h) {
   return hip_check(h, hipStreamSynchronize(h->st), "switch");
 }
 
+// Two Cholesky QR passes on an arbitrary block of the float64 engine.
+gsi_status cholqr2_buf(gsi_ctx* h, Engine<double>& e, double* B) {
+  for (int pass = 0; pass < 2; ++pass) {
+    dispatch_pp<double>(e.PP, [&](auto PPc) {
+      constexpr int PP = decltype(PPc)::value;
+      Kernels<double, PP>::gram(h->st, e.nb, e.n, B, B, B, nullptr, e.sc, 0, h->partials);
+      reduce(h, e.nb, (int64_t)PP * PP, (int64_t)PP * PP, e.sc, 0);
+      Small::chol_inv(h->st, PP, e.p, h->red, e.small, h->flags);
+      Kernels<double, PP>::product(h->st, e.nb, e.n, B, B, e.small + S_M * PP * PP);
+    });
+  }
+  int flag = 0;
+  GSI_TRY(hip_check(h, hipMemcpyAsync(&flag, h->flags, sizeof(int), hipMemcpyDeviceToHost, h->st), "copy flag"));
+  GSI_TRY(hip_check(h, hipStreamSynchronize(h->st), "cholqr2"));
+  if (flag) {
+    (void)hipMemsetAsync(h->flags, 0, sizeof(int), h->st);
+    return fail(h, GSI_BREAKDOWN, "Cholesky QR of the filtered block: rank deficient or not finite");
+  }
+  return GSI_OK;
+}
+
+// Rayleigh-Ritz of (Q, AQ) into X = Q U, Y = (A Q) U with Ritz values in dvec, then the
+// residual rho = ||Y - X diag(theta)||_F / (sqrt(p) ||A||_inf) (Algorithm 1 steps 2, 6-7).
+gsi_status si_ritz(gsi_ctx* h, const double* Q, double* AQ, double* rho) {
+  Engine<double>& e = h->e64;
+  double* theta = h->dvec;
+  dispatch_pp<double>(e.PP, [&](auto PPc) {
+    constexpr int PP = decltype(PPc)::value;
+    Kernels<double, PP>::gram(h->st, e.nb, e.n, Q, Q, AQ, nullptr, e.sc, 0, h->partials);
+    reduce(h, e.nb, (int64_t)PP * PP, (int64_t)PP * PP, e.sc, 0);
+    Small::ritz(h->st, PP, e.p, h->red, e.small, theta);
+    Kernels<double, PP>::product(h->st, e.nb, e.n, Q, e.X, e.small + S_M * PP * PP);
+    Kernels<double, PP>::product(h->st, e.nb, e.n, AQ, e.Y, e.small + S_M * PP * PP);
+    Kernels<double, PP>::colres(h->st, e.nb, e.n, e.X, e.Y, theta, h->partials);
+    reduce(h, e.nb, PP, PP, e.sc, 0);
+  });
+  std::vector<double> cr(h->PP);
+  GSI_TRY(hip_check(h, hipMemcpyAsync(cr.data(), h->red, sizeof(double) * h->PP, hipMemcpyDeviceToHost, h->st),
+                    "si residual"));
+  GSI_TRY(hip_check(h, hipStreamSynchronize(h->st), "si ritz"));
+  double sq = 0.0;
+  for (int i = 0; i < h->p; ++i) sq += cr[i];
+  *rho = sqrt(sq > 0.0 ? sq : 0.0) / (sqrt((double)h->p) * h->nA);
+  return GSI_OK;
+}
+
+// Up to `count` outer iterations of subspace iteration with a polynomial filter (Algorithm 1)
+// from the current X (orthonormal), Y = A X. The Chebyshev filter runs the three-term
+// recurrence of C_d((t - c)/h) normalized at cheb_top (Zhou and Saad 2007) with each step
+// fused into an SpMM; the first step reuses Y = A X.
+gsi_status si_iterate(gsi_ctx* h, int count) {
+  Engine<double>& e = h->e64;
+  const int64_t rows = (h->n + TR - 1) / TR * TR;
+  const int64_t nel = rows * h->PP;
+  const int d = h->opt.cheb_degree;
+  if (h->si_rho.empty()) {
+    // Rayleigh-Ritz of the start block: rho_0 (A X formed when the handle was started)
+    double r0;
+    GSI_TRY(hip_check(h, hipMemcpyAsync(e.G0, e.X, nel * sizeof(double), hipMemcpyDeviceToDevice, h->st), "si"));
+    GSI_TRY(hip_check(h, hipMemcpyAsync(e.Z, e.Y, nel * sizeof(double), hipMemcpyDeviceToDevice, h->st), "si"));
+    GSI_TRY(si_ritz(h, e.G0, e.Z, &r0));
+    h->si_rho.push_back(r0);
+    h->si_spmm = 1;
+    if (r0 <= h->opt.tol) h->si_done = 1;
+  }
+  for (int it = 0; it < count && !h->si_done; ++it) {
+    if (h->si_k >= h->opt.max_iter) {
+      h->si_done = 2;
+      break;
+    }
+    double* Xh = e.G0;
+    if (d <= 0) {
+      GSI_TRY(hip_check(h, hipMemcpyAsync(Xh, e.Y, nel * sizeof(double), hipMemcpyDeviceToDevice, h->st), "si"));
+    } else {
+      const double c = 0.5 * (h->opt.cheb_lo + h->opt.cheb_hi), hw = 0.5 * (h->opt.cheb_hi - h->opt.cheb_lo);
+      const double sigma1 = hw / (h->opt.cheb_top - c);
+      double sigma = sigma1;
+      // three rotating blocks; the first step reads X and Y = A X
+      double* pool[3] = {e.G0, e.G1, e.P0};
+      double* prev = e.X;
+      double* cur = e.G0;
+      launch_axpby<double>(h->st, nel, e.Y, e.X, cur, sigma1 / hw, -c * sigma1 / hw);
+      for (int j = 2; j <= d; ++j) {
+        const double sigma_new = 1.0 / (2.0 / sigma1 - sigma);
+        double* nxt = pool[0];
+        for (double* b : pool)
+          if (b != cur && b != prev) { nxt = b; break; }
+        const double a = 2.0 * sigma_new / hw;
+        dispatch_pp<double>(e.PP, [&](auto PPc) {
+          constexpr int PP = decltype(PPc)::value;
+          Kernels<double, PP>::spmm_axpy(h->st, e.n, h->rowptr, h->colind, e.vals, cur, prev, nxt, a, -c * a,
+                                         -sigma * sigma_new, h->plane_tiles);
+        });
+        prev = cur;
+        cur = nxt;
+        sigma = sigma_new;
+      }
+      Xh = cur;
+      h->si_spmm += d - 1;
+    }
+    GSI_TRY(cholqr2_buf(h, e, Xh));
+    dispatch_pp<double>(e.PP, [&](auto PPc) {
+      constexpr int PP = decltype(PPc)::value;
+      Kernels<double, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, Xh, Xh, e.Z, e.sc, 0, h->plane_tiles);
+    });
+    h->si_spmm += 1;
+    double r;
+    GSI_TRY(si_ritz(h, Xh, e.Z, &r));
+    h->si_rho.push_back(r);
+    ++h->si_k;
+    if (!(r == r)) { h->si_done = 3; break; }
+    if (r <= h->opt.tol) h->si_done = 1;
+  }
+  return GSI_OK;
+}
+
 gsi_status start(gsi_ctx* h, const double* X0) {
   // pack X0 into the active engine, orthonormalize, form A X and reset the state
   h->e64.destroy_graph();
   h->e32.destroy_graph();
   h->e64.vals32 = nullptr;
   h->e64.P32 = nullptr;
+  h->si_k = h->si_spmm = h->si_done = 0;
+  h->si_rho.clear();
   h->low_iters = h->low_spmm = h->low_restarts = h->low_refresh = h->low_null = h->low_sweeps = 0;
   h->hist_off = 0;
   if (h->mixed) {
@@ -559,7 +680,13 @@ gsi_status gsi_create(gsi_handle* out, const gsi_csr* A, const gsi_options* opt,
   if (opt->p < 1 || opt->p >= A->n) return bail(GSI_EINVAL, "need 1 <= p < n");
   if (opt->p > MAXP) return bail(GSI_EUNSUPPORTED, "p above 64 is not built");
   if (opt->which != 1 && opt->which != -1) return bail(GSI_EINVAL, "which must be +1 or -1");
-  if (opt->method != GSI_RSD && opt->method != GSI_RCG) return bail(GSI_EINVAL, "unknown method");
+  if (opt->method != GSI_RSD && opt->method != GSI_RCG && opt->method != GSI_SI)
+    return bail(GSI_EINVAL, "unknown method");
+  if (opt->method == GSI_SI && opt->precision != GSI_FP64)
+    return bail(GSI_EUNSUPPORTED, "subspace iteration runs in float64 only");
+  if (opt->method == GSI_SI && opt->cheb_degree > 0 &&
+      !(opt->cheb_hi > opt->cheb_lo && opt->cheb_top > opt->cheb_hi))
+    return bail(GSI_EINVAL, "Chebyshev filter needs cheb_lo < cheb_hi < cheb_top");
   if (opt->precision != GSI_FP64 && opt->precision != GSI_MIXED_FP32 && opt->precision != GSI_MIXED_BF16)
     return bail(GSI_EINVAL, "unknown precision");
   if (!(opt->tol >= 0.0) || opt->max_iter < 0) return bail(GSI_EINVAL, "bad tol or max_iter");
@@ -652,12 +779,20 @@ gsi_status gsi_create(gsi_handle* out, const gsi_csr* A, const gsi_options* opt,
 
 gsi_status gsi_step(gsi_handle h, int32_t n_iter) {
   if (!h || n_iter < 0) return GSI_EINVAL;
+  if (h->opt.method == GSI_SI) return si_iterate(h, n_iter);
   if (h->phase == 1) return enqueue_iterations(h, h->e32, h->hist, n_iter);
   return enqueue_iterations(h, h->e64, h->hist + (size_t)h->hist_off * H_FIELDS, n_iter);
 }
 
 gsi_status gsi_solve(gsi_handle h, int32_t* iters_out) {
   if (!h) return GSI_EINVAL;
+  if (h->opt.method == GSI_SI) {
+    GSI_TRY(si_iterate(h, INT32_MAX));
+    if (iters_out) *iters_out = h->si_k;
+    if (h->si_done == 1) return GSI_OK;
+    if (h->si_done == 2) return fail(h, GSI_NOT_CONVERGED, "max_iter reached");
+    return fail(h, GSI_BREAKDOWN, "subspace iteration: non-finite residual");
+  }
   Scalars s;
   if (h->phase == 1) {
     // a float32 breakdown means float32 resolution is exhausted: refine in float64
@@ -737,6 +872,36 @@ gsi_status gsi_set_x0(gsi_handle h, const double* X0) {
   return start(h, X0);
 }
 
+gsi_status gsi_set_values(gsi_handle h, const double* vals) {
+  if (!h || !vals) return GSI_EINVAL;
+  hipStream_t st = h->st;
+  const int cb = 256;
+  GSI_TRY(hip_check(h, hipMemsetAsync(h->flags, 0, 4 * sizeof(int), st), "flags"));
+  launch_csr_check(st, cb, h->n, h->nnz, h->rowptr, h->colind, vals, h->dvec, h->flags, nullptr);
+  std::vector<double> pm(cb);
+  int fl = 0;
+  GSI_TRY(hip_check(h, hipMemcpyAsync(pm.data(), h->dvec, sizeof(double) * cb, hipMemcpyDeviceToHost, st), "norm"));
+  GSI_TRY(hip_check(h, hipMemcpyAsync(&fl, h->flags, sizeof(int), hipMemcpyDeviceToHost, st), "flags"));
+  GSI_TRY(hip_check(h, hipStreamSynchronize(st), "set_values"));
+  (void)hipMemsetAsync(h->flags, 0, 4 * sizeof(int), st);
+  if (fl & 4) return fail(h, GSI_BREAKDOWN, "non-finite matrix value");
+  double nA = 0.0;
+  for (int i = 0; i < cb; ++i) nA = pm[i] > nA ? pm[i] : nA;
+  if (!(nA > 0.0)) return fail(h, GSI_EINVAL, "zero matrix");
+  h->nA = nA;
+  // the current basis, unpacked into a float64 block (the engine's G0 holds >= n*p doubles;
+  // the restart below resets the state that used it)
+  if (h->phase == 1)
+    launch_unpack<float>(st, h->n, h->p, h->PP, h->e32.X, h->e64.G0);
+  else
+    launch_unpack<double>(st, h->n, h->p, h->PP, h->e64.X, h->e64.G0);
+  const double sign = h->opt.which > 0 ? 1.0 : -1.0;
+  launch_convert<double, double>(st, h->nnz, vals, h->e64.vals, sign);
+  if (h->mixed) launch_convert<double, float>(st, h->nnz, vals, h->e32.vals, sign);
+  if (h->bf16) launch_to_bf16(st, h->nnz, vals, h->e32.vals16, sign);
+  return start(h, h->e64.G0);
+}
+
 gsi_status gsi_spmm(gsi_handle h, const double* W, double* Z) {
   if (!h || !W || !Z) return GSI_EINVAL;
   Engine<double>& e = h->e64;
@@ -776,6 +941,18 @@ gsi_status gsi_spmm_lowp(gsi_handle h, const double* W, double* Z) {
 gsi_status gsi_history(gsi_handle h, int32_t* count, double* rho, double* phi, double* mu, double* beta_pr,
                        double* ginf_rel) {
   if (!h || !count) return GSI_EINVAL;
+  if (h->opt.method == GSI_SI) {
+    const int m = (int)h->si_rho.size() < *count ? (int)h->si_rho.size() : *count;
+    for (int i = 0; i < m; ++i) {
+      if (rho) rho[i] = h->si_rho[i];
+      if (phi) phi[i] = 0.0;
+      if (mu) mu[i] = 0.0;
+      if (beta_pr) beta_pr[i] = 0.0;
+      if (ginf_rel) ginf_rel[i] = 0.0;
+    }
+    *count = m;
+    return GSI_OK;
+  }
   Scalars s;
   GSI_TRY(read_scalars(h, h->phase == 1 ? h->e32.sc : h->e64.sc, &s));
   const int len = (h->phase == 1 ? 0 : h->hist_off) + s.hist_len;
@@ -799,6 +976,13 @@ gsi_status gsi_history(gsi_handle h, int32_t* count, double* rho, double* phi, d
 gsi_status gsi_counters(gsi_handle h, int32_t* iters, int32_t* spmm, int32_t* restarts, int32_t* refreshes,
                         int32_t* null_steps, int32_t* low_iters, int32_t* eig_sweeps) {
   if (!h) return GSI_EINVAL;
+  if (h->opt.method == GSI_SI) {
+    if (iters) *iters = h->si_k;
+    if (spmm) *spmm = h->si_spmm;
+    for (int32_t* q : {restarts, refreshes, null_steps, low_iters, eig_sweeps})
+      if (q) *q = 0;
+    return GSI_OK;
+  }
   Scalars s;
   GSI_TRY(read_scalars(h, h->phase == 1 ? h->e32.sc : h->e64.sc, &s));
   const bool lowonly = h->phase == 1;

@@ -35,6 +35,10 @@ struct Kernels {
   // Z = A W with bfloat16 values and W, float32 accumulation and output
   static void spmm16(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind, const uint16_t* vals,
                      const uint16_t* W, float* Z, const Scalars* sc, int mode, int64_t plane_tiles = 0);
+  // Z = alpha (A W) + beta W + gamma V (V nullable), always runs
+  static void spmm_axpy(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind, const T* vals,
+                        const T* W, const T* V, T* Z, double alpha, double beta, double gamma,
+                        int64_t plane_tiles = 0);
   // Z (float64) = A W from float32 values and W, float64 products and accumulation
   static void spmm_fin(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind, const float* vals,
                        const float* W, double* Z, const Scalars* sc, int mode, int64_t plane_tiles = 0);
@@ -46,6 +50,8 @@ void launch_reduce(hipStream_t st, const double* partials, int nb, int64_t nv, i
                    const Scalars* sc, int cond);
 void launch_set_sym(hipStream_t st, int PP, const double* red, double* dst);
 void launch_to_bf16(hipStream_t st, int64_t count, const double* src, uint16_t* dst, double scale);
+template <typename T>
+void launch_axpby(hipStream_t st, int64_t count, const T* Y, const T* X, T* Z, double a, double b);
 template <typename T>
 void launch_pack(hipStream_t st, int64_t n, int p, int PP, const double* src, T* dst, double scale);
 template <typename T>

@@ -473,6 +473,65 @@ __global__ __launch_bounds__(WG) void k_spmm_fin(int64_t n, const int32_t* __res
   }
 }
 
+// Z = alpha (A W) + beta W + gamma V (V nullable): one step of a polynomial filter's
+// three-term recurrence fused into the SpMM (the row of W and of V a lane needs for the
+// epilogue is its own output row). Always runs (mode 0), same tiling as k_spmm.
+template <typename T, int PP>
+__global__ __launch_bounds__(WG) void k_spmm_axpy(int64_t n, const int32_t* __restrict__ rowptr,
+                                                  const int32_t* __restrict__ colind, const T* __restrict__ vals,
+                                                  const T* __restrict__ W, const T* __restrict__ V, T* __restrict__ Z,
+                                                  double alpha, double beta, double gamma, int64_t plane_tiles) {
+  constexpr int EPL = 4;
+  constexpr int LPR = PP / EPL;
+  constexpr int RPB = WG / LPR;
+  constexpr int U = 8;
+  const int64_t ntiles = (n + TR - 1) / TR;
+  const int64_t t = spmm_tile(ntiles, plane_tiles);
+  if (t >= ntiles) return;
+  const int sub = threadIdx.x / LPR, lane = threadIdx.x % LPR;
+#pragma unroll
+  for (int pass = 0; pass < TR / RPB; ++pass) {
+    const int64_t row = t * TR + pass * RPB + sub;
+    if (row >= n) continue;
+    T acc[EPL] = {T(0), T(0), T(0), T(0)};
+    const int32_t j0 = rowptr[row], j1 = rowptr[row + 1];
+    for (int32_t j = j0; j < j1; j += U) {
+      int32_t col[U];
+      T v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool ok = j + u < j1;
+        col[u] = ok ? colind[j + u] : 0;
+        v[u] = ok ? vals[j + u] : T(0);
+      }
+      T x[U][EPL];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) x[u][e] = gld(W + (int64_t)col[u] * PP + EPL * lane + e);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) acc[e] += v[u] * x[u][e];
+    }
+    const int64_t o = row * PP + EPL * lane;
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      double z = alpha * (double)acc[e] + beta * (double)gld(W + o + e);
+      if (V) z += gamma * (double)gld(V + o + e);
+      gst(Z + o + e, (T)z);
+    }
+  }
+}
+
+// Z = a Y + b X over count elements.
+template <typename T>
+__global__ void k_axpby(int64_t count, const T* __restrict__ Y, const T* __restrict__ X, T* __restrict__ Z, double a,
+                        double b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) Z[i] = (T)(a * (double)Y[i] + b * (double)X[i]);
+}
+
 // ---------------------------------------------------------------- Gram pass
 // Partials of A^T B1 and (when B2 != nullptr) A^T B2 over the workgroup's rows, without LDS.
 // At k-step s a lane (g = l/16, c = l%16) reads row 4s+g, columns c*V .. c*V+V-1 of each
@@ -790,6 +849,14 @@ void Kernels<T, PP>::dir(hipStream_t st, int nb, int64_t n, const T* X, const T*
   k_dir<T, PP><<<nb, WG, lds_bytes<T, PP>(Pass::Dir), st>>>(n, X, G0, G1, P0, P1, small, sc, partials, P16, P32);
 }
 template <typename T, int PP>
+void Kernels<T, PP>::spmm_axpy(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind, const T* vals,
+                               const T* W, const T* V, T* Z, double alpha, double beta, double gamma,
+                               int64_t plane_tiles) {
+  const int64_t grid = spmm_grid((n + TR - 1) / TR, plane_tiles);
+  k_spmm_axpy<T, PP><<<dim3((unsigned)grid), dim3(WG), 0, st>>>(n, rowptr, colind, vals, W, V, Z, alpha, beta, gamma,
+                                                               plane_tiles);
+}
+template <typename T, int PP>
 void Kernels<T, PP>::spmm_fin(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind,
                               const float* vals, const float* W, double* Z, const Scalars* sc, int mode,
                               int64_t plane_tiles) {
@@ -869,6 +936,11 @@ void launch_convert(hipStream_t st, int64_t count, const TS* src, TD* dst, doubl
   hipLaunchKernelGGL((k_convert<TS, TD>), dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count, src, dst,
                      scale);
 }
+template <typename T>
+void launch_axpby(hipStream_t st, int64_t count, const T* Y, const T* X, T* Z, double a, double b) {
+  hipLaunchKernelGGL((k_axpby<T>), dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count, Y, X, Z, a, b);
+}
+template void launch_axpby<double>(hipStream_t, int64_t, const double*, const double*, double*, double, double);
 void launch_to_bf16(hipStream_t st, int64_t count, const double* src, uint16_t* dst, double scale) {
   hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count, src, dst, scale);
 }

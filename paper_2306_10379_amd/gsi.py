@@ -16,12 +16,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgsi.so")
 
 GSI_OK, GSI_EINVAL, GSI_ENOMEM, GSI_EDEVICE, GSI_NOT_CONVERGED, GSI_BREAKDOWN, GSI_EUNSUPPORTED = range(7)
-GSI_RSD, GSI_RCG = 1, 2
+GSI_RSD, GSI_RCG, GSI_SI = 1, 2, 3
 GSI_FP64, GSI_MIXED_FP32, GSI_MIXED_BF16 = 0, 1, 2
 
 EXPORTS = [
     "gsi_options_default", "gsi_create", "gsi_step", "gsi_solve", "gsi_residuals", "gsi_get_x",
-    "gsi_set_x0", "gsi_spmm", "gsi_spmm_lowp", "gsi_history", "gsi_counters", "gsi_pass_times", "gsi_destroy",
+    "gsi_set_x0", "gsi_set_values", "gsi_spmm", "gsi_spmm_lowp", "gsi_history", "gsi_counters", "gsi_pass_times", "gsi_destroy",
     "gsi_status_str", "gsi_last_error", "gsi_create_batched", "gsi_solve_batched", "gsi_batched_results",
     "gsi_batched_get_x", "gsi_batched_set_tuning", "gsi_batched_timeline", "gsi_batched_pass_times", "gsi_batched_last_error", "gsi_destroy_batched",
 ]
@@ -38,7 +38,8 @@ class GsiOptions(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("recompute_ax", ctypes.c_int32), ("k_restart", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("switch_tol", ctypes.c_double),
                 ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("explicit_c", ctypes.c_int32),
-                ("stall_window", ctypes.c_int32)]
+                ("stall_window", ctypes.c_int32), ("cheb_degree", ctypes.c_int32), ("cheb_lo", ctypes.c_double),
+                ("cheb_hi", ctypes.c_double), ("cheb_top", ctypes.c_double)]
 
 
 _lib = None
@@ -68,6 +69,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gsi_get_x.restype = ctypes.c_int
     L.gsi_set_x0.argtypes = [vp, vp]
     L.gsi_set_x0.restype = ctypes.c_int
+    L.gsi_set_values.argtypes = [vp, vp]
+    L.gsi_set_values.restype = ctypes.c_int
     L.gsi_spmm.argtypes = [vp, vp, vp]
     L.gsi_spmm.restype = ctypes.c_int
     L.gsi_spmm_lowp.argtypes = [vp, vp, vp]
@@ -178,6 +181,10 @@ def gsi_set_x0(h, X0):
     return _check(h, load().gsi_set_x0(h, ctypes.c_void_p(_dptr(X0))))
 
 
+def gsi_set_values(h, vals):
+    _check(h, load().gsi_set_values(h, _dptr(vals)))
+
+
 def gsi_spmm(h, W, Z):
     return _check(h, load().gsi_spmm(h, ctypes.c_void_p(_dptr(W)), ctypes.c_void_p(_dptr(Z))))
 
@@ -243,7 +250,7 @@ class Solver:
         self.n, self.p = int(n), int(p)
         method = opts.pop("method", "rcg")
         precision = opts.pop("precision", "fp64")
-        opts["method"] = {"rsd": GSI_RSD, "rcg": GSI_RCG}[method] if isinstance(method, str) else method
+        opts["method"] = {"rsd": GSI_RSD, "rcg": GSI_RCG, "si": GSI_SI}[method] if isinstance(method, str) else method
         opts["precision"] = {"fp64": GSI_FP64, "mixed": GSI_MIXED_FP32, "fp32": GSI_MIXED_FP32,
                              "bf16": GSI_MIXED_BF16}[precision] \
             if isinstance(precision, str) else precision
@@ -271,6 +278,14 @@ class Solver:
 
     def set_x0(self, X0):
         gsi_set_x0(self.h, X0)
+
+    def set_values(self, vals):
+        """New matrix values (same sparsity pattern); the iteration restarts from the current
+        basis (subspace tracking)."""
+        import torch
+        if not torch.is_tensor(vals):
+            vals = torch.as_tensor(np.asarray(vals, dtype=np.float64), device=self.device)
+        gsi_set_values(self.h, vals.contiguous())
 
     def spmm(self, W):
         import torch
@@ -413,7 +428,7 @@ class BatchedSolver:
         opts["precision"] = {"fp64": GSI_FP64, "fp32": GSI_MIXED_FP32, "mixed": GSI_MIXED_FP32}[precision] \
             if isinstance(precision, str) else precision
         method = opts.pop("method", "rcg")
-        opts["method"] = {"rsd": GSI_RSD, "rcg": GSI_RCG}[method] if isinstance(method, str) else method
+        opts["method"] = {"rsd": GSI_RSD, "rcg": GSI_RCG, "si": GSI_SI}[method] if isinstance(method, str) else method
         self.opt = options(**opts)
         self.device = device
         self.h = gsi_create_batched(dev_mats, self.ps, xs, self.opt)

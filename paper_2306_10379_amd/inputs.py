@@ -158,6 +158,22 @@ def schrodinger_2d(N: int, wells: Wells | None) -> CSR:
     return A
 
 
+def moving_well_sequence(N: int, steps: int, seed: int = 0, depth: float = -15.0, width: float = 0.08,
+                         start=(0.35, 0.4), velocity=(0.01, 0.005)):
+    """Schroedinger operators H_t = -Laplacian + V_t, t = 0 .. steps-1, on one N x N grid
+    (one sparsity pattern): a fixed random background of wells plus one Gaussian well of the
+    given depth and width whose centre moves by `velocity` per step (a slowly varying
+    sequence, as in self-consistent field iterations or time stepping)."""
+    bg = random_wells(seed, count=3, amp=(-8.0, 0.0))
+    mats = []
+    for t in range(steps):
+        c = np.array([[start[0] + t * velocity[0], start[1] + t * velocity[1]]])
+        w = Wells(amp=np.concatenate([bg.amp, [depth]]), width=np.concatenate([bg.width, [width]]),
+                  centre=np.concatenate([bg.centre, c]))
+        mats.append(schrodinger_2d(N, w))
+    return mats
+
+
 def schrodinger_batch(count: int = 512, seed: int = 2024, sides: tuple[int, int] = (32, 160),
                       blocks: tuple[int, int] = (4, 32), wells: tuple[int, int] = (1, 6)):
     """A batch of 2D Schroedinger operators H = -Laplacian + V of uneven sizes: grid side N

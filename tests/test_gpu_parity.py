@@ -344,3 +344,94 @@ def test_batched_team_policy_setter_and_results_unchanged():
             assert team[0] <= max(1, min(16, (big.n + 63) // 64 // policy[0]))
             ritz, rho, _ = b.results(0)
             assert np.max(np.abs(-ritz - ref.theta) / np.abs(ref.theta)) <= 1e-10
+
+
+def test_si_monomial_and_chebyshev_match_oracle():
+    # subspace iteration (Algorithm 1) with the monomial filter and with the Chebyshev filter
+    # of eq. optimal_poly on the smallest eigenvalues of the 2D Laplacian: the operator solved
+    # is -A, whose unwanted eigenvalues lie in [-lambda_n, -lambda_{p+1}]
+    gsi = _gsi()
+    N, p = 24, 6
+    A = I.laplacian_2d(N)
+    lam = laplacian_spectrum(N, N)
+    X0 = I.start_block(A.n, p, 5)
+    # monomial filter on the largest eigenvalues (which = +1)
+    print("SI monomial", flush=True)
+    ref = O.subspace_iteration(A, X0, tol=1e-9, max_iter=5000, which=1)
+    with gsi.Solver(A, X0, p, which=1, method="si", tol=1e-9, max_iter=5000) as s:
+        r = s.run()
+        X = s.get_x().cpu().numpy()
+        hist = s.history()
+    assert r.status == 0 and ref.converged
+    assert abs(r.iters - ref.iters) <= 1
+    k = min(len(hist["rho"]), len(ref.rho))
+    assert np.allclose(hist["rho"][:k], ref.rho[:k], rtol=1e-6, atol=1e-14)
+    assert np.max(np.abs(r.ritz - lam[:p]) / lam[:p]) <= 1e-10
+    assert O.principal_angles(X, ref.X).max() <= 1e-7
+    # Chebyshev filters on the smallest eigenvalues (which = -1): the operator is -A, the
+    # unwanted interval [-lambda_max, -lambda_{p+1}], normalized just above -lambda_min
+    la = np.sort(lam)
+    lo, hi, top = -la[-1] * 1.01, -la[p] * 0.999, -la[0] * 0.99
+    for d in (1, 2, 8):
+        print(f"SI chebyshev degree={d}", flush=True)
+        ref = O.chebyshev_si(A, X0, d, lo, hi, top, tol=1e-10, max_iter=5000, which=-1)
+        with gsi.Solver(A, X0, p, which=-1, method="si", tol=1e-10, max_iter=5000, cheb_degree=d, cheb_lo=lo,
+                        cheb_hi=hi, cheb_top=top) as s:
+            r = s.run()
+            X = s.get_x().cpu().numpy()
+            hist = s.history()
+            cnt = s.counters()
+        assert r.status == 0 and ref.converged
+        assert abs(r.iters - ref.iters) <= 1
+        k = min(len(hist["rho"]), len(ref.rho), 30)
+        assert np.allclose(hist["rho"][:k], ref.rho[:k], rtol=1e-6, atol=1e-13)
+        assert np.max(np.abs(r.ritz - la[:p]) / la[:p]) <= 1e-10
+        assert O.principal_angles(X, ref.X).max() <= 1e-7
+        assert cnt["spmm"] == 1 + d * r.iters
+
+
+def test_si_rejects_bad_filter_and_mixed_precision():
+    gsi = _gsi()
+    A = I.laplacian_2d(16)
+    X0 = I.start_block(A.n, 4, 0)
+    with pytest.raises(gsi.GsiError):
+        gsi.Solver(A, X0, 4, method="si", cheb_degree=4, cheb_lo=1.0, cheb_hi=0.5, cheb_top=2.0)
+    with pytest.raises(gsi.GsiError):
+        gsi.Solver(A, X0, 4, method="si", precision="mixed")
+
+
+def test_tracking_sequence_matches_oracle_chain():
+    # subspace tracking: each matrix of a slowly varying sequence is solved from the basis of
+    # the previous one, through gsi_set_values on one handle; the oracle runs its own chain
+    gsi = _gsi()
+    N, p, steps = 40, 8, 5
+    mats = I.moving_well_sequence(N, steps, seed=4)
+    X0 = I.start_block(N * N, p, 9)
+    print(f"tracking N={N} p={p} steps={steps}", flush=True)
+    ref = O.track(mats, X0, tol=1e-10, max_iter=20000, which=-1)
+    iters = []
+    with gsi.Solver(mats[0], X0, p, which=-1, tol=1e-10, max_iter=20000) as s:
+        for t, A in enumerate(mats):
+            if t:
+                s.set_values(A.vals)
+            r = s.run()
+            X = s.get_x().cpu().numpy()
+            assert r.status == 0, t
+            w = np.linalg.eigvalsh(A.to_dense())[:p]
+            assert np.max(np.abs(r.ritz - w) / np.abs(w)) <= 1e-9, t
+            assert np.max(np.abs(r.ritz - ref[t].theta) / np.abs(w)) <= 1e-9, t
+            assert O.principal_angles(X, ref[t].X).max() <= 1e-6, t
+            assert _true_rho(A, X) <= 1.05e-10, t
+            iters.append(r.iters)
+        # a non-finite value is refused and the handle keeps working on the old values
+        bad = np.array(mats[-1].vals)
+        bad[7] = np.nan
+        with pytest.raises(gsi.GsiError):
+            s.set_values(bad)
+        s.set_x0(X0)
+        r = s.run()
+        assert r.status == 0
+        assert np.allclose(r.ritz, np.linalg.eigvalsh(mats[-1].to_dense())[:p], rtol=1e-9)
+    print("iterations per step", iters, "oracle", [x.iters for x in ref], flush=True)
+    assert all(i < iters[0] for i in iters[1:])
+    assert all(abs(i - x.iters) <= max(5, x.iters // 5) for i, x in zip(iters, ref))

@@ -327,3 +327,67 @@ def test_cholesky_qr2():
     Q = O.cholesky_qr2(X)
     assert np.linalg.norm(Q.T @ Q - np.eye(7)) < 1e-14
     assert O.subspace_distance(Q, O.orthonormalize(X)) < 1e-12
+
+
+def test_chebyshev_filter_is_the_scaled_polynomial():
+    """The recurrence equals C_d((t - c)/h) / C_d((top - c)/h) applied to the eigenvalues of a
+    dense symmetric matrix (numpy's Chebyshev series evaluation, not the recurrence)."""
+    import numpy.polynomial.chebyshev as npc
+    n, p, d = 60, 4, 9
+    lam = np.concatenate([np.linspace(3.0, 2.2, p), np.linspace(1.0, -1.0, n - p)])
+    A = I.random_symmetric_dense(n, 3, spectrum=lam)
+    X = I.start_block(n, p, 4)
+    lo, hi, top = -1.0, 1.0, 3.0
+    got = O.chebyshev_filter(A, X, A @ X, d, lo, hi, top)
+    c, h = 0.5 * (lo + hi), 0.5 * (hi - lo)
+    coef = np.zeros(d + 1)
+    coef[d] = 1.0
+    w, V = np.linalg.eigh(A)
+    pw = npc.chebval((w - c) / h, coef) / npc.chebval((top - c) / h, coef)
+    ref = V @ (pw[:, None] * (V.T @ X))
+    assert np.allclose(got, ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+
+
+def test_chebyshev_si_matches_brute_force_and_needs_fewer_products():
+    """Chebyshev-filtered subspace iteration with the exact unwanted interval converges to
+    the dense eigensolver's answer, in fewer matrix products than the monomial filter
+    (the acceleration of Sec. 2.3)."""
+    A = I.laplacian_2d(16)
+    Ad = A.to_dense()
+    w = np.sort(np.linalg.eigvalsh(Ad))[::-1]
+    p = 6
+    X0 = I.start_block(A.n, p, 5)
+    r1 = O.subspace_iteration(A, X0, tol=1e-9, max_iter=20000)
+    r8 = O.chebyshev_si(A, X0, 8, w[-1], w[p], w[0], tol=1e-9, max_iter=20000)
+    assert r8.converged and r1.converged
+    assert np.allclose(r8.theta, w[:p], rtol=1e-9)
+    assert r8.spmm < 0.5 * r1.spmm
+    # degree 1 with the interval is the shifted monomial filter: same subspace as SI on A - cI
+    r_shift = O.chebyshev_si(A, X0, 1, w[-1], w[p], w[0], tol=1e-9, max_iter=20000)
+    assert r_shift.converged and np.allclose(r_shift.theta, w[:p], rtol=1e-9)
+
+
+def test_track_restarts_from_previous_subspace():
+    # a repeated matrix converges at once from the previous basis, and the tracked subspace
+    # of every step is the one dense diagonalization gives (independent of the start)
+    mats = I.moving_well_sequence(12, 3, seed=1)
+    seq = [mats[0], mats[0], mats[1], mats[2]]
+    p = 4  # lambda_4 = 76.5 is well separated from lambda_5 = 93.5
+    res = O.track(seq, I.start_block(144, p, 3), tol=1e-10, which=-1)
+    assert all(r.converged for r in res)
+    assert res[1].iters == 0
+    for A, r in zip(seq, res):
+        w, V = np.linalg.eigh(A.to_dense())
+        assert np.allclose(np.sort(r.theta), w[:p], rtol=1e-10)
+        assert O.principal_angles(r.X, V[:, :p]).max() < 1e-7
+    # the moving well changes the operator only slightly: tracking costs fewer iterations
+    # than the first solve from a random block
+    assert res[2].iters < res[0].iters and res[3].iters < res[0].iters
+
+
+def test_moving_well_sequence_shares_pattern_and_moves():
+    mats = I.moving_well_sequence(10, 3, seed=0)
+    for A in mats[1:]:
+        assert np.array_equal(A.rowptr, mats[0].rowptr) and np.array_equal(A.colind, mats[0].colind)
+    d1 = np.abs(mats[1].vals - mats[0].vals).max()
+    assert 0.0 < d1 < 0.2 * np.abs(mats[0].vals).max()
