@@ -169,6 +169,39 @@ def si_leg(args, gsi, torch, rowptr, colind, vals, n, X0, ritz_ref, rcg_spmm):
     return out
 
 
+def stencil_leg(args, gsi, torch, X0, t_csr, it_csr, spmm_csr_us):
+    """The headline solve with the operator applied matrix-free (gsi_create_stencil): same
+    matrix, same arithmetic and order, so the same iterates; the SpMM reads the block once
+    and no index or value arrays."""
+    N, p = args.grid, args.p
+    S = gsi.Stencil(N, N, N, diag=6.0, off=-1.0)
+    s = gsi.Solver(S, X0, p, tol=args.tol, max_iter=20000, check_every=50)
+    times, iters = [], 0
+    for i in range(1 + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.set_x0(X0)
+        status, iters = s.solve()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        log(f"stencil solve {i}: {dt:.3f} s, {iters} iterations, status {status}")
+        if i >= 1:
+            times.append(dt)
+    s.pass_times(1)
+    s.set_x0(X0)
+    s.step(20)
+    pt = s.pass_times(0)
+    s.close()
+    ms, cnt = pt["spmm"]
+    avg = ms / max(cnt, 1) * 1e-3
+    nbytes = 2 * N ** 3 * p * 8 + N ** 3 * 8
+    value = float(np.mean(times))
+    return {"s": round(value, 4), "iters": iters, "same_iters_as_csr": iters == it_csr,
+            "speedup_vs_csr": round(t_csr / value, 3), "spmm_us": round(avg * 1e6, 1),
+            "spmm_csr_us": round(spmm_csr_us, 1), "spmm_GBps": round(nbytes / avg / 1e9, 1),
+            "spmm_bytes": nbytes}
+
+
 def batched_leg(args, gsi, inputs, torch):
     """Many small problems in one persistent launch: the whole batch to rho <= tol with float32
     blocks then float64 refinement, and with float64 blocks, against the plain float64 path
@@ -254,6 +287,8 @@ def main():
     ap.add_argument("--no-si", action="store_true",
                     help="skip the Chebyshev-filtered subspace iteration on the headline workload")
     ap.add_argument("--si-degrees", type=int, nargs="*", default=[64, 128])
+    ap.add_argument("--no-stencil", action="store_true",
+                    help="skip the matrix-free stencil solve of the headline workload")
     ap.add_argument("--warm-train", type=int, default=144)
     ap.add_argument("--warm-test", type=int, default=24)
     ap.add_argument("--batch", type=int, default=512)
@@ -364,6 +399,10 @@ def main():
                  "ritz_rel_err_vs_fp64": float(np.max(np.abs(ritz32 - ritz64) / np.abs(ritz64))),
                  "rho": rho32}
 
+    stencil = None
+    if not args.no_stencil:
+        stencil = stencil_leg(args, gsi, torch, X0, float(np.mean(t64)), it64, kern["spmm"]["avg_us"])
+
     si = None
     if not args.no_si and args.si_degrees:
         si = si_leg(args, gsi, torch, rowptr, colind, vals, A.n, X0, ritz64, c64["spmm"])
@@ -409,6 +448,7 @@ def main():
                     for k, v in kern.items()},
         "pass_share": {k: round(v[0] / total_ms, 4) for k, v in pt.items() if total_ms > 0},
         "mixed_fp32": mixed,
+        "matrix_free": stencil,
         "si_chebyshev": si,
         "batched": batched,
         "random_sparse": c3,

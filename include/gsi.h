@@ -79,6 +79,19 @@ typedef struct {
   const double* vals;    /* nnz */
 } gsi_csr;
 
+/* A 5- or 7-point stencil operator on an nx x ny x nz grid of nodes in lexicographic order
+ * (x fastest; ny = nz = 1 for a 1D grid, nz = 1 for 2D), applied without index or value
+ * arrays: row r has diag + diag_vec[r] on the diagonal and off at each neighbour inside the
+ * grid (r -+ 1, r -+ nx, r -+ nx ny). The Dirichlet Laplacians and Schroedinger operators
+ * -Laplacian + V of the test problems (Sec. 6) are of this form: diag = 2 d / h^2, off =
+ * -1 / h^2, diag_vec = V (d the dimension). */
+typedef struct {
+  int64_t nx, ny, nz;      /* grid sides, >= 1, n = nx ny nz < 2^31 */
+  double diag;             /* constant part of the diagonal */
+  double off;              /* weight of every neighbour */
+  const double* diag_vec;  /* nullable device array of n values added to the diagonal */
+} gsi_stencil;
+
 typedef struct {
   int32_t p;            /* block size, 1 <= p < n, p <= 64 */
   int32_t which;        /* +1 largest eigenvalues, -1 smallest (the solver runs on -A) */
@@ -119,6 +132,16 @@ void gsi_options_default(gsi_options* opt);
  * workspace; gsi_step / gsi_solve never allocate. Syncs. */
 gsi_status gsi_create(gsi_handle* h, const gsi_csr* A, const gsi_options* opt, const double* X0,
                       void* hip_stream);
+
+/* As gsi_create for a matrix-free stencil operator: every product with A reads the block
+ * once (the neighbours from the caches) and the n diagonal values, and no index or value
+ * arrays (Sec. 6.4 observes that the cost of a product with a very sparse A relative to the
+ * rest of the iteration decides between RCG and RCG(+); a stencil makes that product as
+ * cheap as a streaming pass). The results equal those of gsi_create on the same matrix in
+ * CSR form (same arithmetic, same order). diag_vec is copied; gsi_set_values on such a
+ * handle takes n new diag_vec values. GSI_MIXED_BF16 is not supported (GSI_EUNSUPPORTED). */
+gsi_status gsi_create_stencil(gsi_handle* h, const gsi_stencil* S, const gsi_options* opt, const double* X0,
+                              void* hip_stream);
 
 /* Enqueue n_iter iterations (fewer if the convergence flag is raised on the device;
  * the remaining launches return immediately). Asynchronous. */

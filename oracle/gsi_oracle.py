@@ -433,3 +433,21 @@ def track(mats, X0, tol: float = 1e-10, max_iter: int = 10000, which: int = 1, m
         out.append(r)
         X = r.X
     return out
+
+
+def stencil_matrix(nx: int, ny: int = 1, nz: int = 1, diag: float = 0.0, off: float = -1.0, diag_vec=None):
+    """The matrix of a 5- or 7-point stencil operator on an nx x ny x nz grid (lexicographic,
+    x fastest): diag + diag_vec[r] on the diagonal, off between grid neighbours. Written out
+    entry by entry from that definition (the Sec. 6 test operators: Dirichlet Laplacians and
+    -Laplacian + V)."""
+    n = nx * ny * nz
+    d = np.full(n, float(diag)) + (np.zeros(n) if diag_vec is None else np.asarray(diag_vec, dtype=np.float64))
+    rows, cols, vals = [np.arange(n)], [np.arange(n)], [d]
+    r = np.arange(n)
+    i, j, k = r % nx, (r // nx) % ny, r // (nx * ny)
+    for ok, step in ((i < nx - 1, 1), (j < ny - 1, nx), (k < nz - 1, nx * ny)):
+        a = r[ok]
+        rows += [a, a + step]
+        cols += [a + step, a]
+        vals += [np.full(a.size, float(off))] * 2
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
+#include <cmath>
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -107,6 +108,11 @@ struct gsi_ctx {
   int hist_cap = 0;
   double nA = 0.0;
   int64_t plane_tiles = 0;  // banded SpMM tile order (0: one slab per XCD)
+  // matrix-free stencil operator (gsi_create_stencil): grid, neighbour weight (times the
+  // sign of which); the engines' vals hold the n diagonal entries
+  bool stencil = false;
+  int32_t sdims[3] = {1, 1, 1};
+  double sdiag = 0.0, soff = 0.0;
   Engine<double> e64;
   Engine<float> e32;
   bool mixed = false;
@@ -136,6 +142,15 @@ namespace {
 gsi_status fail(gsi_ctx* h, gsi_status s, const std::string& msg) {
   if (h) h->err = msg;
   return s;
+}
+
+// Z = A_op W through the handle's operator: the CSR kernel or the matrix-free stencil.
+template <typename T, int PP>
+void spmm_op(gsi_ctx* h, Engine<T>& e, const T* W0, const T* W1, T* Z, int mode) {
+  if (h->stencil)
+    Kernels<T, PP>::spmm_stencil(h->st, e.n, h->sdims, e.vals, h->soff, W0, W1, Z, e.sc, mode, h->plane_tiles);
+  else
+    Kernels<T, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, W0, W1, Z, e.sc, mode, h->plane_tiles);
 }
 
 gsi_status hip_check(gsi_ctx* h, hipError_t e, const char* what) {
@@ -255,7 +270,7 @@ gsi_status init_state(gsi_ctx* h, Engine<T>& e, double tol, int max_iter, int hi
                     "small reset"));
   dispatch_pp<T>(e.PP, [&](auto PPc) {
     constexpr int PP = decltype(PPc)::value;
-    Kernels<T, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.X, e.X, e.Y, e.sc, 0, h->plane_tiles);
+    spmm_op<T, PP>(h, e, e.X, e.X, e.Y, 0);
     Kernels<T, PP>::gram(h->st, e.nb, e.n, e.X, e.X, e.Y, nullptr, e.sc, 0, h->partials);
     reduce(h, e.nb, (int64_t)PP * PP, (int64_t)PP * PP, e.sc, 0);
     launch_set_sym(h->st, PP, h->red, e.small + S_C * PP * PP);
@@ -307,12 +322,12 @@ void launch_iteration(gsi_ctx* h, Engine<T>& e, double* hist) {
         if (e.P16)
           Kernels<T, PP>::spmm16(h->st, e.n, h->rowptr, h->colind, e.vals16, e.P16, e.Z, e.sc, 1, h->plane_tiles);
         else
-          Kernels<T, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.P0, e.P1, e.Z, e.sc, 1, h->plane_tiles);
+          spmm_op<T, PP>(h, e, e.P0, e.P1, e.Z, 1);
       } else {
         if (e.P32)
           Kernels<T, PP>::spmm_fin(h->st, e.n, h->rowptr, h->colind, e.vals32, e.P32, e.Z, e.sc, 1, h->plane_tiles);
         else
-          Kernels<T, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.P0, e.P1, e.Z, e.sc, 1, h->plane_tiles);
+          spmm_op<T, PP>(h, e, e.P0, e.P1, e.Z, 1);
       }
     }
     {
@@ -337,7 +352,7 @@ void launch_iteration(gsi_ctx* h, Engine<T>& e, double* hist) {
     }
     {
       PassTimer t(h, GSI_PASS_REFRESH);
-      Kernels<T, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.X, e.X, e.Y, e.sc, 2, h->plane_tiles);
+      spmm_op<T, PP>(h, e, e.X, e.X, e.Y, 2);
       Kernels<T, PP>::gram(h->st, e.nb, e.n, e.X, e.X, e.Y, nullptr, e.sc, 2, h->partials);
     }
     reduce(h, e.nb, P2, P2, e.sc, 2);
@@ -399,7 +414,7 @@ gsi_status run_until_done(gsi_ctx* h, Engine<T>& e, double* hist, Scalars* out, 
       verify = false;
       dispatch_pp<T>(e.PP, [&](auto PPc) {
         constexpr int PP = decltype(PPc)::value;
-        Kernels<T, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.X, e.X, e.Y, e.sc, 0, h->plane_tiles);
+        spmm_op<T, PP>(h, e, e.X, e.X, e.Y, 0);
         Kernels<T, PP>::gram(h->st, e.nb, e.n, e.X, e.X, e.Y, nullptr, e.sc, 0, h->partials);
         reduce(h, e.nb, (int64_t)PP * PP, (int64_t)PP * PP, e.sc, 0);
         launch_set_sym(h->st, PP, h->red, e.small + S_C * PP * PP);
@@ -460,8 +475,10 @@ gsi_status switch_to_fp64(gsi_ctx* h) {
                       "carry W"));
   }
   // the float64 phase's SpMM reads float32 copies of A and P (the float32 blocks are free now)
-  h->e64.vals32 = h->e32.vals;
-  h->e64.P32 = h->e32.Z;
+  if (!h->stencil) {
+    h->e64.vals32 = h->e32.vals;
+    h->e64.P32 = h->e32.Z;
+  }
   h->e64.destroy_graph();
   h->phase = 0;
   return hip_check(h, hipStreamSynchronize(h->st), "switch");
@@ -557,8 +574,12 @@ gsi_status si_iterate(gsi_ctx* h, int count) {
         const double a = 2.0 * sigma_new / hw;
         dispatch_pp<double>(e.PP, [&](auto PPc) {
           constexpr int PP = decltype(PPc)::value;
-          Kernels<double, PP>::spmm_axpy(h->st, e.n, h->rowptr, h->colind, e.vals, cur, prev, nxt, a, -c * a,
-                                         -sigma * sigma_new, h->plane_tiles);
+          if (h->stencil)
+            Kernels<double, PP>::spmm_stencil_axpy(h->st, e.n, h->sdims, e.vals, h->soff, cur, prev, nxt, a,
+                                                   -c * a, -sigma * sigma_new, h->plane_tiles);
+          else
+            Kernels<double, PP>::spmm_axpy(h->st, e.n, h->rowptr, h->colind, e.vals, cur, prev, nxt, a, -c * a,
+                                           -sigma * sigma_new, h->plane_tiles);
         });
         prev = cur;
         cur = nxt;
@@ -570,7 +591,7 @@ gsi_status si_iterate(gsi_ctx* h, int count) {
     GSI_TRY(cholqr2_buf(h, e, Xh));
     dispatch_pp<double>(e.PP, [&](auto PPc) {
       constexpr int PP = decltype(PPc)::value;
-      Kernels<double, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, Xh, Xh, e.Z, e.sc, 0, h->plane_tiles);
+      spmm_op<double, PP>(h, e, Xh, Xh, e.Z, 0);
     });
     h->si_spmm += 1;
     double r;
@@ -646,8 +667,14 @@ const char* gsi_status_str(gsi_status s) {
 
 const char* gsi_last_error(gsi_handle h) { return h ? h->err.c_str() : "null handle"; }
 
-gsi_status gsi_create(gsi_handle* out, const gsi_csr* A, const gsi_options* opt, const double* X0, void* stream) {
-  if (!out || !A || !opt) return GSI_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// Shared by gsi_create (A != nullptr) and gsi_create_stencil (S != nullptr).
+gsi_status create_impl(gsi_handle* out, const gsi_csr* A, const gsi_stencil* S, const gsi_options* opt,
+                       const double* X0, void* stream) {
+  if (!out || (!A && !S) || !opt) return GSI_EINVAL;
   *out = nullptr;
   gsi_ctx* h = new (std::nothrow) gsi_ctx();
   if (!h) return GSI_ENOMEM;
@@ -675,9 +702,22 @@ gsi_status gsi_create(gsi_handle* out, const gsi_csr* A, const gsi_options* opt,
     *out = h;
     return s;
   };
-  if (A->n < 2 || A->nnz < 1 || !A->rowptr || !A->colind || !A->vals) return bail(GSI_EINVAL, "bad CSR arguments");
-  if (A->n > (int64_t)INT32_MAX || A->nnz > (int64_t)INT32_MAX) return bail(GSI_EUNSUPPORTED, "n or nnz >= 2^31");
-  if (opt->p < 1 || opt->p >= A->n) return bail(GSI_EINVAL, "need 1 <= p < n");
+  int64_t n_op = 0;
+  if (A) {
+    if (A->n < 2 || A->nnz < 1 || !A->rowptr || !A->colind || !A->vals) return bail(GSI_EINVAL, "bad CSR arguments");
+    if (A->n > (int64_t)INT32_MAX || A->nnz > (int64_t)INT32_MAX) return bail(GSI_EUNSUPPORTED, "n or nnz >= 2^31");
+    n_op = A->n;
+  } else {
+    if (S->nx < 1 || S->ny < 1 || S->nz < 1 || !std::isfinite(S->diag) || !std::isfinite(S->off))
+      return bail(GSI_EINVAL, "bad stencil arguments");
+    if (S->nx > INT32_MAX || S->ny > INT32_MAX || S->nz > INT32_MAX ||
+        (double)S->nx * (double)S->ny * (double)S->nz > (double)INT32_MAX)
+      return bail(GSI_EUNSUPPORTED, "n >= 2^31");
+    n_op = S->nx * S->ny * S->nz;
+    if (n_op < 2) return bail(GSI_EINVAL, "bad stencil arguments");
+    if (opt->precision == GSI_MIXED_BF16) return bail(GSI_EUNSUPPORTED, "bfloat16 mode needs a CSR matrix");
+  }
+  if (opt->p < 1 || opt->p >= n_op) return bail(GSI_EINVAL, "need 1 <= p < n");
   if (opt->p > MAXP) return bail(GSI_EUNSUPPORTED, "p above 64 is not built");
   if (opt->which != 1 && opt->which != -1) return bail(GSI_EINVAL, "which must be +1 or -1");
   if (opt->method != GSI_RSD && opt->method != GSI_RCG && opt->method != GSI_SI)
@@ -691,8 +731,16 @@ gsi_status gsi_create(gsi_handle* out, const gsi_csr* A, const gsi_options* opt,
     return bail(GSI_EINVAL, "unknown precision");
   if (!(opt->tol >= 0.0) || opt->max_iter < 0) return bail(GSI_EINVAL, "bad tol or max_iter");
   if (!X0) return bail(GSI_EINVAL, "X0 is required");
-  h->n = A->n;
-  h->nnz = A->nnz;
+  h->n = n_op;
+  h->nnz = A ? A->nnz : n_op;  // values held: the nonzeros, or the stencil's diagonal
+  if (S) {
+    h->stencil = true;
+    h->sdims[0] = (int32_t)S->nx;
+    h->sdims[1] = (int32_t)S->ny;
+    h->sdims[2] = (int32_t)S->nz;
+    h->sdiag = S->diag;
+    h->soff = (opt->which > 0 ? 1.0 : -1.0) * S->off;
+  }
   h->p = opt->p;
   h->PP = round16(opt->p);
   h->mixed = opt->precision == GSI_MIXED_FP32 || opt->precision == GSI_MIXED_BF16;
@@ -706,8 +754,10 @@ gsi_status gsi_create(gsi_handle* out, const gsi_csr* A, const gsi_options* opt,
   h->nb = (int)(ntiles < 4 * ncu ? ntiles : 4 * ncu);
   h->hist_cap = opt->max_iter + 2;
   Dev& d = h->dev;
-  h->rowptr = d.alloc<int32_t>(h->n + 1);
-  h->colind = d.alloc<int32_t>(h->nnz);
+  if (A) {
+    h->rowptr = d.alloc<int32_t>(h->n + 1);
+    h->colind = d.alloc<int32_t>(h->nnz);
+  }
   h->partials = d.alloc<double>((size_t)h->nb * (2 * h->PP * h->PP + 8) + 4096);
   h->red = d.alloc<double>(2 * h->PP * h->PP + 8);
   h->hist = d.alloc<double>((size_t)h->hist_cap * H_FIELDS);
@@ -729,16 +779,22 @@ gsi_status gsi_create(gsi_handle* out, const gsi_csr* A, const gsi_options* opt,
   if (ke != hipSuccess) return bail(GSI_EDEVICE, std::string("kernel attributes: ") + hipGetErrorString(ke));
   hipStream_t st = h->st;
   gsi_status s = GSI_OK;
-  s = hip_check(h, hipMemcpyAsync(h->rowptr, A->rowptr, sizeof(int32_t) * (h->n + 1), hipMemcpyDeviceToDevice, st),
-                "copy rowptr");
-  if (s == GSI_OK)
+  if (A)
+    s = hip_check(h, hipMemcpyAsync(h->rowptr, A->rowptr, sizeof(int32_t) * (h->n + 1), hipMemcpyDeviceToDevice, st),
+                  "copy rowptr");
+  if (s == GSI_OK && A)
     s = hip_check(h, hipMemcpyAsync(h->colind, A->colind, sizeof(int32_t) * h->nnz, hipMemcpyDeviceToDevice, st),
                   "copy colind");
   if (s == GSI_OK) s = hip_check(h, hipMemsetAsync(h->flags, 0, 4 * sizeof(int), st), "flags");
   if (s != GSI_OK) return bail(s, h->err);
   // validate the CSR and compute ||A||_inf
   const int cb = 256;
-  launch_csr_check(st, cb, h->n, h->nnz, A->rowptr, A->colind, A->vals, h->dvec, h->flags, h->dvec + cb);
+  if (A) {
+    launch_csr_check(st, cb, h->n, h->nnz, A->rowptr, A->colind, A->vals, h->dvec, h->flags, h->dvec + cb);
+  } else {
+    launch_stencil_check(st, cb, h->n, h->sdims, S->diag, S->off, S->diag_vec, h->dvec, h->flags);
+    (void)hipMemsetAsync(h->dvec + cb, 0, sizeof(double) * cb, st);
+  }
   launch_finite(st, h->n * (int64_t)h->p, X0, h->flags + 1);
   std::vector<double> pm(2 * cb);
   int fl[2] = {0, 0};
@@ -757,6 +813,8 @@ gsi_status gsi_create(gsi_handle* out, const gsi_csr* A, const gsi_options* opt,
     nA = pm[i] > nA ? pm[i] : nA;
     band = pm[cb + i] > band ? pm[cb + i] : band;
   }
+  // band of a stencil: its farthest neighbour (a plane, a grid line or the next node)
+  if (S) band = S->nz > 1 ? (double)(S->nx * S->ny) : (S->ny > 1 ? (double)S->nx : 1.0);
   if (!(nA > 0.0)) return bail(GSI_EINVAL, "zero matrix");
   h->nA = nA;
   // banded SpMM tile order when the rows reach at least 64 tiles away and the matrix spans
@@ -766,15 +824,35 @@ gsi_status gsi_create(gsi_handle* out, const gsi_csr* A, const gsi_options* opt,
     h->plane_tiles = (pt >= 64 && 4 * pt <= ntiles) ? pt : 0;
   }
   const double sign = opt->which > 0 ? 1.0 : -1.0;
-  launch_convert<double, double>(st, h->nnz, A->vals, h->e64.vals, sign);
-  if (h->mixed) launch_convert<double, float>(st, h->nnz, A->vals, h->e32.vals, sign);
-  if (h->bf16) launch_to_bf16(st, h->nnz, A->vals, h->e32.vals16, sign);
+  if (A) {
+    launch_convert<double, double>(st, h->nnz, A->vals, h->e64.vals, sign);
+    if (h->mixed) launch_convert<double, float>(st, h->nnz, A->vals, h->e32.vals, sign);
+    if (h->bf16) launch_to_bf16(st, h->nnz, A->vals, h->e32.vals16, sign);
+  } else {
+    launch_stencil_diag<double>(st, h->n, S->diag, S->diag_vec, sign, h->e64.vals);
+    if (h->mixed) launch_stencil_diag<float>(st, h->n, S->diag, S->diag_vec, sign, h->e32.vals);
+  }
   h->e64.explicit_grams = opt->explicit_c != 0;
   h->e32.explicit_grams = opt->explicit_c != 0;
   s = start(h, X0);
   if (s != GSI_OK) return bail(s, h->err);
   *out = h;
   return GSI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gsi_status gsi_create(gsi_handle* out, const gsi_csr* A, const gsi_options* opt, const double* X0, void* stream) {
+  if (!A) return GSI_EINVAL;
+  return create_impl(out, A, nullptr, opt, X0, stream);
+}
+
+gsi_status gsi_create_stencil(gsi_handle* out, const gsi_stencil* S, const gsi_options* opt, const double* X0,
+                              void* stream) {
+  if (!S) return GSI_EINVAL;
+  return create_impl(out, nullptr, S, opt, X0, stream);
 }
 
 gsi_status gsi_step(gsi_handle h, int32_t n_iter) {
@@ -814,7 +892,7 @@ gsi_status gsi_residuals(gsi_handle h, double* ritz, double* col_res, double* rh
   double* theta = h->dvec;
   dispatch_pp<double>(e.PP, [&](auto PPc) {
     constexpr int PP = decltype(PPc)::value;
-    Kernels<double, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.X, e.X, e.Y, e.sc, 0, h->plane_tiles);
+    spmm_op<double, PP>(h, e, e.X, e.X, e.Y, 0);
     Kernels<double, PP>::gram(h->st, e.nb, e.n, e.X, e.X, e.Y, nullptr, e.sc, 0, h->partials);
     reduce(h, e.nb, (int64_t)PP * PP, (int64_t)PP * PP, e.sc, 0);
     Small::ritz(h->st, PP, p, h->red, e.small, theta);
@@ -877,7 +955,10 @@ gsi_status gsi_set_values(gsi_handle h, const double* vals) {
   hipStream_t st = h->st;
   const int cb = 256;
   GSI_TRY(hip_check(h, hipMemsetAsync(h->flags, 0, 4 * sizeof(int), st), "flags"));
-  launch_csr_check(st, cb, h->n, h->nnz, h->rowptr, h->colind, vals, h->dvec, h->flags, nullptr);
+  if (h->stencil)
+    launch_stencil_check(st, cb, h->n, h->sdims, h->sdiag, h->soff, vals, h->dvec, h->flags);
+  else
+    launch_csr_check(st, cb, h->n, h->nnz, h->rowptr, h->colind, vals, h->dvec, h->flags, nullptr);
   std::vector<double> pm(cb);
   int fl = 0;
   GSI_TRY(hip_check(h, hipMemcpyAsync(pm.data(), h->dvec, sizeof(double) * cb, hipMemcpyDeviceToHost, st), "norm"));
@@ -896,9 +977,14 @@ gsi_status gsi_set_values(gsi_handle h, const double* vals) {
   else
     launch_unpack<double>(st, h->n, h->p, h->PP, h->e64.X, h->e64.G0);
   const double sign = h->opt.which > 0 ? 1.0 : -1.0;
-  launch_convert<double, double>(st, h->nnz, vals, h->e64.vals, sign);
-  if (h->mixed) launch_convert<double, float>(st, h->nnz, vals, h->e32.vals, sign);
-  if (h->bf16) launch_to_bf16(st, h->nnz, vals, h->e32.vals16, sign);
+  if (h->stencil) {
+    launch_stencil_diag<double>(st, h->n, h->sdiag, vals, sign, h->e64.vals);
+    if (h->mixed) launch_stencil_diag<float>(st, h->n, h->sdiag, vals, sign, h->e32.vals);
+  } else {
+    launch_convert<double, double>(st, h->nnz, vals, h->e64.vals, sign);
+    if (h->mixed) launch_convert<double, float>(st, h->nnz, vals, h->e32.vals, sign);
+    if (h->bf16) launch_to_bf16(st, h->nnz, vals, h->e32.vals16, sign);
+  }
   return start(h, h->e64.G0);
 }
 
@@ -909,7 +995,7 @@ gsi_status gsi_spmm(gsi_handle h, const double* W, double* Z) {
   launch_pack<double>(h->st, h->n, h->p, h->PP, W, e.G0, 1.0);
   dispatch_pp<double>(e.PP, [&](auto PPc) {
     constexpr int PP = decltype(PPc)::value;
-    Kernels<double, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.G0, e.G0, e.Z, e.sc, 0, h->plane_tiles);
+    spmm_op<double, PP>(h, e, e.G0, e.G0, e.Z, 0);
   });
   launch_unpack<double>(h->st, h->n, h->p, h->PP, e.Z, Z);
   return hip_check(h, hipGetLastError(), "spmm");
@@ -931,7 +1017,7 @@ gsi_status gsi_spmm_lowp(gsi_handle h, const double* W, double* Z) {
       Kernels<float, PP>::spmm16(h->st, e.n, h->rowptr, h->colind, e.vals16, e.P16, e.Z, e.sc, 0, h->plane_tiles);
     } else {
       launch_pack<float>(h->st, h->n, h->p, h->PP, W, e.G0, 1.0);
-      Kernels<float, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, e.G0, e.G0, e.Z, e.sc, 0, h->plane_tiles);
+      spmm_op<float, PP>(h, e, e.G0, e.G0, e.Z, 0);
     }
   });
   launch_unpack<float>(h->st, h->n, h->p, h->PP, e.Z, Z);

@@ -44,6 +44,14 @@ struct Kernels {
                        const float* W, double* Z, const Scalars* sc, int mode, int64_t plane_tiles = 0);
   static void colres(hipStream_t st, int nb, int64_t n, const T* X, const T* Y, const double* theta,
                      double* partials);
+  // matrix-free stencil operator on the grid dims[0] x dims[1] x dims[2] (host array):
+  // diagonal diag[r], `off` at each neighbour; mode as for spmm
+  static void spmm_stencil(hipStream_t st, int64_t n, const int32_t* dims, const T* diag, double off, const T* W0,
+                           const T* W1, T* Z, const Scalars* sc, int mode, int64_t plane_tiles = 0);
+  // Z = alpha (A W) + beta W + gamma V for the stencil operator, always runs
+  static void spmm_stencil_axpy(hipStream_t st, int64_t n, const int32_t* dims, const T* diag, double off,
+                                const T* W, const T* V, T* Z, double alpha, double beta, double gamma,
+                                int64_t plane_tiles = 0);
 };
 
 void launch_reduce(hipStream_t st, const double* partials, int nb, int64_t nv, int64_t max_from, double* out,
@@ -62,6 +70,10 @@ void launch_csr_check(hipStream_t st, int nb, int64_t n, int64_t nnz, const int3
                       const double* vals, double* partial_max, int* flags,
                       double* partial_band = nullptr);
 void launch_finite(hipStream_t st, int64_t count, const double* x, int* flags);
+template <typename T>
+void launch_stencil_diag(hipStream_t st, int64_t n, double d, const double* dv, double scale, T* out);
+void launch_stencil_check(hipStream_t st, int nb, int64_t n, const int32_t* dims, double d, double off,
+                          const double* dv, double* partial_max, int* flags);
 
 // Single-workgroup p x p solves (gsi_small.hip). All read/write the small buffer and the
 // scalars; `red` is the reduced partial-sum vector of the preceding pass.

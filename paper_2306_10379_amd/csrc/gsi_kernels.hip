@@ -43,8 +43,18 @@ __global__ __launch_bounds__(WG) void k_grad(int64_t n, const T* __restrict__ X,
   typename Vec4<T>::type kacc[GramSplit<PP>::PER_WAVE];
   gram_zero<T, PP>(kacc);
   double gg = 0.0, gdot = 0.0, ginf = 0.0;
+  // at PP = 64 each wave owns column block w of X in the Gram: its 64 x 16 slice of the
+  // tile is loaded at the top of the tile, so the loads overlap the product (K^T blocks
+  // (q, w) = G^T X are accumulated and stored transposed)
+  constexpr bool XCOL = (PP == 64);
+  const int lg = (threadIdx.x & 63) >> 4, lc = threadIdx.x & 15;
   for (int64_t t = t0; t < t1; ++t) {
     const int64_t row0 = t * TR + 16 * w;
+    T xcol[XCOL ? TR / 4 : 1];
+    if constexpr (XCOL) {
+#pragma unroll
+      for (int s = 0; s < TR / 4; ++s) xcol[s] = gld(X + (t * TR + 4 * s + lg) * PP + 16 * w + lc);
+    }
     T a[PP / 4];
     load_al<T, PP>(X, row0, n, a);
     typename Vec4<T>::type acc[PP / 16];
@@ -80,12 +90,27 @@ __global__ __launch_bounds__(WG) void k_grad(int64_t n, const T* __restrict__ X,
     // tall blocks are allocated with whole tiles of zero rows), G through LDS
     rl_to_lds<T, PP>(sG, g);
     __syncthreads();
-    gram_tile<T, PP>(X + t * TR * PP, sG, kacc);
+    if constexpr (XCOL) {
+#pragma unroll
+      for (int s = 0; s < TR / 4; ++s)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) kacc[q] = mfma(sG[(4 * s + lg) * PP + 16 * q + lc], xcol[s], kacc[q]);
+    } else {
+      gram_tile<T, PP>(X + t * TR * PP, sG, kacc);
+    }
     __syncthreads();
   }
   const int64_t nv = PP * PP + 3;
   double* out = partials + (int64_t)blockIdx.x * nv;
-  gram_store<T, PP>(out, kacc);
+  if constexpr (XCOL) {
+    // kacc[q] holds block (q, w) of K^T: element (i, j) -> K[16 w + j][16 q + i]
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out[(16 * w + lc) * PP + 16 * q + rowof<T>(lg, r)] = (double)kacc[q][r];
+  } else {
+    gram_store<T, PP>(out, kacc);
+  }
   // scalars: sums for gg, gdot; max for ginf
   {
     const int l = threadIdx.x & 63;
@@ -524,6 +549,109 @@ __global__ __launch_bounds__(WG) void k_spmm_axpy(int64_t n, const int32_t* __re
   }
 }
 
+// ---------------------------------------------------------------- matrix-free stencil SpMM
+// Z = A W for a 5- or 7-point stencil on an nx x ny x nz grid (lexicographic order, x
+// fastest): row r holds diag[r] on the diagonal and `off` at each neighbour inside the grid
+// (r -+ nx ny, r -+ nx, r -+ 1). No index or value arrays are read: W once (neighbours from
+// the caches), diag once, Z written once. The seven terms are summed in increasing column
+// order with zero weights for neighbours outside the grid, the order and arithmetic of the
+// CSR kernel, so both give identical results for the same matrix. AXPY: Z = alpha (A W) +
+// beta W + gamma V (V nullable) for the Chebyshev recurrence; such a launch always runs.
+template <typename T, int PP, bool AXPY>
+__global__ __launch_bounds__(WG) void k_spmm_stencil(int64_t n, int32_t nx, int32_t ny, int32_t nz,
+                                                     const T* __restrict__ diag, T off, const T* __restrict__ W0,
+                                                     const T* __restrict__ W1, T* __restrict__ Z,
+                                                     const Scalars* __restrict__ sc, int mode, int64_t plane_tiles,
+                                                     const T* __restrict__ V, double alpha, double beta,
+                                                     double gamma) {
+  if (!AXPY && spmm_skip(sc, mode)) return;
+  const T* W = (!AXPY && mode == 1 && (sc->k & 1)) ? W1 : W0;
+  constexpr int EPL = 4;
+  constexpr int LPR = PP / EPL;
+  constexpr int RPB = WG / LPR;
+  constexpr int PASSES = TR / RPB > 0 ? TR / RPB : 1;
+  const int64_t ntiles = (n + TR - 1) / TR;
+  const int64_t t = spmm_tile(ntiles, plane_tiles);
+  if (t >= ntiles) return;
+  const int sub = threadIdx.x / LPR, lane = threadIdx.x % LPR;
+  const int64_t plane = (int64_t)nx * ny;
+#pragma unroll
+  for (int pass = 0; pass < PASSES; ++pass) {
+    if (pass * RPB + sub >= TR) continue;
+    const int64_t row = t * TR + pass * RPB + sub;
+    if (row >= n) continue;
+    const uint32_t r32 = (uint32_t)row;
+    const uint32_t i = r32 % (uint32_t)nx, jk = r32 / (uint32_t)nx;
+    const uint32_t j = jk % (uint32_t)ny, k = jk / (uint32_t)ny;
+    int64_t col[7];
+    T v[7];
+    col[0] = k > 0 ? row - plane : row;                v[0] = k > 0 ? off : T(0);
+    col[1] = j > 0 ? row - nx : row;                   v[1] = j > 0 ? off : T(0);
+    col[2] = i > 0 ? row - 1 : row;                    v[2] = i > 0 ? off : T(0);
+    col[3] = row;                                      v[3] = diag[row];
+    col[4] = i + 1 < (uint32_t)nx ? row + 1 : row;     v[4] = i + 1 < (uint32_t)nx ? off : T(0);
+    col[5] = j + 1 < (uint32_t)ny ? row + nx : row;    v[5] = j + 1 < (uint32_t)ny ? off : T(0);
+    col[6] = k + 1 < (uint32_t)nz ? row + plane : row; v[6] = k + 1 < (uint32_t)nz ? off : T(0);
+    T x[7][EPL];
+#pragma unroll
+    for (int u = 0; u < 7; ++u)
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) x[u][e] = gld(W + col[u] * PP + EPL * lane + e);
+    T acc[EPL] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int u = 0; u < 7; ++u)
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) acc[e] += v[u] * x[u][e];
+    const int64_t o = row * PP + EPL * lane;
+    if constexpr (AXPY) {
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        double z = alpha * (double)acc[e] + beta * (double)x[3][e];
+        if (V) z += gamma * (double)gld(V + o + e);
+        gst(Z + o + e, (T)z);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) gst(Z + o + e, acc[e]);
+    }
+  }
+}
+
+// Diagonal of a stencil operator, scaled: out[r] = scale (d + (dv ? dv[r] : 0)).
+template <typename T>
+__global__ void k_stencil_diag(int64_t n, double d, const double* __restrict__ dv, double scale, T* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) out[r] = (T)(scale * (d + (dv ? dv[r] : 0.0)));
+}
+
+// Per-block maxima of the absolute row sums |d + dv[r]| + |off| (number of grid neighbours)
+// and the finiteness flag (4) of dv.
+__global__ void k_stencil_check(int64_t n, int32_t nx, int32_t ny, int32_t nz, double d, double off,
+                                const double* __restrict__ dv, double* __restrict__ partial_max,
+                                int* __restrict__ flags) {
+  __shared__ double red[WG];
+  double m = 0.0;
+  int f = 0;
+  for (int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x; row < n; row += (int64_t)gridDim.x * WG) {
+    const uint32_t r32 = (uint32_t)row;
+    const uint32_t i = r32 % (uint32_t)nx, jk = r32 / (uint32_t)nx;
+    const uint32_t j = jk % (uint32_t)ny, k = jk / (uint32_t)ny;
+    const int deg = (i > 0) + (i + 1 < (uint32_t)nx) + (j > 0) + (j + 1 < (uint32_t)ny) + (k > 0) +
+                    (k + 1 < (uint32_t)nz);
+    const double dr = d + (dv ? dv[row] : 0.0);
+    if (!isfinite(dr)) f |= 4;
+    m = fmax(m, fabs(dr) + fabs(off) * deg);
+  }
+  if (f) atomicOr(flags, f);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = WG / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial_max[blockIdx.x] = red[0];
+}
+
 // Z = a Y + b X over count elements.
 template <typename T>
 __global__ void k_axpby(int64_t count, const T* __restrict__ Y, const T* __restrict__ X, T* __restrict__ Z, double a,
@@ -626,6 +754,84 @@ __global__ __launch_bounds__(WG) void k_gram(int64_t n, const T* __restrict__ A0
         }
     }
   }
+}
+
+// The iteration's two Grams P^T Z and P^T Y at PP = 64: wave w owns the 16 columns
+// 16w .. 16w+15 of P (loaded at the top of each tile, so the loads overlap the staging) and
+// the eight 16 x 16 output blocks (w, q) of both Grams; each wave stages its 16 rows of Z
+// and Y in LDS, from where all four waves read them. Every row of P, Z and Y is read from
+// memory once per workgroup. Rows of a tile past n are the zero padding of the blocks.
+template <typename T, int PP>
+__global__ __launch_bounds__(WG) void k_gram2(int64_t n, const T* __restrict__ A0, const T* __restrict__ A1,
+                                              const T* __restrict__ B1, const T* __restrict__ B2,
+                                              const Scalars* __restrict__ sc, int mode,
+                                              double* __restrict__ partials) {
+  static_assert(PP == 64, "k_gram2 is written for 64 columns");
+  if (spmm_skip(sc, mode)) return;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* sZ = reinterpret_cast<T*>(lds_raw);
+  T* sY = sZ + TR * PP;
+  const T* A = (mode == 1 && (sc->k & 1)) ? A1 : A0;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+  const int64_t ntiles = (n + TR - 1) / TR;
+  int64_t t0, t1;
+  tile_range(ntiles, t0, t1);
+  typename Vec4<T>::type accZ[4], accY[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    accZ[q] = typename Vec4<T>::type{0, 0, 0, 0};
+    accY[q] = typename Vec4<T>::type{0, 0, 0, 0};
+  }
+  // staging: wave w copies rows 16w .. 16w+15 of the tile, 4 rows per step, a lane 4 values
+  constexpr int EPL = 4, LPR = PP / EPL, RPS = 64 / LPR;
+  const int sr = l / LPR, sc4 = (l % LPR) * EPL;
+  for (int64_t t = t0; t < t1; ++t) {
+    const int64_t base = t * TR;
+    T pcol[TR / 4];
+#pragma unroll
+    for (int s = 0; s < TR / 4; ++s) pcol[s] = gld(A + (base + 4 * s + g) * PP + 16 * w + c);
+    // 16-byte pieces: two per lane and row for float64, one for float32
+    typedef typename std::conditional<sizeof(T) == 8, d2, f4>::type V16;
+    constexpr int NV = EPL * (int)sizeof(T) / 16;
+    V16 z[16 / RPS][NV], y[16 / RPS][NV];
+#pragma unroll
+    for (int k = 0; k < 16 / RPS; ++k) {
+      const int r = 16 * w + k * RPS + sr;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        z[k][v] = gld(reinterpret_cast<const V16*>(B1 + (base + r) * PP + sc4) + v);
+        y[k][v] = gld(reinterpret_cast<const V16*>(B2 + (base + r) * PP + sc4) + v);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 16 / RPS; ++k) {
+      const int r = 16 * w + k * RPS + sr;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        reinterpret_cast<V16*>(to_lds(sZ + r * PP + sc4))[v] = z[k][v];
+        reinterpret_cast<V16*>(to_lds(sY + r * PP + sc4))[v] = y[k][v];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < TR / 4; ++s)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int idx = (4 * s + g) * PP + 16 * q + c;
+        accZ[q] = mfma(pcol[s], sZ[idx], accZ[q]);
+        accY[q] = mfma(pcol[s], sY[idx], accY[q]);
+      }
+    __syncthreads();
+  }
+  double* out = partials + (int64_t)blockIdx.x * 2 * PP * PP;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t o = (16 * w + rowof<T>(g, r)) * PP + 16 * q + c;
+      out[o] = (double)accZ[q][r];
+      out[PP * PP + o] = (double)accY[q][r];
+    }
 }
 
 // OUT = IN M (M from the small buffer, PP x PP). IN and OUT may alias.
@@ -834,6 +1040,11 @@ hipError_t set_lds_limits() {
   GSI_SET((k_update<T, PP, false>), Pass::Update)
   GSI_SET((k_update<T, PP, true>), Pass::UpdateGrams)
   GSI_SET((k_product<T, PP>), Pass::Product)
+  if constexpr (PP == 64) {
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_gram2<T, PP>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              2 * TR * PP * (int)sizeof(T));
+  }
 #undef GSI_SET
   return e;
 }
@@ -855,6 +1066,21 @@ void Kernels<T, PP>::spmm_axpy(hipStream_t st, int64_t n, const int32_t* rowptr,
   const int64_t grid = spmm_grid((n + TR - 1) / TR, plane_tiles);
   k_spmm_axpy<T, PP><<<dim3((unsigned)grid), dim3(WG), 0, st>>>(n, rowptr, colind, vals, W, V, Z, alpha, beta, gamma,
                                                                plane_tiles);
+}
+template <typename T, int PP>
+void Kernels<T, PP>::spmm_stencil(hipStream_t st, int64_t n, const int32_t* dims, const T* diag, double off,
+                                  const T* W0, const T* W1, T* Z, const Scalars* sc, int mode, int64_t plane_tiles) {
+  const int64_t grid = spmm_grid((n + TR - 1) / TR, plane_tiles);
+  k_spmm_stencil<T, PP, false><<<dim3((unsigned)grid), dim3(WG), 0, st>>>(
+      n, dims[0], dims[1], dims[2], diag, (T)off, W0, W1, Z, sc, mode, plane_tiles, nullptr, 1.0, 0.0, 0.0);
+}
+template <typename T, int PP>
+void Kernels<T, PP>::spmm_stencil_axpy(hipStream_t st, int64_t n, const int32_t* dims, const T* diag, double off,
+                                       const T* W, const T* V, T* Z, double alpha, double beta, double gamma,
+                                       int64_t plane_tiles) {
+  const int64_t grid = spmm_grid((n + TR - 1) / TR, plane_tiles);
+  k_spmm_stencil<T, PP, true><<<dim3((unsigned)grid), dim3(WG), 0, st>>>(
+      n, dims[0], dims[1], dims[2], diag, (T)off, W, W, Z, nullptr, 0, plane_tiles, V, alpha, beta, gamma);
 }
 template <typename T, int PP>
 void Kernels<T, PP>::spmm_fin(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind,
@@ -888,6 +1114,12 @@ void Kernels<T, PP>::spmm(hipStream_t st, int64_t n, const int32_t* rowptr, cons
 template <typename T, int PP>
 void Kernels<T, PP>::gram(hipStream_t st, int nb, int64_t n, const T* A0, const T* A1, const T* B1, const T* B2,
                           const Scalars* sc, int mode, double* partials) {
+  if constexpr (PP == 64) {
+    if (B2) {
+      k_gram2<T, PP><<<nb, WG, 2 * TR * PP * sizeof(T), st>>>(n, A0, A1, B1, B2, sc, mode, partials);
+      return;
+    }
+  }
   k_gram<T, PP><<<nb, WG, 0, st>>>(n, A0, A1, B1, B2, sc, mode, partials);
 }
 template <typename T, int PP>
@@ -948,6 +1180,17 @@ void launch_csr_check(hipStream_t st, int nb, int64_t n, int64_t nnz, const int3
                       const double* vals, double* partial_max, int* flags, double* partial_band) {
   hipLaunchKernelGGL(k_csr_check, dim3(nb), dim3(WG), 0, st, n, nnz, rowptr, colind, vals, partial_max, flags,
                      partial_band);
+}
+template <typename T>
+void launch_stencil_diag(hipStream_t st, int64_t n, double d, const double* dv, double scale, T* out) {
+  hipLaunchKernelGGL(k_stencil_diag<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, d, dv, scale, out);
+}
+template void launch_stencil_diag<double>(hipStream_t, int64_t, double, const double*, double, double*);
+template void launch_stencil_diag<float>(hipStream_t, int64_t, double, const double*, double, float*);
+void launch_stencil_check(hipStream_t st, int nb, int64_t n, const int32_t* dims, double d, double off,
+                          const double* dv, double* partial_max, int* flags) {
+  hipLaunchKernelGGL(k_stencil_check, dim3(nb), dim3(WG), 0, st, n, dims[0], dims[1], dims[2], d, off, dv,
+                     partial_max, flags);
 }
 void launch_finite(hipStream_t st, int64_t count, const double* x, int* flags) {
   hipLaunchKernelGGL(k_finite, dim3(1024), dim3(256), 0, st, count, x, flags);

@@ -20,7 +20,7 @@ GSI_RSD, GSI_RCG, GSI_SI = 1, 2, 3
 GSI_FP64, GSI_MIXED_FP32, GSI_MIXED_BF16 = 0, 1, 2
 
 EXPORTS = [
-    "gsi_options_default", "gsi_create", "gsi_step", "gsi_solve", "gsi_residuals", "gsi_get_x",
+    "gsi_options_default", "gsi_create", "gsi_create_stencil", "gsi_step", "gsi_solve", "gsi_residuals", "gsi_get_x",
     "gsi_set_x0", "gsi_set_values", "gsi_spmm", "gsi_spmm_lowp", "gsi_history", "gsi_counters", "gsi_pass_times", "gsi_destroy",
     "gsi_status_str", "gsi_last_error", "gsi_create_batched", "gsi_solve_batched", "gsi_batched_results",
     "gsi_batched_get_x", "gsi_batched_set_tuning", "gsi_batched_timeline", "gsi_batched_pass_times", "gsi_batched_last_error", "gsi_destroy_batched",
@@ -31,6 +31,27 @@ PASSES = ["grad", "dir", "spmm", "update", "reduce", "small", "linesearch", "ref
 class GsiCsr(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("rowptr", ctypes.c_void_p),
                 ("colind", ctypes.c_void_p), ("vals", ctypes.c_void_p)]
+
+
+class GsiStencil(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64), ("diag", ctypes.c_double),
+                ("off", ctypes.c_double), ("diag_vec", ctypes.c_void_p)]
+
+
+@dataclass
+class Stencil:
+    """Matrix-free 5/7-point operator: diagonal diag (+ diag_vec[r]), off at each grid
+    neighbour; grid nx x ny x nz, x fastest."""
+    nx: int
+    ny: int = 1
+    nz: int = 1
+    diag: float = 0.0
+    off: float = -1.0
+    diag_vec: object = None  # host array or device tensor of n values, or None
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny * self.nz
 
 
 class GsiOptions(ctypes.Structure):
@@ -59,6 +80,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gsi_options_default.restype = None
     L.gsi_create.argtypes = [P(vp), P(GsiCsr), P(GsiOptions), vp, vp]
     L.gsi_create.restype = ctypes.c_int
+    L.gsi_create_stencil.argtypes = [P(vp), P(GsiStencil), P(GsiOptions), vp, vp]
+    L.gsi_create_stencil.restype = ctypes.c_int
     L.gsi_step.argtypes = [vp, i32]
     L.gsi_step.restype = ctypes.c_int
     L.gsi_solve.argtypes = [vp, P(i32)]
@@ -141,6 +164,27 @@ def gsi_create(rowptr, colind, vals, n: int, X0, opt: GsiOptions, stream=None):
     h = ctypes.c_void_p()
     st = ctypes.c_void_p(stream if stream is not None else torch.cuda.current_stream().cuda_stream)
     s = L.gsi_create(ctypes.byref(h), ctypes.byref(csr), ctypes.byref(opt), ctypes.c_void_p(_dptr(X0)), st)
+    if s != GSI_OK:
+        msg = L.gsi_last_error(h).decode() if h.value else L.gsi_status_str(s).decode()
+        if h.value:
+            L.gsi_destroy(h)
+        raise GsiError(s, msg)
+    return h
+
+
+def gsi_create_stencil(S: Stencil, dvec, X0, opt: GsiOptions, stream=None):
+    """Create a handle for a matrix-free stencil; dvec: float64 device tensor of n values or None."""
+    import torch
+    L = load()
+    if not X0.is_cuda or X0.dtype != torch.float64 or not X0.is_contiguous():
+        raise TypeError("X0 must be a contiguous float64 device tensor")
+    if dvec is not None and (not dvec.is_cuda or dvec.dtype != torch.float64 or dvec.numel() != S.n):
+        raise TypeError("diag_vec must be a float64 device tensor of n values")
+    st_ = GsiStencil(nx=int(S.nx), ny=int(S.ny), nz=int(S.nz), diag=float(S.diag), off=float(S.off),
+                     diag_vec=_dptr(dvec) if dvec is not None else None)
+    h = ctypes.c_void_p()
+    st = ctypes.c_void_p(stream if stream is not None else torch.cuda.current_stream().cuda_stream)
+    s = L.gsi_create_stencil(ctypes.byref(h), ctypes.byref(st_), ctypes.byref(opt), ctypes.c_void_p(_dptr(X0)), st)
     if s != GSI_OK:
         msg = L.gsi_last_error(h).decode() if h.value else L.gsi_status_str(s).decode()
         if h.value:
@@ -238,7 +282,13 @@ class Solver:
 
     def __init__(self, A, X0, p: int, device="cuda", **opts):
         import torch
-        if isinstance(A, tuple):
+        stencil = isinstance(A, Stencil)
+        if stencil:
+            n = A.n
+            dvec = A.diag_vec
+            if dvec is not None and not torch.is_tensor(dvec):
+                dvec = torch.as_tensor(np.ascontiguousarray(dvec, dtype=np.float64), device=device)
+        elif isinstance(A, tuple):
             rowptr, colind, vals, n = A
         else:
             rowptr = torch.as_tensor(np.asarray(A.rowptr, dtype=np.int32), device=device)
@@ -258,7 +308,10 @@ class Solver:
             if b in opts:
                 opts[b] = int(bool(opts[b]))
         self.opt = options(p=self.p, **opts)
-        self.h = gsi_create(rowptr, colind, vals, self.n, X0, self.opt)
+        if stencil:
+            self.h = gsi_create_stencil(A, dvec, X0, self.opt)
+        else:
+            self.h = gsi_create(rowptr, colind, vals, self.n, X0, self.opt)
         self.device = X0.device
 
     def step(self, n_iter: int):
@@ -277,7 +330,10 @@ class Solver:
         return out
 
     def set_x0(self, X0):
-        gsi_set_x0(self.h, X0)
+        import torch
+        if not torch.is_tensor(X0):
+            X0 = torch.as_tensor(np.ascontiguousarray(X0, dtype=np.float64), device=self.device)
+        gsi_set_x0(self.h, X0.contiguous())
 
     def set_values(self, vals):
         """New matrix values (same sparsity pattern); the iteration restarts from the current

@@ -391,3 +391,24 @@ def test_moving_well_sequence_shares_pattern_and_moves():
         assert np.array_equal(A.rowptr, mats[0].rowptr) and np.array_equal(A.colind, mats[0].colind)
     d1 = np.abs(mats[1].vals - mats[0].vals).max()
     assert 0.0 < d1 < 0.2 * np.abs(mats[0].vals).max()
+
+
+def test_stencil_matrix_spectrum_is_the_closed_form():
+    # the Dirichlet Laplacian on an nx x ny x nz grid has the eigenvalues
+    # sum over dimensions of 4 sin^2(k pi / (2 (N + 1))), k = 1 .. N
+    nx, ny, nz = 5, 4, 3
+    A = O.stencil_matrix(nx, ny, nz, 6.0, -1.0).toarray()
+    lam = np.zeros(1)
+    for N in (nx, ny, nz):
+        k = np.arange(1, N + 1)
+        lam = (lam[:, None] + 4.0 * np.sin(k * np.pi / (2.0 * (N + 1))) ** 2).reshape(-1)
+    # the 6 on the diagonal is 2 per dimension
+    assert np.allclose(np.sort(np.linalg.eigvalsh(A)), np.sort(lam), atol=1e-12)
+    # a potential on the diagonal: the trace grows by its sum, the matrix stays symmetric
+    v = np.random.default_rng(0).standard_normal(nx * ny * nz)
+    B = O.stencil_matrix(nx, ny, nz, 6.0, -1.0, v).toarray()
+    assert np.allclose(B, B.T) and np.isclose(np.trace(B) - np.trace(A), v.sum())
+    # 2D with h-scaling: the 5-point operator of the Schroedinger test problems
+    N = 6
+    C = O.stencil_matrix(N, N, 1, 4.0 * (N + 1) ** 2, -(N + 1) ** 2, v[:N * N])
+    assert np.array_equal((C != 0).toarray(), (I.schrodinger_2d(N, None).to_scipy() != 0).toarray())
