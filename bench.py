@@ -150,9 +150,12 @@ def si_leg(args, gsi, torch, rowptr, colind, vals, n, X0, ritz_ref, rcg_spmm):
     lam, lmin = laplacian3d_top(N, p + 16)
     lp = lam[p - 1]
     hi = float(lam[lam < lp - 1e-12 * lp][0])
-    out = {"filter_interval": [float(lmin), hi], "normalized_at": float(lam[0])}
+    out = {"filter_interval": [float(lmin), hi], "normalized_at": float(lam[0]),
+           "budget": "to tol" if args.si_full else f"as many products with A as the RCG solve ({rcg_spmm})"}
     for d in args.si_degrees:
-        s = gsi.Solver((rowptr, colind, vals, n), X0, p, method="si", tol=args.tol, max_iter=5000,
+        # without --si-full: the same number of products with A as RCG used, and the rho reached
+        cap = 5000 if args.si_full else max(1, (rcg_spmm - 1) // d)
+        s = gsi.Solver((rowptr, colind, vals, n), X0, p, method="si", tol=args.tol, max_iter=cap,
                        cheb_degree=d, cheb_lo=float(lmin), cheb_hi=hi, cheb_top=float(lam[0]))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -169,7 +172,7 @@ def si_leg(args, gsi, torch, rowptr, colind, vals, n, X0, ritz_ref, rcg_spmm):
     return out
 
 
-def stencil_leg(args, gsi, torch, X0, t_csr, it_csr, spmm_csr_us):
+def stencil_leg(args, gsi, torch, X0, t_csr, it_csr, spmm_csr_us, csr):
     """The headline solve with the operator applied matrix-free (gsi_create_stencil): same
     matrix, same arithmetic and order, so the same iterates; the SpMM reads the block once
     and no index or value arrays."""
@@ -195,11 +198,21 @@ def stencil_leg(args, gsi, torch, X0, t_csr, it_csr, spmm_csr_us):
     ms, cnt = pt["spmm"]
     avg = ms / max(cnt, 1) * 1e-3
     nbytes = 2 * N ** 3 * p * 8 + N ** 3 * 8
+    # RCG vs RCG(+) measured on the device (the first iterations of an automatic solve)
+    choice = {}
+    for kind, op in (("stencil", S), ("csr", csr)):
+        a = gsi.Solver(op, X0, p, tol=args.tol, max_iter=12, recompute_ax="auto")
+        a.solve()
+        c, m0, m1 = a.recompute_choice()
+        a.close()
+        choice[kind] = {"chosen": "rcg(+)" if c else "rcg", "ms_per_iter_rcg": round(m0, 3),
+                        "ms_per_iter_rcg_plus": round(m1, 3)}
+        log(f"recompute choice {kind}: {choice[kind]}")
     value = float(np.mean(times))
     return {"s": round(value, 4), "iters": iters, "same_iters_as_csr": iters == it_csr,
             "speedup_vs_csr": round(t_csr / value, 3), "spmm_us": round(avg * 1e6, 1),
             "spmm_csr_us": round(spmm_csr_us, 1), "spmm_GBps": round(nbytes / avg / 1e9, 1),
-            "spmm_bytes": nbytes}
+            "spmm_bytes": nbytes, "recompute_choice": choice}
 
 
 def batched_leg(args, gsi, inputs, torch):
@@ -287,6 +300,8 @@ def main():
     ap.add_argument("--no-si", action="store_true",
                     help="skip the Chebyshev-filtered subspace iteration on the headline workload")
     ap.add_argument("--si-degrees", type=int, nargs="*", default=[64, 128])
+    ap.add_argument("--si-full", action="store_true",
+                    help="run the Chebyshev-filtered subspace iteration to the tolerance")
     ap.add_argument("--no-stencil", action="store_true",
                     help="skip the matrix-free stencil solve of the headline workload")
     ap.add_argument("--warm-train", type=int, default=144)
@@ -401,7 +416,8 @@ def main():
 
     stencil = None
     if not args.no_stencil:
-        stencil = stencil_leg(args, gsi, torch, X0, float(np.mean(t64)), it64, kern["spmm"]["avg_us"])
+        stencil = stencil_leg(args, gsi, torch, X0, float(np.mean(t64)), it64, kern["spmm"]["avg_us"],
+                              (rowptr, colind, vals, A.n))
 
     si = None
     if not args.no_si and args.si_degrees:

@@ -79,6 +79,16 @@ typedef struct {
   const double* vals;    /* nnz */
 } gsi_csr;
 
+/* A complex Hermitian matrix in CSR form: vals holds nnz complex values as interleaved
+ * (real, imaginary) float64 pairs; the full matrix is stored (both triangles). */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int32_t* rowptr; /* n + 1 */
+  const int32_t* colind; /* nnz, sorted within each row */
+  const double* vals;    /* 2 nnz */
+} gsi_zcsr;
+
 /* A 5- or 7-point stencil operator on an nx x ny x nz grid of nodes in lexicographic order
  * (x fastest; ny = nz = 1 for a 1D grid, nz = 1 for 2D), applied without index or value
  * arrays: row r has diag + diag_vec[r] on the diagonal and off at each neighbour inside the
@@ -98,7 +108,9 @@ typedef struct {
   int32_t method;       /* gsi_method */
   int32_t precision;    /* gsi_precision */
   int32_t recompute_ax; /* 0: A X by the recursion of Sec. 6.1; 1: A X formed every iteration
-                           (the RCG(+) variant of Sec. 6.4) */
+                           (the RCG(+) variant of Sec. 6.4); -1: automatic, each solve times
+                           a few iterations of both on the device and keeps the faster
+                           (gsi_recompute_choice reports the outcome) */
   int32_t k_restart;    /* restart the CG direction every k_restart iterations (0 = never) */
   int32_t max_iter;     /* iteration cap (accepted steps) */
   double tol;           /* stop when rho = ||G||_F / (sqrt(p) ||A||_inf) <= tol */
@@ -142,6 +154,38 @@ gsi_status gsi_create(gsi_handle* h, const gsi_csr* A, const gsi_options* opt, c
  * handle takes n new diag_vec values. GSI_MIXED_BF16 is not supported (GSI_EUNSUPPORTED). */
 gsi_status gsi_create_stencil(gsi_handle* h, const gsi_stencil* S, const gsi_options* opt, const double* X0,
                               void* hip_stream);
+
+/* Complex Hermitian variant (the extension the paper notes for Hermitian A: the iteration
+ * with conjugate transposes on phi(X) = -1/2 Re Tr(X^H A X), X^H X = I). A is held as its
+ * real symmetric embedding [[Re A, -Im A], [Im A, Re A]] (2n x 2n) and X as the 2n x 2p real
+ * block [[Re X, -Im X], [Im X, Re X]]: the real iteration on this block spans the embedding
+ * of the complex iterate at every step (phi and the real inner product of the embedding are
+ * twice the complex ones, so the step sizes and Polak-Ribiere coefficients are the same), at
+ * twice the memory traffic of native complex arithmetic. opt->p is the number of complex
+ * columns, 1 <= p <= 32; X0: device array of n x p complex values (interleaved, row-major).
+ * The stopping test uses ||A_emb||_inf (the max over rows of sum |Re a| + |Im a|). Other
+ * calls (gsi_solve, gsi_step, gsi_history, gsi_counters) act on the embedded problem; read
+ * results with gsi_hermitian_results. Builds the embedding on the host (copies A and X0 out
+ * and back); syncs. Errors as gsi_create; p > 32 gives GSI_EUNSUPPORTED. */
+gsi_status gsi_create_hermitian(gsi_handle* h, const gsi_zcsr* A, const gsi_options* opt, const double* X0,
+                                void* hip_stream);
+
+/* Rayleigh-Ritz of a Hermitian handle's iterate: ritz (host, p; nullable) the Ritz values
+ * of A, largest first for which = +1, smallest first for -1; Xc (device, n x p complex
+ * interleaved; nullable) the Ritz vectors; rho (host, nullable) the residual measure. Each
+ * eigenvalue of the embedding is a complex eigenvalue twice, with the pair's real vectors
+ * spanning one complex vector; column j of Xc is the first vector of pair j read as
+ * complex. A complex eigenvalue of multiplicity above one inside the block has a
+ * four-dimensional real eigenspace whose Ritz vectors need not pair up this way, so such
+ * blocks should be cut between distinct eigenvalues. Syncs. */
+gsi_status gsi_hermitian_results(gsi_handle h, double* ritz, double* Xc, double* rho);
+
+/* The variant an automatic solve (recompute_ax = -1) chose: *recompute_ax 0 (recursion) or
+ * 1 (RCG(+)), and the measured milliseconds per iteration of each (0 until a solve ran the
+ * trial; a handle created with recompute_ax >= 0 reports its fixed choice). Sec. 6.4 finds
+ * RCG(+) the cheaper one when a product with A costs less than the recursion's extra block
+ * traffic, i.e. for very sparse A; the trial measures that on the actual matrix. */
+gsi_status gsi_recompute_choice(gsi_handle h, int32_t* recompute_ax, double* ms_recursion, double* ms_recompute);
 
 /* Enqueue n_iter iterations (fewer if the convergence flag is raised on the device;
  * the remaining launches return immediately). Asynchronous. */

@@ -451,3 +451,95 @@ def stencil_matrix(nx: int, ny: int = 1, nz: int = 1, diag: float = 0.0, off: fl
         cols += [a + step, a]
         vals += [np.full(a.size, float(off))] * 2
     return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+
+
+# ----------------------------------------------------------------------------- complex Hermitian
+
+def principal_angles_complex(X: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """Principal angles between the complex column spans of orthonormal X and Y (the
+    Sec. 4.2 definition with conjugate transposes), ascending."""
+    c = np.sort(np.linalg.svd(Y.conj().T @ X, compute_uv=False))[::-1]
+    s = np.sort(np.linalg.svd(X - Y @ (Y.conj().T @ X), compute_uv=False))
+    return np.arctan2(s, c)
+
+
+def rcg_hermitian(A, X0, tol: float = 1e-10, max_iter: int = 10000, method: str = "rcg", which: int = 1,
+                  refresh_threshold: float = 1e3) -> SolveResult:
+    """The complex Hermitian variant of RSD / RCG with exact line search: the steps of
+    Algorithms 2 and 4 with every transpose a conjugate transpose (the extension the paper
+    states for Hermitian A), on phi(X) = -1/2 Re Tr(X^H A X) over n x p complex X with
+    X^H X = I and the real inner product <U, V> = Re Tr(U^H V) (which makes the Polak-Ribiere
+    beta and the descent test real). The line-search model keeps its form with
+    alpha = diag(V^H C V), gamma = diag(V^H (P^H A P) V), zeta = -Re diag(V^H (P^H A X) V),
+    P^H P = V D_beta V^H; the retraction is (X - mu P) V D_mu^{-1} V^H. rho uses the max
+    absolute row sum of the complex entries."""
+    A = as_operator(A)
+    A_op = A if which > 0 else -A
+    X, _ = np.linalg.qr(np.asarray(X0, dtype=np.complex128))
+    n, p = X.shape
+    nA = norm_inf(A)
+    herm = lambda M: 0.5 * (M + M.conj().T)
+    tang = lambda D: D - X @ (X.conj().T @ D)
+    rip = lambda U, V: float(np.real(np.vdot(U, V)))
+    Y = A_op @ X
+    res = SolveResult(X=X, theta=np.zeros(p), iters=0, converged=False, spmm=1)
+    G_old = P_old = None
+    k = 0
+    while True:
+        C = herm(X.conj().T @ Y)
+        G = -(Y - X @ C)
+        gg = rip(G, G)
+        rho = np.sqrt(gg) / (np.sqrt(p) * nA)
+        res.rho.append(rho)
+        res.phi.append(-0.5 * float(np.real(np.trace(C))))
+        if rho <= tol:
+            res.converged = True
+            break
+        if k >= max_iter:
+            break
+        restart = method == "rsd" or k == 0
+        beta_pr = 0.0
+        if not restart:
+            den = rip(G_old, G_old)
+            beta_pr = (gg - rip(G_old, G)) / den if den > 0.0 else 0.0
+            P = tang(G + beta_pr * P_old)
+            if rip(G, P) <= 0.0:
+                restart, beta_pr = True, 0.0
+        if restart:
+            P = tang(G)
+        Z = A_op @ P
+        res.spmm += 1
+        while True:
+            b, V = np.linalg.eigh(herm(P.conj().T @ P))
+            b = np.maximum(b, 0.0)
+            VH = V.conj().T
+            alpha = np.real(np.diag(VH @ C @ V))
+            gamma = np.real(np.diag(VH @ herm(P.conj().T @ Z) @ V))
+            zeta = -np.real(np.diag(VH @ (P.conj().T @ Y) @ V))
+            mr = get_mu(alpha, b, gamma, zeta)
+            if mr.ok or restart:
+                break
+            P, restart, beta_pr = tang(G), True, 0.0
+            Z = A_op @ P
+            res.spmm += 1
+        if not mr.ok:
+            break
+        mu = mr.mu
+        res.mu.append(mu)
+        res.beta_pr.append(beta_pr)
+        res.restarts.append(bool(restart))
+        M = (V * (1.0 / np.sqrt(1.0 + mu * mu * b))) @ VH
+        X = (X - mu * P) @ M
+        if mu * np.sqrt(b.max()) <= refresh_threshold * EPS:
+            Y = A_op @ X
+            res.spmm += 1
+        else:
+            Y = (Y - mu * Z) @ M
+        G_old, P_old = G, P
+        k += 1
+    res.iters = k
+    w, U = np.linalg.eigh(herm(X.conj().T @ (A_op @ X)))
+    w, U = w[::-1], U[:, ::-1]
+    res.X = X @ U
+    res.theta = w if which > 0 else -w
+    return res

@@ -1165,6 +1165,7 @@ gsi_status gsi_create_batched(gsi_batch_handle* out, int32_t count, const gsi_cs
   if (opt->which != 1 && opt->which != -1) { b->err = "which must be +1 or -1"; return GSI_EINVAL; }
   if (opt->precision != GSI_FP64 && opt->precision != GSI_MIXED_FP32) { b->err = "unknown precision"; return GSI_EINVAL; }
   if (opt->method != GSI_RSD && opt->method != GSI_RCG) { b->err = "batched solves run RSD or RCG"; return GSI_EINVAL; }
+  if (opt->recompute_ax != 0 && opt->recompute_ax != 1) { b->err = "recompute_ax must be 0 or 1"; return GSI_EINVAL; }
   for (int i = 0; i < count; ++i) {
     if (p[i] < 1 || p[i] > 32 || p[i] >= A[i].n || !A[i].rowptr || !A[i].colind || !A[i].vals || !X0[i]) {
       b->err = "problem " + std::to_string(i) + ": need 1 <= p <= 32, p < n and device arrays";

@@ -110,6 +110,12 @@ struct gsi_ctx {
   int64_t plane_tiles = 0;  // banded SpMM tile order (0: one slab per XCD)
   // matrix-free stencil operator (gsi_create_stencil): grid, neighbour weight (times the
   // sign of which); the engines' vals hold the n diagonal entries
+  // RCG or RCG(+) (A X by the recursion or formed every iteration): recompute_ax = -1 lets
+  // the first iterations of each solve time both and keep the faster
+  int rax = 0;
+  bool rax_pending = false;
+  double rax_ms[2] = {0.0, 0.0};
+  int hermitian_p = 0;  // > 0: a Hermitian problem of this many complex columns, held as its real embedding
   bool stencil = false;
   int32_t sdims[3] = {1, 1, 1};
   double sdiag = 0.0, soff = 0.0;
@@ -281,7 +287,7 @@ gsi_status init_state(gsi_ctx* h, Engine<T>& e, double tol, int max_iter, int hi
 // One iteration's launch sequence.
 template <typename T>
 void launch_iteration(gsi_ctx* h, Engine<T>& e, double* hist) {
-  const int recompute = h->opt.recompute_ax;
+  const int recompute = h->rax;
   dispatch_pp<T>(e.PP, [&](auto PPc) {
     constexpr int PP = decltype(PPc)::value;
     const int64_t P2 = (int64_t)PP * PP;
@@ -398,9 +404,44 @@ void reorthonormalize(gsi_ctx* h, Engine<T>& e) {
   });
 }
 
+// Automatic choice between the A X recursion and RCG(+): one iteration to warm up, then
+// `trial` iterations of each variant timed with events on the solver's stream (launched
+// directly, the same way for both); the faster is kept for the rest of the solve. All
+// these iterations are iterations of the solve.
+template <typename T>
+gsi_status choose_recompute(gsi_ctx* h, Engine<T>& e, double* hist) {
+  const int trial = 3;
+  hipEvent_t ev[3];
+  for (auto& x : ev)
+    if (hipEventCreate(&x) != hipSuccess) return fail(h, GSI_EDEVICE, "event creation failed");
+  e.destroy_graph();
+  h->rax = 0;
+  launch_iteration(h, e, hist);
+  (void)hipEventRecord(ev[0], h->st);
+  for (int i = 0; i < trial; ++i) launch_iteration(h, e, hist);
+  (void)hipEventRecord(ev[1], h->st);
+  h->rax = 1;
+  for (int i = 0; i < trial; ++i) launch_iteration(h, e, hist);
+  (void)hipEventRecord(ev[2], h->st);
+  gsi_status s = hip_check(h, hipEventSynchronize(ev[2]), "recompute trial");
+  float a = 0.f, b = 0.f;
+  if (s == GSI_OK) {
+    (void)hipEventElapsedTime(&a, ev[0], ev[1]);
+    (void)hipEventElapsedTime(&b, ev[1], ev[2]);
+    h->rax_ms[0] = a / trial;
+    h->rax_ms[1] = b / trial;
+    h->rax = b < a ? 1 : 0;
+  }
+  for (auto& x : ev) (void)hipEventDestroy(x);
+  h->rax_pending = false;
+  e.destroy_graph();
+  return s;
+}
+
 template <typename T>
 gsi_status run_until_done(gsi_ctx* h, Engine<T>& e, double* hist, Scalars* out, bool reorth = false,
                           bool verify = false) {
+  if (h->rax_pending && !h->timing) GSI_TRY(choose_recompute(h, e, hist));
   // in timing mode poll every iteration so that no launch after convergence is timed
   const int every = h->timing ? 1 : (h->opt.check_every > 0 ? h->opt.check_every : 25);
   for (;;) {
@@ -612,6 +653,8 @@ gsi_status start(gsi_ctx* h, const double* X0) {
   h->e64.P32 = nullptr;
   h->si_k = h->si_spmm = h->si_done = 0;
   h->si_rho.clear();
+  h->rax = h->opt.recompute_ax > 0 ? 1 : 0;
+  h->rax_pending = h->opt.recompute_ax < 0;
   h->low_iters = h->low_spmm = h->low_restarts = h->low_refresh = h->low_null = h->low_sweeps = 0;
   h->hist_off = 0;
   if (h->mixed) {
@@ -855,6 +898,109 @@ gsi_status gsi_create_stencil(gsi_handle* out, const gsi_stencil* S, const gsi_o
   return create_impl(out, nullptr, S, opt, X0, stream);
 }
 
+gsi_status gsi_create_hermitian(gsi_handle* out, const gsi_zcsr* A, const gsi_options* opt, const double* X0,
+                                void* stream) {
+  if (!out || !A || !opt || !X0) return GSI_EINVAL;
+  *out = nullptr;
+  if (A->n < 1 || A->nnz < 1 || !A->rowptr || !A->colind || !A->vals) return GSI_EINVAL;
+  if (opt->p < 1 || 2 * opt->p > MAXP) return GSI_EUNSUPPORTED;
+  if (A->n >= (int64_t)INT32_MAX / 2 || 4 * A->nnz >= (int64_t)INT32_MAX) return GSI_EUNSUPPORTED;
+  const int64_t n = A->n, nnz = A->nnz;
+  const int p = opt->p;
+  // the real embedding [[Re A, -Im A], [Im A, Re A]] and [[Re X0, -Im X0], [Im X0, Re X0]],
+  // built on the host from copies of the device arrays (rows stay sorted: the left block's
+  // columns precede the right block's; imaginary parts that are zero are not stored)
+  std::vector<int32_t> rp(n + 1), ci(nnz);
+  std::vector<double> va(2 * nnz), x0(2 * n * p);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (hipStreamSynchronize(st) != hipSuccess ||
+      hipMemcpy(rp.data(), A->rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(ci.data(), A->colind, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(va.data(), A->vals, sizeof(double) * 2 * nnz, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(x0.data(), X0, sizeof(double) * 2 * n * p, hipMemcpyDeviceToHost) != hipSuccess)
+    return GSI_EDEVICE;
+  if (rp[0] != 0 || rp[n] != nnz) return GSI_EINVAL;
+  for (int64_t r = 0; r < n; ++r)
+    if (rp[r + 1] < rp[r]) return GSI_EINVAL;
+  std::vector<int32_t> erp(2 * n + 1), eci;
+  std::vector<double> eva;
+  eci.reserve(4 * nnz);
+  eva.reserve(4 * nnz);
+  erp[0] = 0;
+  for (int half = 0; half < 2; ++half)
+    for (int64_t r = 0; r < n; ++r) {
+      // left block: Re A (top) / Im A (bottom); right block: -Im A (top) / Re A (bottom)
+      for (int blk = 0; blk < 2; ++blk)
+        for (int32_t j = rp[r]; j < rp[r + 1]; ++j) {
+          const double re = va[2 * j], im = va[2 * j + 1];
+          const double v = half == 0 ? (blk == 0 ? re : -im) : (blk == 0 ? im : re);
+          const bool real_part = (half == 0) == (blk == 0);
+          if (!real_part && v == 0.0) continue;
+          eci.push_back((int32_t)(blk * n + ci[j]));
+          eva.push_back(v);
+        }
+      erp[half * n + r + 1] = (int32_t)eci.size();
+    }
+  std::vector<double> ex((size_t)2 * n * 2 * p);
+  for (int64_t r = 0; r < n; ++r)
+    for (int j = 0; j < p; ++j) {
+      const double re = x0[2 * (r * p + j)], im = x0[2 * (r * p + j) + 1];
+      ex[r * 2 * p + j] = re;
+      ex[r * 2 * p + p + j] = -im;
+      ex[(n + r) * 2 * p + j] = im;
+      ex[(n + r) * 2 * p + p + j] = re;
+    }
+  int32_t *drp = nullptr, *dci = nullptr;
+  double *dva = nullptr, *dx = nullptr;
+  gsi_status s = GSI_OK;
+  if (hipMalloc(&drp, sizeof(int32_t) * erp.size()) != hipSuccess ||
+      hipMalloc(&dci, sizeof(int32_t) * eci.size()) != hipSuccess ||
+      hipMalloc(&dva, sizeof(double) * eva.size()) != hipSuccess ||
+      hipMalloc(&dx, sizeof(double) * ex.size()) != hipSuccess)
+    s = GSI_ENOMEM;
+  if (s == GSI_OK &&
+      (hipMemcpy(drp, erp.data(), sizeof(int32_t) * erp.size(), hipMemcpyHostToDevice) != hipSuccess ||
+       hipMemcpy(dci, eci.data(), sizeof(int32_t) * eci.size(), hipMemcpyHostToDevice) != hipSuccess ||
+       hipMemcpy(dva, eva.data(), sizeof(double) * eva.size(), hipMemcpyHostToDevice) != hipSuccess ||
+       hipMemcpy(dx, ex.data(), sizeof(double) * ex.size(), hipMemcpyHostToDevice) != hipSuccess))
+    s = GSI_EDEVICE;
+  if (s == GSI_OK) {
+    gsi_csr E;
+    E.n = 2 * n;
+    E.nnz = (int64_t)eci.size();
+    E.rowptr = drp;
+    E.colind = dci;
+    E.vals = dva;
+    gsi_options o2 = *opt;
+    o2.p = 2 * p;
+    s = create_impl(out, &E, nullptr, &o2, dx, stream);
+    if (*out) {
+      (*out)->hermitian_p = p;
+      (void)hipStreamSynchronize((*out)->st);
+    }
+  }
+  (void)hipDeviceSynchronize();
+  for (void* q : {(void*)drp, (void*)dci, (void*)dva, (void*)dx})
+    if (q) (void)hipFree(q);
+  return s;
+}
+
+gsi_status gsi_hermitian_results(gsi_handle h, double* ritz, double* Xc, double* rho) {
+  if (!h) return GSI_EINVAL;
+  if (h->hermitian_p <= 0) return fail(h, GSI_EUNSUPPORTED, "not a Hermitian handle");
+  const int pc = h->hermitian_p;
+  std::vector<double> r2(2 * pc);
+  GSI_TRY(gsi_residuals(h, r2.data(), nullptr, rho, nullptr));
+  // every eigenvalue of the embedding appears twice; the Ritz pairs are adjacent
+  if (ritz)
+    for (int j = 0; j < pc; ++j) ritz[j] = r2[2 * j];
+  if (Xc) {
+    launch_complex_extract(h->st, h->n / 2, pc, h->PP, h->e64.X, Xc);
+    GSI_TRY(hip_check(h, hipStreamSynchronize(h->st), "complex basis"));
+  }
+  return GSI_OK;
+}
+
 gsi_status gsi_step(gsi_handle h, int32_t n_iter) {
   if (!h || n_iter < 0) return GSI_EINVAL;
   if (h->opt.method == GSI_SI) return si_iterate(h, n_iter);
@@ -986,6 +1132,14 @@ gsi_status gsi_set_values(gsi_handle h, const double* vals) {
     if (h->bf16) launch_to_bf16(st, h->nnz, vals, h->e32.vals16, sign);
   }
   return start(h, h->e64.G0);
+}
+
+gsi_status gsi_recompute_choice(gsi_handle h, int32_t* recompute_ax, double* ms_recursion, double* ms_recompute) {
+  if (!h) return GSI_EINVAL;
+  if (recompute_ax) *recompute_ax = h->rax;
+  if (ms_recursion) *ms_recursion = h->rax_ms[0];
+  if (ms_recompute) *ms_recompute = h->rax_ms[1];
+  return GSI_OK;
 }
 
 gsi_status gsi_spmm(gsi_handle h, const double* W, double* Z) {

@@ -70,6 +70,7 @@ void launch_csr_check(hipStream_t st, int nb, int64_t n, int64_t nnz, const int3
                       const double* vals, double* partial_max, int* flags,
                       double* partial_band = nullptr);
 void launch_finite(hipStream_t st, int64_t count, const double* x, int* flags);
+void launch_complex_extract(hipStream_t st, int64_t n, int pc, int PP, const double* X, double* out);
 template <typename T>
 void launch_stencil_diag(hipStream_t st, int64_t n, double d, const double* dv, double scale, T* out);
 void launch_stencil_check(hipStream_t st, int nb, int64_t n, const int32_t* dims, double d, double off,

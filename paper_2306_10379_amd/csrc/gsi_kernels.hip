@@ -943,6 +943,18 @@ __global__ void k_unpack(int64_t n, int p, int PP, const T* __restrict__ src, do
   dst[i] = (double)src[(i / p) * PP + (i % p)];
 }
 
+// Complex basis from the real embedding of a Hermitian problem: column j of the n x pc
+// complex output (interleaved re, im) is column 2j of the 2n x 2pc real block X (padded
+// width PP) read as top half + i bottom half.
+__global__ void k_complex_extract(int64_t n, int pc, int PP, const double* __restrict__ X, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * pc) return;
+  const int64_t r = i / pc;
+  const int j = (int)(i % pc);
+  out[2 * i] = X[r * PP + 2 * j];
+  out[2 * i + 1] = X[(n + r) * PP + 2 * j];
+}
+
 template <typename TS, typename TD>
 __global__ void k_convert(int64_t count, const TS* __restrict__ src, TD* __restrict__ dst, double scale) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1191,6 +1203,11 @@ void launch_stencil_check(hipStream_t st, int nb, int64_t n, const int32_t* dims
                           const double* dv, double* partial_max, int* flags) {
   hipLaunchKernelGGL(k_stencil_check, dim3(nb), dim3(WG), 0, st, n, dims[0], dims[1], dims[2], d, off, dv,
                      partial_max, flags);
+}
+void launch_complex_extract(hipStream_t st, int64_t n, int pc, int PP, const double* X, double* out) {
+  const int64_t count = n * pc;
+  if (count > 0)
+    hipLaunchKernelGGL(k_complex_extract, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, n, pc, PP, X, out);
 }
 void launch_finite(hipStream_t st, int64_t count, const double* x, int* flags) {
   hipLaunchKernelGGL(k_finite, dim3(1024), dim3(256), 0, st, count, x, flags);

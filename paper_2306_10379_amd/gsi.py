@@ -20,7 +20,7 @@ GSI_RSD, GSI_RCG, GSI_SI = 1, 2, 3
 GSI_FP64, GSI_MIXED_FP32, GSI_MIXED_BF16 = 0, 1, 2
 
 EXPORTS = [
-    "gsi_options_default", "gsi_create", "gsi_create_stencil", "gsi_step", "gsi_solve", "gsi_residuals", "gsi_get_x",
+    "gsi_options_default", "gsi_create", "gsi_create_stencil", "gsi_create_hermitian", "gsi_hermitian_results", "gsi_recompute_choice", "gsi_step", "gsi_solve", "gsi_residuals", "gsi_get_x",
     "gsi_set_x0", "gsi_set_values", "gsi_spmm", "gsi_spmm_lowp", "gsi_history", "gsi_counters", "gsi_pass_times", "gsi_destroy",
     "gsi_status_str", "gsi_last_error", "gsi_create_batched", "gsi_solve_batched", "gsi_batched_results",
     "gsi_batched_get_x", "gsi_batched_set_tuning", "gsi_batched_timeline", "gsi_batched_pass_times", "gsi_batched_last_error", "gsi_destroy_batched",
@@ -29,6 +29,11 @@ PASSES = ["grad", "dir", "spmm", "update", "reduce", "small", "linesearch", "ref
 
 
 class GsiCsr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("rowptr", ctypes.c_void_p),
+                ("colind", ctypes.c_void_p), ("vals", ctypes.c_void_p)]
+
+
+class GsiZcsr(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("rowptr", ctypes.c_void_p),
                 ("colind", ctypes.c_void_p), ("vals", ctypes.c_void_p)]
 
@@ -82,6 +87,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gsi_create.restype = ctypes.c_int
     L.gsi_create_stencil.argtypes = [P(vp), P(GsiStencil), P(GsiOptions), vp, vp]
     L.gsi_create_stencil.restype = ctypes.c_int
+    L.gsi_create_hermitian.argtypes = [P(vp), P(GsiZcsr), P(GsiOptions), vp, vp]
+    L.gsi_create_hermitian.restype = ctypes.c_int
+    L.gsi_hermitian_results.argtypes = [vp, P(dbl), vp, P(dbl)]
+    L.gsi_hermitian_results.restype = ctypes.c_int
+    L.gsi_recompute_choice.argtypes = [vp, P(i32), P(dbl), P(dbl)]
+    L.gsi_recompute_choice.restype = ctypes.c_int
     L.gsi_step.argtypes = [vp, i32]
     L.gsi_step.restype = ctypes.c_int
     L.gsi_solve.argtypes = [vp, P(i32)]
@@ -304,7 +315,11 @@ class Solver:
         opts["precision"] = {"fp64": GSI_FP64, "mixed": GSI_MIXED_FP32, "fp32": GSI_MIXED_FP32,
                              "bf16": GSI_MIXED_BF16}[precision] \
             if isinstance(precision, str) else precision
-        for b in ("recompute_ax", "use_graph", "explicit_c"):
+        if opts.get("recompute_ax") == "auto":
+            opts["recompute_ax"] = -1
+        elif "recompute_ax" in opts and opts["recompute_ax"] != -1:
+            opts["recompute_ax"] = int(bool(opts["recompute_ax"]))
+        for b in ("use_graph", "explicit_c"):
             if b in opts:
                 opts[b] = int(bool(opts[b]))
         self.opt = options(p=self.p, **opts)
@@ -356,6 +371,12 @@ class Solver:
         gsi_spmm_lowp(self.h, W.contiguous(), Z)
         torch.cuda.synchronize()
         return Z
+
+    def recompute_choice(self):
+        """(recompute_ax chosen, ms per iteration with the recursion, ms with RCG(+))."""
+        r, a, b = ctypes.c_int32(), ctypes.c_double(), ctypes.c_double()
+        _check(self.h, load().gsi_recompute_choice(self.h, ctypes.byref(r), ctypes.byref(a), ctypes.byref(b)))
+        return r.value, a.value, b.value
 
     def history(self, capacity: int | None = None):
         return gsi_history(self.h, capacity or (self.opt.max_iter + 2))
@@ -527,3 +548,59 @@ class BatchedSolver:
                 self.close()
         except Exception:
             pass
+
+
+class HermitianSolver(Solver):
+    """Complex Hermitian problem (gsi_create_hermitian). A: scipy sparse complex matrix (host;
+    copied to the device), X0: n x p complex host array or complex128 device tensor. run()
+    returns (status, iters, ritz (p,), X (n x p complex128 device tensor), rho)."""
+
+    def __init__(self, A, X0, p: int, device="cuda", **opts):
+        import torch
+        import scipy.sparse as sps
+        A = sps.csr_matrix(A)
+        A.sort_indices()
+        n = A.shape[0]
+        self._rowptr = torch.as_tensor(A.indptr.astype(np.int32), device=device)
+        self._colind = torch.as_tensor(A.indices.astype(np.int32), device=device)
+        self._vals = torch.as_tensor(np.ascontiguousarray(A.data.astype(np.complex128)).view(np.float64),
+                                     device=device)
+        if torch.is_tensor(X0):
+            X0r = torch.view_as_real(X0.contiguous()).contiguous()
+        else:
+            X0r = torch.as_tensor(np.ascontiguousarray(np.asarray(X0, dtype=np.complex128)).view(np.float64),
+                                  device=device)
+        method = opts.pop("method", "rcg")
+        opts["method"] = {"rsd": GSI_RSD, "rcg": GSI_RCG}[method] if isinstance(method, str) else method
+        for b in ("use_graph", "explicit_c"):
+            if b in opts:
+                opts[b] = int(bool(opts[b]))
+        self.n, self.p = int(n), int(p)
+        self.opt = options(p=self.p, **opts)
+        L = load()
+        z = GsiZcsr(n=self.n, nnz=int(A.nnz), rowptr=_dptr(self._rowptr), colind=_dptr(self._colind),
+                    vals=_dptr(self._vals))
+        h = ctypes.c_void_p()
+        st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        s = L.gsi_create_hermitian(ctypes.byref(h), ctypes.byref(z), ctypes.byref(self.opt),
+                                   ctypes.c_void_p(_dptr(X0r)), st)
+        if s != GSI_OK:
+            msg = L.gsi_last_error(h).decode() if h.value else L.gsi_status_str(s).decode()
+            if h.value:
+                L.gsi_destroy(h)
+            raise GsiError(s, msg)
+        self.h = h
+        self.device = self._rowptr.device
+
+    def results(self):
+        import torch
+        ritz = (ctypes.c_double * self.p)()
+        rho = ctypes.c_double()
+        X = torch.empty((self.n, self.p, 2), dtype=torch.float64, device=self.device)
+        _check(self.h, load().gsi_hermitian_results(self.h, ritz, ctypes.c_void_p(_dptr(X)), ctypes.byref(rho)))
+        return np.array(ritz[:]), torch.view_as_complex(X), rho.value
+
+    def run(self):
+        status, iters = self.solve()
+        ritz, X, rho = self.results()
+        return status, iters, ritz, X, rho

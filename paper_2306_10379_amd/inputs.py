@@ -174,6 +174,32 @@ def moving_well_sequence(N: int, steps: int, seed: int = 0, depth: float = -15.0
     return mats
 
 
+def magnetic_lattice(N: int, flux: float = 0.1, seed: int = 0, disorder: float = 0.5):
+    """Complex Hermitian test operator: the 5-point Laplacian on an N x N grid with Peierls
+    phases of a uniform magnetic field (Landau gauge: the bond (x, y) -> (x + 1, y) carries
+    exp(2 pi i flux y)), plus a random on-site potential U(-disorder, disorder) that lifts
+    degeneracies. Returns a scipy CSR complex128 matrix, sorted indices."""
+    import scipy.sparse as sps
+    g = rng(seed)
+    n = N * N
+    idx = np.arange(n)
+    x, y = idx % N, idx // N
+    rows, cols, vals = [idx], [idx], [4.0 + g.uniform(-disorder, disorder, n)]
+    ok = x < N - 1
+    t = -np.exp(2j * np.pi * flux * y[ok])
+    rows += [idx[ok], idx[ok] + 1]
+    cols += [idx[ok] + 1, idx[ok]]
+    vals += [t, np.conj(t)]
+    ok = y < N - 1
+    rows += [idx[ok], idx[ok] + N]
+    cols += [idx[ok] + N, idx[ok]]
+    vals += [-np.ones(ok.sum()), -np.ones(ok.sum())]
+    A = sps.csr_matrix((np.concatenate(vals).astype(np.complex128), (np.concatenate(rows), np.concatenate(cols))),
+                       shape=(n, n))
+    A.sort_indices()
+    return A
+
+
 def schrodinger_batch(count: int = 512, seed: int = 2024, sides: tuple[int, int] = (32, 160),
                       blocks: tuple[int, int] = (4, 32), wells: tuple[int, int] = (1, 6)):
     """A batch of 2D Schroedinger operators H = -Laplacian + V of uneven sizes: grid side N

@@ -132,3 +132,23 @@ def test_stencil_rejects_bad_arguments():
         gsi.Solver(gsi.Stencil(8, 8, 1, diag=4.0, off=-1.0, diag_vec=np.full(64, np.inf)), X0, 4)
     with pytest.raises(gsi.GsiError):
         gsi.Solver(gsi.Stencil(0, 8, 1, diag=4.0, off=-1.0), X0, 4)
+
+
+@pytest.mark.parametrize("kind", ["stencil", "csr"])
+def test_automatic_recompute_choice_times_both_and_converges(kind):
+    gsi = _gsi()
+    N, p = 40, 8
+    S = gsi.Stencil(N, N, 1, diag=4.0, off=-1.0)
+    A, M = _csr_of(S)
+    X0 = I.start_block(N * N, p, 4)
+    print(f"auto recompute {kind}", flush=True)
+    ref = O.rcg(M, X0, tol=1e-10, max_iter=20000, which=-1)
+    with gsi.Solver(S if kind == "stencil" else A, X0, p, which=-1, tol=1e-10, max_iter=20000,
+                    recompute_ax="auto") as s:
+        r = s.run()
+        choice, ms0, ms1 = s.recompute_choice()
+    assert r.status == 0
+    assert ms0 > 0.0 and ms1 > 0.0
+    assert choice == (1 if ms1 < ms0 else 0)
+    assert np.max(np.abs(r.ritz - ref.theta) / np.abs(ref.theta)) <= 1e-10
+    assert abs(r.iters - ref.iters) <= max(5, ref.iters // 10)

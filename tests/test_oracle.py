@@ -412,3 +412,52 @@ def test_stencil_matrix_spectrum_is_the_closed_form():
     N = 6
     C = O.stencil_matrix(N, N, 1, 4.0 * (N + 1) ** 2, -(N + 1) ** 2, v[:N * N])
     assert np.array_equal((C != 0).toarray(), (I.schrodinger_2d(N, None).to_scipy() != 0).toarray())
+
+
+def _magnetic_ring(n, theta):
+    """H = 2I - e^{i theta} S - e^{-i theta} S^T on a ring (S the cyclic shift): Hermitian,
+    eigenvalues 2 - 2 cos(2 pi k / n + theta), eigenvectors the Fourier modes."""
+    import scipy.sparse as sps
+    S = sps.csr_matrix((np.ones(n), (np.arange(n), (np.arange(n) + 1) % n)), shape=(n, n))
+    return (2.0 * sps.identity(n) - np.exp(1j * theta) * S - np.exp(-1j * theta) * S.T).tocsr()
+
+
+def test_hermitian_rcg_magnetic_ring_closed_form():
+    n, p, theta = 60, 4, 0.37
+    H = _magnetic_ring(n, theta)
+    lam = 2.0 - 2.0 * np.cos(2.0 * np.pi * np.arange(n) / n + theta)
+    order = np.argsort(lam)
+    g = np.random.default_rng(0)
+    X0 = g.standard_normal((n, p)) + 1j * g.standard_normal((n, p))
+    r = O.rcg_hermitian(H, X0, tol=1e-11, max_iter=5000, which=-1)
+    assert r.converged
+    assert np.allclose(r.theta, lam[order[:p]], atol=1e-10)
+    F = np.exp(2j * np.pi * np.outer(np.arange(n), order[:p]) / n) / np.sqrt(n)
+    assert O.principal_angles_complex(r.X, F).max() < 1e-8
+    assert np.allclose(r.X.conj().T @ r.X, np.eye(p), atol=1e-12)
+
+
+def test_hermitian_rcg_on_a_real_matrix_follows_the_real_iteration():
+    # a real symmetric matrix with a real start block: the complex variant takes the real
+    # steps (same step sizes and Ritz values as the real solver)
+    A = I.laplacian_2d(10)
+    X0 = I.start_block(100, 4, 2)
+    rr = O.rcg(A, X0, tol=1e-10, max_iter=3000)
+    rc = O.rcg_hermitian(A.to_scipy().astype(np.complex128), X0.astype(np.complex128), tol=1e-10, max_iter=3000)
+    # the same step sizes until rounding differences (complex vs real kernels) grow
+    assert np.allclose(rc.mu[:15], rr.mu[:15], rtol=1e-8)
+    assert abs(rc.iters - rr.iters) <= 3
+    assert np.allclose(rc.theta, rr.theta, rtol=1e-12)
+
+
+def test_hermitian_rcg_dense_random_matches_library_eigh():
+    g = np.random.default_rng(5)
+    n, p = 40, 5
+    B = g.standard_normal((n, n)) + 1j * g.standard_normal((n, n))
+    H = 0.5 * (B + B.conj().T)
+    w, V = np.linalg.eigh(H)
+    X0 = g.standard_normal((n, p)) + 1j * g.standard_normal((n, p))
+    r = O.rcg_hermitian(H, X0, tol=1e-12, max_iter=20000, which=1)
+    assert r.converged
+    assert np.allclose(r.theta, w[::-1][:p], atol=1e-10)
+    assert O.principal_angles_complex(r.X, V[:, ::-1][:, :p]).max() < 1e-8
