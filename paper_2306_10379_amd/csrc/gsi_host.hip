@@ -27,7 +27,9 @@ namespace {
 
 constexpr int MAXP = 64;
 
-int round16(int p) { return (p + 15) / 16 * 16; }
+// Padded block width: the kernels are built for 16, 32 and 64 columns; the padding
+// columns stay zero.
+int padded_width(int p) { return p <= 16 ? 16 : (p <= 32 ? 32 : 64); }
 
 struct Dev {
   std::vector<void*> ptrs;
@@ -66,7 +68,7 @@ struct Engine {
   bool explicit_grams = false;
 
   bool alloc(Dev& d, int64_t n_, int p_, int nb_, int64_t nnz, bool bf16 = false) {
-    n = n_; p = p_; PP = round16(p_); nb = nb_;
+    n = n_; p = p_; PP = padded_width(p_); nb = nb_;
     // whole TR-row tiles; the rows past n stay zero (cleared once here, never written)
     const size_t blk = (size_t)((n + TR - 1) / TR * TR) * PP;
     X = d.alloc<T>(blk); Y = d.alloc<T>(blk); G0 = d.alloc<T>(blk); G1 = d.alloc<T>(blk);
@@ -785,7 +787,7 @@ gsi_status create_impl(gsi_handle* out, const gsi_csr* A, const gsi_stencil* S, 
     h->soff = (opt->which > 0 ? 1.0 : -1.0) * S->off;
   }
   h->p = opt->p;
-  h->PP = round16(opt->p);
+  h->PP = padded_width(opt->p);
   h->mixed = opt->precision == GSI_MIXED_FP32 || opt->precision == GSI_MIXED_BF16;
   h->bf16 = opt->precision == GSI_MIXED_BF16;
   const int64_t ntiles = (h->n + TR - 1) / TR;

@@ -1,12 +1,15 @@
 #!/bin/bash
 # Regenerates the rocprofv3 summaries under profiles/. Run from the repository root on a
 # machine with the GPU (the library built): bash paper_2306_10379_amd/profile_runs.sh
-# Raw databases go to gpurun_out/prof/; each summary records the command that produced it.
+# Raw databases go to /tmp/gsi_prof (they exceed what a results folder should carry); the
+# rocprofv3 logs and the summaries are copied to gpurun_out/prof/. Each summary records the
+# command that produced it.
 # rocprofv3 may exit with a segmentation fault after the profiled program has finished and
 # its database is complete; a step counts as done when its database exists.
 R=$(pwd)
-O=$R/gpurun_out/prof
-mkdir -p "$O"
+O=/tmp/gsi_prof
+K=$R/gpurun_out/prof
+mkdir -p "$O" "$K"
 export TMPDIR=/tmp
 db() { find "$1" -name '*.db' | head -1; }
 step() {  # step <dir> <timeout> <rocprofv3 arguments...>; counter runs are killed outright at the limit
@@ -14,9 +17,9 @@ step() {  # step <dir> <timeout> <rocprofv3 arguments...>; counter runs are kill
   shift 2
   echo "== rocprofv3 $* (${d})"
   if [ "$1" = "--pmc" ]; then
-    (cd /tmp && timeout -s KILL "$t" rocprofv3 "$@" > "$O/$(basename "$d").log" 2>&1)
+    (cd /tmp && timeout -s KILL "$t" rocprofv3 "$@" > "$K/$(basename "$d").log" 2>&1)
   else
-    (cd /tmp && timeout -k 10 "$t" rocprofv3 "$@" > "$O/$(basename "$d").log" 2>&1)
+    (cd /tmp && timeout -k 10 "$t" rocprofv3 "$@" > "$K/$(basename "$d").log" 2>&1)
   fi
   local rc=$?
   if [ -z "$(db "$d")" ]; then echo "no database from ${d} (status $rc)"; return 1; fi
@@ -40,5 +43,5 @@ $S trace "$(db "$O/c3_trace")" "$C --kernel-trace --stats -- $B --profile-steps 
 $S traffic "$(db "$O/c3_fetch")" "$(db "$O/c3_write")" "$C --pmc FETCH_SIZE / WRITE_SIZE -- $B --profile-steps 3 --profile-matrix spiked --profile-precision bf16)" profiles/traffic_spiked4M_p64_bf16.json > /dev/null
 $S trace "$(db "$O/c4_trace")" "$C --kernel-trace --stats -- $B --legs-only --steps 1 --warmup 0)" > profiles/kernels_schrodinger_batch512.md
 $S trace "$(db "$O/fno_trace")" "$C --kernel-trace --stats -- python3 -m pytest tests/test_gpu_fno.py)" > profiles/kernels_warmstart_network.md
-cp profiles/*.md profiles/*.json "$O/" 2>/dev/null
+cp profiles/*.md profiles/*.json "$K/" 2>/dev/null
 echo "summaries written"

@@ -78,3 +78,20 @@ def test_hermitian_rejects_p_above_32():
     H = I.magnetic_lattice(10, seed=1)
     with pytest.raises(gsi.GsiError):
         gsi.HermitianSolver(H, _start(100, 33, 0), 33)
+
+
+@pytest.mark.parametrize("N,p", [(23, 1), (23, 7)])
+def test_hermitian_ragged_rows_and_p1(N, p):
+    # 2n = 1058 real rows (a partial last tile), p = 1 and an odd p
+    gsi = _gsi()
+    H = I.magnetic_lattice(N, flux=0.21, seed=3)
+    X0 = _start(N * N, p, 11)
+    print(f"hermitian ragged N={N} p={p}", flush=True)
+    ref = O.rcg_hermitian(H, X0, tol=1e-10, max_iter=20000, which=-1)
+    w = np.linalg.eigvalsh(H.toarray())[:p]
+    with gsi.HermitianSolver(H, X0, p, which=-1, tol=1e-10, max_iter=20000) as s:
+        status, iters, ritz, X, rho = s.run()
+    X = X.cpu().numpy()
+    assert status == 0 and ref.converged
+    assert np.max(np.abs(ritz - w) / np.abs(w)) <= 1e-9
+    assert O.principal_angles_complex(X, ref.X).max() <= 1e-6

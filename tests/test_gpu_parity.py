@@ -435,3 +435,62 @@ def test_tracking_sequence_matches_oracle_chain():
     print("iterations per step", iters, "oracle", [x.iters for x in ref], flush=True)
     assert all(i < iters[0] for i in iters[1:])
     assert all(abs(i - x.iters) <= max(5, x.iters // 5) for i, x in zip(iters, ref))
+
+
+@pytest.mark.parametrize("n,p,seed", [(1000, 13, 21), (777, 1, 22), (2049, 64, 23)])
+def test_si_chebyshev_ragged_shapes(n, p, seed):
+    # ragged n (a partial last tile), p not a multiple of 16, p = 1 and p = 64; the filter
+    # interval from the dense spectrum of the operator solved (+A, largest eigenvalues)
+    gsi = _gsi()
+    A = I.spiked_sparse(n, 4, p, seed, gap=0.3)
+    lam = np.sort(np.linalg.eigvalsh(A.to_dense()))[::-1]
+    lo, hi, top = lam[-1] - 0.01, lam[p] + 1e-3 * abs(lam[p]), lam[0] + 0.01
+    X0 = I.start_block(n, p, seed)
+    print(f"SI ragged n={n} p={p}", flush=True)
+    ref = O.chebyshev_si(A, X0, 10, lo, hi, top, tol=1e-10, max_iter=3000, which=1)
+    with gsi.Solver(A, X0, p, which=1, method="si", tol=1e-10, max_iter=3000, cheb_degree=10, cheb_lo=lo,
+                    cheb_hi=hi, cheb_top=top) as s:
+        r = s.run()
+        X = s.get_x().cpu().numpy()
+        hist = s.history()
+    assert r.status == 0 and ref.converged
+    assert abs(r.iters - ref.iters) <= 1
+    k = min(len(hist["rho"]), len(ref.rho), 20)
+    assert np.allclose(hist["rho"][:k], ref.rho[:k], rtol=1e-6, atol=1e-13)
+    assert np.max(np.abs(r.ritz - lam[:p]) / np.abs(lam[:p])) <= 1e-10
+    assert O.principal_angles(X, ref.X).max() <= 1e-7
+
+
+def test_tracking_in_mixed_precision_reaches_fp64_accuracy():
+    gsi = _gsi()
+    N, p, steps = 32, 6, 3
+    mats = I.moving_well_sequence(N, steps, seed=7)
+    X0 = I.start_block(N * N, p, 3)
+    print("tracking mixed", flush=True)
+    with gsi.Solver(mats[0], X0, p, which=-1, tol=1e-10, max_iter=20000, precision="mixed") as s:
+        for t, A in enumerate(mats):
+            if t:
+                s.set_values(A.vals)
+            r = s.run()
+            X = s.get_x().cpu().numpy()
+            assert r.status == 0, t
+            w = np.linalg.eigvalsh(A.to_dense())[:p]
+            assert np.max(np.abs(r.ritz - w) / np.abs(w)) <= 1e-9, t
+            assert _true_rho(A, X) <= 1.05e-10, t
+
+
+@pytest.mark.parametrize("p", [33, 40, 48, 57])
+def test_block_sizes_between_32_and_64(p):
+    # p in 33..64 runs in the 64-column kernels with zero padding columns
+    gsi = _gsi()
+    n = 1500
+    A = I.spiked_sparse(n, 4, p, 30 + p, gap=0.3)
+    X0 = I.start_block(n, p, p)
+    print(f"p={p}", flush=True)
+    ref = O.rcg(A, X0, tol=1e-10, max_iter=5000)
+    with gsi.Solver(A, X0, p, tol=1e-10, max_iter=5000) as s:
+        r = s.run()
+        X = s.get_x().cpu().numpy()
+    assert r.status == 0
+    assert np.max(np.abs(r.ritz - ref.theta) / np.abs(ref.theta)) <= 1e-10
+    assert O.principal_angles(X, ref.X).max() <= 1e-7

@@ -152,3 +152,19 @@ def test_automatic_recompute_choice_times_both_and_converges(kind):
     assert choice == (1 if ms1 < ms0 else 0)
     assert np.max(np.abs(r.ritz - ref.theta) / np.abs(ref.theta)) <= 1e-10
     assert abs(r.iters - ref.iters) <= max(5, ref.iters // 10)
+
+
+def test_stencil_small_grid_p1_and_tail_tile():
+    # a 1D grid of 130 nodes (two full tiles and a 2-row tail) and p = 1
+    gsi = _gsi()
+    S = gsi.Stencil(130, 1, 1, diag=2.0, off=-1.0)
+    A, M = _csr_of(S)
+    X0 = I.start_block(130, 1, 0)
+    print("stencil 1D p=1", flush=True)
+    with gsi.Solver(S, X0, 1, which=-1, tol=1e-10, max_iter=20000) as s1, \
+            gsi.Solver(A, X0, 1, which=-1, tol=1e-10, max_iter=20000) as s2:
+        r1, r2 = s1.run(), s2.run()
+        assert r1.status == 0 and r1.iters == r2.iters
+        assert np.array_equal(s1.get_x().cpu().numpy(), s2.get_x().cpu().numpy())
+    lam = 2.0 - 2.0 * np.cos(np.pi / 131.0)
+    assert abs(r1.ritz[0] - lam) <= 1e-10 * lam
