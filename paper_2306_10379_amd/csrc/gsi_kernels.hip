@@ -340,6 +340,28 @@ inline int64_t spmm_grid(int64_t ntiles, int64_t plane_tiles) {
   return 8 * chunk * planes;
 }
 
+// The row pointers of a workgroup's tile and, when they fit (at most CSR_CAP nonzeros), its
+// column indices and values, read into LDS with coalesced loads before any gather: a gather
+// then waits on one LDS read instead of two dependent global loads. Returns whether the
+// indices and values were staged (the same answer in every thread of the workgroup).
+constexpr int CSR_CAP = 2048;
+template <typename V>
+__device__ __forceinline__ bool csr_stage(int32_t* s_rp, int32_t* s_col, V* s_val, const int32_t* __restrict__ rowptr,
+                                          const int32_t* __restrict__ colind, const V* __restrict__ vals, int64_t r0,
+                                          int nrows) {
+  if ((int)threadIdx.x <= nrows) s_rp[threadIdx.x] = rowptr[r0 + threadIdx.x];
+  __syncthreads();
+  const int32_t base = s_rp[0], cnt = s_rp[nrows] - base;
+  const bool staged = cnt <= CSR_CAP;
+  if (staged)
+    for (int i = threadIdx.x; i < cnt; i += WG) {
+      s_col[i] = colind[base + i];
+      s_val[i] = vals[base + i];
+    }
+  __syncthreads();
+  return staged;
+}
+
 template <typename T, int PP>
 __global__ __launch_bounds__(WG) void k_spmm(int64_t n, const int32_t* __restrict__ rowptr,
                                              const int32_t* __restrict__ colind, const T* __restrict__ vals,
@@ -354,21 +376,34 @@ __global__ __launch_bounds__(WG) void k_spmm(int64_t n, const int32_t* __restric
   const int64_t ntiles = (n + TR - 1) / TR;
   const int64_t t = spmm_tile(ntiles, plane_tiles);
   if (t >= ntiles) return;
+  __shared__ int32_t s_rp[TR + 1];
+  __shared__ int32_t s_col[CSR_CAP];
+  __shared__ T s_val[CSR_CAP];
+  const int64_t r0 = t * TR;
+  const int nrows = (int)((n - r0) < TR ? (n - r0) : TR);
+  const bool staged = csr_stage(s_rp, s_col, s_val, rowptr, colind, vals, r0, nrows);
+  const int32_t base = s_rp[0];
   const int sub = threadIdx.x / LPR, lane = threadIdx.x % LPR;
 #pragma unroll
   for (int pass = 0; pass < TR / RPB; ++pass) {
-    const int64_t row = t * TR + pass * RPB + sub;
-    if (row >= n) continue;
+    const int lr = pass * RPB + sub;
+    if (lr >= nrows) continue;
+    const int64_t row = r0 + lr;
     T acc[EPL] = {T(0), T(0), T(0), T(0)};
-    const int32_t j0 = rowptr[row], j1 = rowptr[row + 1];
+    const int32_t j0 = s_rp[lr], j1 = s_rp[lr + 1];
     for (int32_t j = j0; j < j1; j += U) {
       int32_t col[U];
       T v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const bool ok = j + u < j1;
-        col[u] = ok ? colind[j + u] : 0;
-        v[u] = ok ? vals[j + u] : T(0);
+        if (staged) {
+          col[u] = ok ? s_col[j + u - base] : 0;
+          v[u] = ok ? s_val[j + u - base] : T(0);
+        } else {
+          col[u] = ok ? colind[j + u] : 0;
+          v[u] = ok ? vals[j + u] : T(0);
+        }
       }
       T x[U][EPL];
 #pragma unroll
@@ -415,23 +450,36 @@ __global__ __launch_bounds__(WG) void k_spmm16(int64_t n, const int32_t* __restr
   const int64_t t = spmm_tile(ntiles, plane_tiles);
   if (t >= ntiles) return;
   constexpr int PASSES = (TR + RPB - 1) / RPB;  // at PP = 16 a pass spans 128 rows: half the lanes idle
+  __shared__ int32_t s_rp[TR + 1];
+  __shared__ int32_t s_col[CSR_CAP];
+  __shared__ uint16_t s_val[CSR_CAP];
+  const int64_t r0 = t * TR;
+  const int nrows = (int)((n - r0) < TR ? (n - r0) : TR);
+  const bool staged = csr_stage(s_rp, s_col, s_val, rowptr, colind, vals, r0, nrows);
+  const int32_t base = s_rp[0];
   const int sub = threadIdx.x / LPR, lane = threadIdx.x % LPR;
 #pragma unroll
   for (int pass = 0; pass < PASSES; ++pass) {
-    const int64_t row = t * TR + pass * RPB + sub;
-    if (pass * RPB + sub >= TR || row >= n) continue;
+    const int lr = pass * RPB + sub;
+    if (lr >= nrows) continue;
+    const int64_t row = r0 + lr;
     float acc[EPL];
 #pragma unroll
     for (int e = 0; e < EPL; ++e) acc[e] = 0.f;
-    const int32_t j0 = rowptr[row], j1 = rowptr[row + 1];
+    const int32_t j0 = s_rp[lr], j1 = s_rp[lr + 1];
     for (int32_t j = j0; j < j1; j += U) {
       int32_t col[U];
       float v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const bool ok = j + u < j1;
-        col[u] = ok ? colind[j + u] : 0;
-        v[u] = ok ? bf16_widen(vals[j + u]) : 0.f;
+        if (staged) {
+          col[u] = ok ? s_col[j + u - base] : 0;
+          v[u] = ok ? bf16_widen(s_val[j + u - base]) : 0.f;
+        } else {
+          col[u] = ok ? colind[j + u] : 0;
+          v[u] = ok ? bf16_widen(vals[j + u]) : 0.f;
+        }
       }
       u4 x[U];
 #pragma unroll
@@ -468,21 +516,34 @@ __global__ __launch_bounds__(WG) void k_spmm_fin(int64_t n, const int32_t* __res
   const int64_t ntiles = (n + TR - 1) / TR;
   const int64_t t = spmm_tile(ntiles, plane_tiles);
   if (t >= ntiles) return;
+  __shared__ int32_t s_rp[TR + 1];
+  __shared__ int32_t s_col[CSR_CAP];
+  __shared__ float s_val[CSR_CAP];
+  const int64_t r0 = t * TR;
+  const int nrows = (int)((n - r0) < TR ? (n - r0) : TR);
+  const bool staged = csr_stage(s_rp, s_col, s_val, rowptr, colind, vals, r0, nrows);
+  const int32_t base = s_rp[0];
   const int sub = threadIdx.x / LPR, lane = threadIdx.x % LPR;
 #pragma unroll
   for (int pass = 0; pass < TR / RPB; ++pass) {
-    const int64_t row = t * TR + pass * RPB + sub;
-    if (row >= n) continue;
+    const int lr = pass * RPB + sub;
+    if (lr >= nrows) continue;
+    const int64_t row = r0 + lr;
     double acc[EPL] = {0.0, 0.0, 0.0, 0.0};
-    const int32_t j0 = rowptr[row], j1 = rowptr[row + 1];
+    const int32_t j0 = s_rp[lr], j1 = s_rp[lr + 1];
     for (int32_t j = j0; j < j1; j += U) {
       int32_t col[U];
       double v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const bool ok = j + u < j1;
-        col[u] = ok ? colind[j + u] : 0;
-        v[u] = ok ? (double)vals[j + u] : 0.0;
+        if (staged) {
+          col[u] = ok ? s_col[j + u - base] : 0;
+          v[u] = ok ? (double)s_val[j + u - base] : 0.0;
+        } else {
+          col[u] = ok ? colind[j + u] : 0;
+          v[u] = ok ? (double)vals[j + u] : 0.0;
+        }
       }
       f4 x[U];
 #pragma unroll
@@ -513,21 +574,34 @@ __global__ __launch_bounds__(WG) void k_spmm_axpy(int64_t n, const int32_t* __re
   const int64_t ntiles = (n + TR - 1) / TR;
   const int64_t t = spmm_tile(ntiles, plane_tiles);
   if (t >= ntiles) return;
+  __shared__ int32_t s_rp[TR + 1];
+  __shared__ int32_t s_col[CSR_CAP];
+  __shared__ T s_val[CSR_CAP];
+  const int64_t r0 = t * TR;
+  const int nrows = (int)((n - r0) < TR ? (n - r0) : TR);
+  const bool staged = csr_stage(s_rp, s_col, s_val, rowptr, colind, vals, r0, nrows);
+  const int32_t base = s_rp[0];
   const int sub = threadIdx.x / LPR, lane = threadIdx.x % LPR;
 #pragma unroll
   for (int pass = 0; pass < TR / RPB; ++pass) {
-    const int64_t row = t * TR + pass * RPB + sub;
-    if (row >= n) continue;
+    const int lr = pass * RPB + sub;
+    if (lr >= nrows) continue;
+    const int64_t row = r0 + lr;
     T acc[EPL] = {T(0), T(0), T(0), T(0)};
-    const int32_t j0 = rowptr[row], j1 = rowptr[row + 1];
+    const int32_t j0 = s_rp[lr], j1 = s_rp[lr + 1];
     for (int32_t j = j0; j < j1; j += U) {
       int32_t col[U];
       T v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const bool ok = j + u < j1;
-        col[u] = ok ? colind[j + u] : 0;
-        v[u] = ok ? vals[j + u] : T(0);
+        if (staged) {
+          col[u] = ok ? s_col[j + u - base] : 0;
+          v[u] = ok ? s_val[j + u - base] : T(0);
+        } else {
+          col[u] = ok ? colind[j + u] : 0;
+          v[u] = ok ? vals[j + u] : T(0);
+        }
       }
       T x[U][EPL];
 #pragma unroll
