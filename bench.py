@@ -215,6 +215,62 @@ def stencil_leg(args, gsi, torch, X0, t_csr, it_csr, spmm_csr_us, csr):
             "spmm_bytes": nbytes, "recompute_choice": choice}
 
 
+def tracking_leg(args, gsi, inputs, torch):
+    """Subspace tracking: a sequence of 2D Schroedinger operators on one 256 x 256 grid with a
+    Gaussian well moving 0.011 per step, p = 32 smallest; each step solved from the previous
+    basis (gsi_set_values) against a solve from the random start block."""
+    N, p, steps = 256, 32, 6
+    mats = inputs.moving_well_sequence(N, steps, seed=11)
+    X0 = inputs.start_block(N * N, p, 12)
+    s = gsi.Solver(mats[0], X0, p, which=-1, tol=args.tol, max_iter=20000, check_every=50)
+    warm_t, warm_it = [], []
+    for t, A in enumerate(mats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if t:
+            s.set_values(torch.as_tensor(A.vals, device="cuda"))
+        status, it = s.solve()
+        torch.cuda.synchronize()
+        warm_t.append(time.perf_counter() - t0)
+        warm_it.append(it)
+    s.close()
+    cold_t, cold_it = [], []
+    for A in mats[1:3]:
+        c = gsi.Solver(A, X0, p, which=-1, tol=args.tol, max_iter=20000, check_every=50)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        status, it = c.solve()
+        torch.cuda.synchronize()
+        cold_t.append(time.perf_counter() - t0)
+        cold_it.append(it)
+        c.close()
+    log(f"tracking: steps {warm_it} iterations, cold {cold_it}")
+    return {"workload": f"2D Schroedinger {N}^2, moving well, p={p} smallest, {steps} steps, rho <= {args.tol:g}",
+            "iters_per_step": warm_it, "s_per_step": [round(x, 3) for x in warm_t],
+            "cold_iters": cold_it, "cold_s": [round(x, 3) for x in cold_t],
+            "speedup_tracked_vs_cold": round(float(np.mean(cold_t) / np.mean(warm_t[1:])), 2)}
+
+
+def hermitian_leg(args, gsi, inputs, torch):
+    """Complex Hermitian variant: magnetic lattice 512 x 512 (flux 0.13, disorder 0.5),
+    p = 16 smallest, through the real embedding (2n = 524288 real rows, 32 real columns)."""
+    N, p = 512, 16
+    H = inputs.magnetic_lattice(N, flux=0.13, seed=5)
+    g = np.random.default_rng(6)
+    X0 = g.standard_normal((N * N, p)) + 1j * g.standard_normal((N * N, p))
+    s = gsi.HermitianSolver(H, X0, p, which=-1, tol=args.tol, max_iter=20000, check_every=50)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status, it = s.solve()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ritz, X, rho = s.results()
+    s.close()
+    log(f"hermitian {N}^2 p={p}: {dt:.2f} s, {it} iterations, status {status}")
+    return {"workload": f"magnetic lattice {N}^2 (complex Hermitian, n={N * N}), p={p} smallest, rho <= {args.tol:g}",
+            "s": round(dt, 3), "iters": it, "status": status, "rho": rho, "ritz_first": float(ritz[0])}
+
+
 def batched_leg(args, gsi, inputs, torch):
     """Many small problems in one persistent launch: the whole batch to rho <= tol with float32
     blocks then float64 refinement, and with float64 blocks, against the plain float64 path
@@ -304,6 +360,8 @@ def main():
                     help="run the Chebyshev-filtered subspace iteration to the tolerance")
     ap.add_argument("--no-stencil", action="store_true",
                     help="skip the matrix-free stencil solve of the headline workload")
+    ap.add_argument("--no-tracking", action="store_true", help="skip the subspace-tracking leg")
+    ap.add_argument("--no-hermitian", action="store_true", help="skip the complex Hermitian leg")
     ap.add_argument("--warm-train", type=int, default=144)
     ap.add_argument("--warm-test", type=int, default=24)
     ap.add_argument("--batch", type=int, default=512)
@@ -427,6 +485,8 @@ def main():
 
     batched = None if args.no_batched else batched_leg(args, gsi, inputs, torch)
     c3 = c3_leg(args, gsi, inputs, torch) if args.c3 else None
+    tracking = None if args.no_tracking else tracking_leg(args, gsi, inputs, torch)
+    hermitian = None if args.no_hermitian else hermitian_leg(args, gsi, inputs, torch)
     warm = None
     if args.warm:
         from paper_2306_10379_amd import warmstart
@@ -471,6 +531,8 @@ def main():
         "batched": batched,
         "random_sparse": c3,
         "warm_start": warm,
+        "tracking": tracking,
+        "hermitian": hermitian,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
