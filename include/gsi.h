@@ -129,11 +129,14 @@ typedef struct {
                            [lambda_n, lambda_{p+1}] of eq. optimal_poly, and an estimate */
   double cheb_hi;       /* cheb_top > cheb_hi of its largest eigenvalue (the normalization */
   double cheb_top;      /* point that keeps the filtered block bounded) */
+  int32_t check_symmetric; /* 1: gsi_create also verifies that A equals its transpose (every
+                              stored a_ij has a stored a_ji of the same value; GSI_EINVAL
+                              otherwise); 0: not checked (the methods assume it, Sec. 2) */
 } gsi_options;
 
 /* Fill *opt with defaults: p=8, which=+1, RCG, FP64, recursion, no restart, max_iter=10000,
  * tol=1e-8, switch_tol=1e-5, check_every=25, use_graph=1, explicit_c=0, stall_window=60,
- * cheb_degree=0. */
+ * cheb_degree=0, check_symmetric=0. */
 void gsi_options_default(gsi_options* opt);
 
 /* Create a solver for A with options opt, starting block X0 (n x p float64, device; its

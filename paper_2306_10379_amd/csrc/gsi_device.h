@@ -1,7 +1,7 @@
 // Device-side building blocks shared by the gsi kernels (gfx950, wave64).
 //
-// Tall n x p blocks are row-major with leading dimension PP = p rounded up to 16
-// (padding columns are kept at zero). A workgroup has 4 waves; a wave owns 16-row
+// Tall n x p blocks are row-major with leading dimension PP = 16, 32 or 64, the smallest
+// that holds p (padding columns are kept at zero). A workgroup has 4 waves; a wave owns 16-row
 // tiles. Dense contractions use MFMA 16x16x4 (f64 or f32):
 //   A operand (16 x 4):  lane l holds A[l % 16][l / 16]
 //   B operand (4 x 16):  lane l holds B[l / 16][l % 16]

@@ -147,6 +147,31 @@ struct gsi_ctx {
 
 namespace {
 
+// Symmetry check of a CSR matrix: for every stored a_ij, row j must store a_ji with the same
+// value (binary search, column indices sorted within rows). Sets flag 16 otherwise.
+__global__ void k_sym_check(int64_t n, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+                            const double* __restrict__ vals, int* __restrict__ flags) {
+  int bad = 0;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    for (int32_t k = rowptr[r]; k < rowptr[r + 1]; ++k) {
+      const int32_t c = colind[k];
+      int32_t lo = rowptr[c], hi = rowptr[c + 1] - 1;
+      bool found = false;
+      while (lo <= hi) {
+        const int32_t mid = lo + (hi - lo) / 2;
+        const int32_t m = colind[mid];
+        if (m == (int32_t)r) {
+          found = vals[mid] == vals[k];
+          break;
+        }
+        if (m < (int32_t)r) lo = mid + 1; else hi = mid - 1;
+      }
+      if (!found) bad = 1;
+    }
+  }
+  if (bad) atomicOr(flags, 16);
+}
+
 gsi_status fail(gsi_ctx* h, gsi_status s, const std::string& msg) {
   if (h) h->err = msg;
   return s;
@@ -852,6 +877,15 @@ gsi_status create_impl(gsi_handle* out, const gsi_csr* A, const gsi_stencil* S, 
   if (fl[0] & 8) return bail(GSI_EINVAL, "column indices not sorted within a row");
   if (fl[0] & 4) return bail(GSI_BREAKDOWN, "non-finite matrix value");
   if (fl[1]) return bail(GSI_BREAKDOWN, "non-finite value in X0");
+  if (A && opt->check_symmetric) {
+    // the structure is valid (checked above), so the searches stay inside the arrays
+    hipLaunchKernelGGL(k_sym_check, dim3(1024), dim3(256), 0, st, h->n, A->rowptr, A->colind, A->vals, h->flags);
+    int fs = 0;
+    s = hip_check(h, hipMemcpyAsync(&fs, h->flags, sizeof(int), hipMemcpyDeviceToHost, st), "flags");
+    if (s == GSI_OK) s = hip_check(h, hipStreamSynchronize(st), "symmetry check");
+    if (s != GSI_OK) return bail(s, h->err);
+    if (fs & 16) return bail(GSI_EINVAL, "matrix is not symmetric");
+  }
   (void)hipMemsetAsync(h->flags, 0, 4 * sizeof(int), st);
   double nA = 0.0, band = 0.0;
   for (int i = 0; i < cb; ++i) {

@@ -65,7 +65,7 @@ class GsiOptions(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("switch_tol", ctypes.c_double),
                 ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("explicit_c", ctypes.c_int32),
                 ("stall_window", ctypes.c_int32), ("cheb_degree", ctypes.c_int32), ("cheb_lo", ctypes.c_double),
-                ("cheb_hi", ctypes.c_double), ("cheb_top", ctypes.c_double)]
+                ("cheb_hi", ctypes.c_double), ("cheb_top", ctypes.c_double), ("check_symmetric", ctypes.c_int32)]
 
 
 _lib = None
@@ -319,7 +319,7 @@ class Solver:
             opts["recompute_ax"] = -1
         elif "recompute_ax" in opts and opts["recompute_ax"] != -1:
             opts["recompute_ax"] = int(bool(opts["recompute_ax"]))
-        for b in ("use_graph", "explicit_c"):
+        for b in ("use_graph", "explicit_c", "check_symmetric"):
             if b in opts:
                 opts[b] = int(bool(opts[b]))
         self.opt = options(p=self.p, **opts)
@@ -572,7 +572,7 @@ class HermitianSolver(Solver):
                                   device=device)
         method = opts.pop("method", "rcg")
         opts["method"] = {"rsd": GSI_RSD, "rcg": GSI_RCG}[method] if isinstance(method, str) else method
-        for b in ("use_graph", "explicit_c"):
+        for b in ("use_graph", "explicit_c", "check_symmetric"):
             if b in opts:
                 opts[b] = int(bool(opts[b]))
         self.n, self.p = int(n), int(p)

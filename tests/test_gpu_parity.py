@@ -494,3 +494,28 @@ def test_block_sizes_between_32_and_64(p):
     assert r.status == 0
     assert np.max(np.abs(r.ritz - ref.theta) / np.abs(ref.theta)) <= 1e-10
     assert O.principal_angles(X, ref.X).max() <= 1e-7
+
+
+def test_symmetry_check_on_request():
+    gsi = _gsi()
+    A = I.spiked_sparse(600, 4, 4, 3, gap=0.3)
+    X0 = I.start_block(A.n, 4, 0)
+    print("symmetry check", flush=True)
+    with gsi.Solver(A, X0, 4, check_symmetric=True) as s:
+        assert s.run().status == 0
+    B = I.CSR(n=A.n, rowptr=A.rowptr.copy(), colind=A.colind.copy(), vals=A.vals.copy())
+    # change one off-diagonal value only on one side
+    r = 5
+    k = next(k for k in range(B.rowptr[r], B.rowptr[r + 1]) if B.colind[k] != r)
+    B.vals[k] += 1e-3
+    with pytest.raises(gsi.GsiError):
+        gsi.Solver(B, X0, 4, check_symmetric=True)
+    # a complex Hermitian matrix passes through its real embedding; a non-Hermitian one fails
+    H = I.magnetic_lattice(12, seed=2)
+    Z0 = np.random.default_rng(1).standard_normal((144, 3)) + 0j
+    with gsi.HermitianSolver(H, Z0, 3, check_symmetric=True) as s:
+        assert s.run()[0] == 0
+    H2 = H.tolil()
+    H2[0, 1] = H2[0, 1] * np.exp(0.1j)
+    with pytest.raises(gsi.GsiError):
+        gsi.HermitianSolver(H2.tocsr(), Z0, 3, check_symmetric=True)
