@@ -18,58 +18,74 @@ namespace gsi {
 __global__ __launch_bounds__(WG) void k_after_grad(int PP, const double* __restrict__ red, double* __restrict__ small,
                                                    Scalars* __restrict__ sc, double* __restrict__ hist) {
   if (sc->done) return;
-  __shared__ double sbeta;
-  const int p = sc->p;
+  __shared__ double sbeta, sphi;
+  // the scalars and the trace of C are read by all threads at once (one round trip) and the
+  // sequential decisions below work on the LDS copy: dependent global reads one after the
+  // other cost a memory latency each
+  __shared__ Scalars ls;
+  for (int i = threadIdx.x; i < (int)(sizeof(Scalars) / 4); i += blockDim.x)
+    reinterpret_cast<int32_t*>(&ls)[i] = reinterpret_cast<const int32_t*>(sc)[i];
+  if (threadIdx.x < 64) {
+    double d = 0.0;
+    for (int i = threadIdx.x; i < PP; i += 64) d += small[S_C * PP * PP + i * PP + i];
+    d = wave_sum(d);
+    if (threadIdx.x == 0) sphi = -0.5 * d;
+  }
+  __syncthreads();
   const double* K = red;
   if (threadIdx.x == 0) {
+    Scalars* lsc = &ls;
     const double gg = red[PP * PP], gdot = red[PP * PP + 1], ginf = red[PP * PP + 2];
-    const int k = sc->k;
+    const int k = lsc->k;
     sc->gg = gg;
     sc->gdot = gdot;
     sc->ginf = ginf;
-    const double rho = sqrt(gg) / (sc->sqrt_p * sc->nA);
-    double phi = 0.0;
-    for (int i = 0; i < p; ++i) phi += small[S_C * PP * PP + i * PP + i];
-    phi *= -0.5;
+    const double rho = sqrt(gg) / (lsc->sqrt_p * lsc->nA);
+    const double phi = sphi;
     sc->rho = rho;
     sc->phi = phi;
-    if (k == 0) sc->ginf0 = ginf;
-    if (k < sc->hist_cap) {
+    if (k == 0) {
+      lsc->ginf0 = ginf;
+      sc->ginf0 = ginf;
+    }
+    if (k < lsc->hist_cap) {
       double* h = hist + (int64_t)k * H_FIELDS;
       h[H_RHO] = rho;
       h[H_PHI] = phi;
       h[H_MU] = 0.0;
       h[H_BETA] = 0.0;
-      h[H_GINF] = sc->ginf0 > 0.0 ? ginf / sc->ginf0 : 0.0;
-      if (k + 1 > sc->hist_len) sc->hist_len = k + 1;
+      h[H_GINF] = lsc->ginf0 > 0.0 ? ginf / lsc->ginf0 : 0.0;
+      if (k + 1 > lsc->hist_len) sc->hist_len = k + 1;
     }
     double beta = 0.0;
-    if (k == 0 || rho <= 0.5 * sc->rho_best) {
+    if (k == 0 || rho <= 0.5 * lsc->rho_best) {
+      lsc->rho_best = rho;
+      lsc->k_best = k;
       sc->rho_best = rho;
       sc->k_best = k;
     }
     if (!isfinite(gg)) {
-      sc->done = 3;
-    } else if (rho <= sc->tol) {
-      sc->done = 1;
-    } else if (k >= sc->max_iter) {
-      sc->done = 2;
-    } else if (sc->stall_window > 0 && k - sc->k_best > sc->stall_window) {
-      sc->done = 4;  // stagnation: the block precision cannot resolve further progress
+      ls.done = sc->done = 3;
+    } else if (rho <= lsc->tol) {
+      ls.done = sc->done = 1;
+    } else if (k >= lsc->max_iter) {
+      ls.done = sc->done = 2;
+    } else if (lsc->stall_window > 0 && k - lsc->k_best > lsc->stall_window) {
+      ls.done = sc->done = 4;  // stagnation: the block precision cannot resolve further progress
     } else {
-      const bool restart = sc->method == 1 || k == 0 || sc->restart_next ||
-                           (sc->k_restart > 0 && k % sc->k_restart == 0) || !(sc->gg_old > 0.0);
-      beta = restart ? 0.0 : (gg - gdot) / sc->gg_old;
+      const bool restart = lsc->method == 1 || k == 0 || lsc->restart_next ||
+                           (lsc->k_restart > 0 && k % lsc->k_restart == 0) || !(lsc->gg_old > 0.0);
+      beta = restart ? 0.0 : (gg - gdot) / lsc->gg_old;
       sc->restart = restart ? 1 : 0;
       sc->restart_next = 0;
       sc->null_step = 0;
       sc->beta_pr = beta;
-      if (k < sc->hist_cap) hist[(int64_t)k * H_FIELDS + H_BETA] = beta;
+      if (k < lsc->hist_cap) hist[(int64_t)k * H_FIELDS + H_BETA] = beta;
     }
     sbeta = beta;
   }
   __syncthreads();
-  if (sc->done) return;
+  if (ls.done) return;
   const double beta = sbeta;
   double* Kd = small + S_KD * PP * PP;
   double* Ks = small + S_K * PP * PP;
@@ -134,29 +150,35 @@ __global__ __launch_bounds__(WG) void k_linesearch(const double* __restrict__ re
   __shared__ Terms terms;
   __shared__ double smu, sbmax;
   __shared__ int sok, sevals;
-  const int p = sc->p;
+  // the scalars read by the sequential tail, loaded by all threads at once
+  __shared__ Scalars ls;
+  for (int i = threadIdx.x; i < (int)(sizeof(Scalars) / 4); i += blockDim.x)
+    reinterpret_cast<int32_t*>(&ls)[i] = reinterpret_cast<const int32_t*>(sc)[i];
+  __syncthreads();
+  const int p = ls.p;
   linesearch_dev<PP>(red, red + PP * PP, small, p, reinterpret_cast<double*>(lds_raw), terms, &smu, &sok, &sevals,
                      &sbmax);
   if (threadIdx.x == 0) {
     sc->brent_evals = sevals;
     if (!sok) {
-      if (sc->restart) {
+      if (ls.restart) {
         sc->done = 3;
       } else {
         sc->null_step = 1;
         sc->restart_next = 1;
-        sc->n_null += 1;
+        sc->n_null = ls.n_null + 1;
       }
     } else {
-      const int k = sc->k;
+      const int k = ls.k;
       const double mu = smu;
+      const int refresh = (recompute_ax || mu * sqrt(sbmax) <= 1e3 * EPS) ? 1 : 0;
       sc->mu = mu;
-      sc->refresh = (recompute_ax || mu * sqrt(sbmax) <= 1e3 * EPS) ? 1 : 0;
-      if (k < sc->hist_cap) hist[(int64_t)k * H_FIELDS + H_MU] = mu;
-      sc->n_restart += sc->restart;
-      sc->n_refresh += sc->refresh;
-      sc->n_spmm += 1 + sc->refresh;
-      sc->gg_old = sc->gg;
+      sc->refresh = refresh;
+      if (k < ls.hist_cap) hist[(int64_t)k * H_FIELDS + H_MU] = mu;
+      sc->n_restart = ls.n_restart + ls.restart;
+      sc->n_refresh = ls.n_refresh + refresh;
+      sc->n_spmm = ls.n_spmm + 1 + refresh;
+      sc->gg_old = ls.gg;
       sc->k = k + 1;
     }
   }
