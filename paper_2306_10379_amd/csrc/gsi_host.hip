@@ -821,7 +821,10 @@ gsi_status create_impl(gsi_handle* out, const gsi_csr* A, const gsi_stencil* S, 
   (void)hipGetDevice(&dev);
   int ncu = 256;
   if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0) ncu = prop.multiProcessorCount;
-  h->nb = (int)(ntiles < 4 * ncu ? ntiles : 4 * ncu);
+  // two workgroups per CU for the streaming passes (the register-limited residency of the
+  // float64 passes at p = 64): more workgroups did not move the passes and only enlarge the
+  // per-workgroup partial sums the reductions read (measured at n = 128^3, p = 64)
+  h->nb = (int)(ntiles < 2 * (int64_t)ncu ? ntiles : 2 * (int64_t)ncu);
   h->hist_cap = opt->max_iter + 2;
   Dev& d = h->dev;
   if (A) {
