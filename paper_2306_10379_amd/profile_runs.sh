@@ -1,9 +1,9 @@
 #!/bin/bash
 # Regenerates the rocprofv3 summaries under profiles/. Run from the repository root on a
 # machine with the GPU (the library built): bash paper_2306_10379_amd/profile_runs.sh
-# Raw databases go to /tmp/gsi_prof (they exceed what a results folder should carry); the
-# rocprofv3 logs and the summaries are copied to gpurun_out/prof/. Each summary records the
-# command that produced it.
+# Raw databases go to /tmp/gsi_prof (they are too large to keep with the results); the
+# rocprofv3 logs and the summaries are copied to the results folder K below. Each summary
+# records the command that produced it.
 # rocprofv3 may exit with a segmentation fault after the profiled program has finished and
 # its database is complete; a step counts as done when its database exists.
 R=$(pwd)

@@ -3,7 +3,7 @@ sine-basis neural operator on the device, and start blocks for new problems.
 
 The solver always iterates to the tolerance from whatever block it is given, so the
 network can only change the number of iterations, never the accuracy: the residual test of
-the solve is the judge of the network's error. A problem whose warm-started solve does not
+the solve is what measures the network's error. A problem whose warm-started solve does not
 converge (for instance a rank-deficient network output that the start-block
 orthonormalization rejects) is solved again from its random start block, the fallback.
 """
