@@ -289,6 +289,9 @@ gsi_status init_state(gsi_ctx* h, Engine<T>& e, double tol, int max_iter, int hi
     s.hist_len = cont->hist_len;
     s.ginf0 = cont->ginf0;
     s.restart_next = cont->restart_next;
+    // the stall window of a continued solve counts from here
+    s.k_best = cont->k;
+    s.rho_best = 1e300;
   }
   s.nA = h->nA;
   s.tol = tol;
@@ -376,7 +379,7 @@ void launch_iteration(gsi_ctx* h, Engine<T>& e, double* hist) {
     {
       PassTimer t(h, GSI_PASS_UPDATE);
       Kernels<T, PP>::update(h->st, e.nb, e.n, e.X, e.Y, e.P0, e.P1, e.Z, e.small, e.sc, h->partials,
-                             e.explicit_grams);
+                               e.explicit_grams);
     }
     if (e.explicit_grams) {
       reduce(h, e.nb, 2 * P2, 2 * P2, e.sc, 1);
@@ -476,6 +479,26 @@ gsi_status run_until_done(gsi_ctx* h, Engine<T>& e, double* hist, Scalars* out, 
     GSI_TRY(hip_check(h, hipMemcpyAsync(out, e.sc, sizeof(Scalars), hipMemcpyDeviceToHost, h->st), "poll"));
     GSI_TRY(hip_check(h, hipStreamSynchronize(h->st), "iterate"));
     if (h->timing) collect_times(h);
+    if (out->done == 4 && e.P32) {
+      // the float32 copies of A and P set the attainable residual of this phase (their
+      // rounding enters the A X recursion and the line-search Grams): continue with the
+      // float64 SpMM from an explicit A X and C, without a stall window
+      e.P32 = nullptr;
+      e.vals32 = nullptr;
+      e.destroy_graph();
+      dispatch_pp<T>(e.PP, [&](auto PPc) {
+        constexpr int PP = decltype(PPc)::value;
+        spmm_op<T, PP>(h, e, e.X, e.X, e.Y, 0);
+        Kernels<T, PP>::gram(h->st, e.nb, e.n, e.X, e.X, e.Y, nullptr, e.sc, 0, h->partials);
+        reduce(h, e.nb, (int64_t)PP * PP, (int64_t)PP * PP, e.sc, 0);
+        launch_set_sym(h->st, PP, h->red, e.small + S_C * PP * PP);
+      });
+      out->done = 0;
+      out->stall_window = 0;
+      out->restart_next = 1;
+      GSI_TRY(hip_check(h, hipMemcpyAsync(e.sc, out, sizeof(Scalars), hipMemcpyHostToDevice, h->st), "resume"));
+      continue;
+    }
     if (out->done == 1 && verify) {
       // the AX recursion used float32-input SpMMs: confirm with A X and C in float64 and
       // let the next gradient pass test rho again (once; max_iter or a breakdown end at once)
@@ -525,7 +548,10 @@ gsi_status switch_to_fp64(gsi_ctx* h) {
   cont.restart_next = carry ? 0 : 1;
   if (cont.hist_len > k + 1) cont.hist_len = k + 1;
   h->hist_off = 0;
-  GSI_TRY(init_state(h, h->e64, h->opt.tol, h->opt.max_iter, 0, &cont));
+  // with the float32-input SpMM the float64 phase watches for a stall as well (a wide
+  // window: plain float64 progress can be slow); a stall there drops to the float64 SpMM
+  const int sw = h->opt.stall_window > 0 ? h->opt.stall_window : 60;
+  GSI_TRY(init_state(h, h->e64, h->opt.tol, h->opt.max_iter, 0, &cont, h->stencil ? 0 : 16 * sw));
   if (carry) {
     const int po = (k - 1) & 1;
     Engine<float>& a = h->e32;
@@ -753,18 +779,24 @@ gsi_status create_impl(gsi_handle* out, const gsi_csr* A, const gsi_stencil* S, 
   if (!h->st) {
     // graphs cannot be captured on the null stream: use an owned blocking stream, which
     // is ordered with the null stream
-    if (hipStreamCreate(&h->st) != hipSuccess) {
-      delete h;
+    const hipError_t se = hipStreamCreate(&h->st);
+    if (se != hipSuccess) {
+      h->st = nullptr;
+      h->err = std::string("stream creation failed: ") + hipGetErrorString(se);
+      *out = h;
       return GSI_EDEVICE;
     }
     h->own_stream = true;
   }
-  if (hipStreamCreate(&h->st2) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) {
-    h->err = "stream or event creation failed";
-    *out = h;
-    return GSI_EDEVICE;
+  {
+    hipError_t se = hipStreamCreate(&h->st2);
+    if (se == hipSuccess) se = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
+    if (se == hipSuccess) se = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming);
+    if (se != hipSuccess) {
+      h->err = std::string("stream or event creation failed: ") + hipGetErrorString(se);
+      *out = h;
+      return GSI_EDEVICE;
+    }
   }
   auto bail = [&](gsi_status s, const std::string& m) {
     // keep the handle so the caller can read the error text

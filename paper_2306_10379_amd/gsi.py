@@ -78,6 +78,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"libgsi.so not found at {path}; build it with `python -m paper_2306_10379_amd.build`")
+    # PyTorch ships its own HIP runtime under the same soname: loaded first, it is the one the
+    # library binds to, so both use one runtime (loaded the other way round, the process would
+    # hold two runtimes and the library's would find no device)
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     P = ctypes.POINTER

@@ -519,3 +519,27 @@ def test_symmetry_check_on_request():
     H2[0, 1] = H2[0, 1] * np.exp(0.1j)
     with pytest.raises(gsi.GsiError):
         gsi.HermitianSolver(H2.tocsr(), Z0, 3, check_symmetric=True)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "bf16"])
+def test_mixed_precision_at_64_columns(precision):
+    # p = 50 (64 columns), tol 1e-10: after a bfloat16 phase that stops at rho ~ 2e-4 the
+    # float32-input SpMM of the float64 phase stalls near 2e-10; the stall drops it to the
+    # float64 SpMM, which reaches the tolerance
+    gsi = _gsi()
+    n, p = 4097, 50
+    A = I.spiked_sparse(n, 4, p, 61, gap=0.3)
+    X0 = I.start_block(n, p, 62)
+    print(f"mixed {precision} p={p}", flush=True)
+    ref = O.rcg(A, X0, tol=1e-10, max_iter=5000)
+    with gsi.Solver(A, X0, p, tol=1e-10, max_iter=5000, precision=precision, switch_tol=1e-5) as s:
+        r = s.run()
+        X = s.get_x().cpu().numpy()
+        c = s.counters()
+    print(f"  iterations {r.iters} (low {c['low_iters']}), oracle {ref.iters}", flush=True)
+    assert r.status == 0
+    assert c["low_iters"] > 0 and r.iters > c["low_iters"]
+    assert np.max(np.abs(r.ritz - ref.theta) / np.abs(ref.theta)) <= 1e-10
+    assert _true_rho(A, X) <= 1.05e-10
+    gap = float(np.min(np.abs(ref.theta[-1] - np.sort(np.linalg.eigvalsh(A.to_dense()))[::-1][p])))
+    assert O.principal_angles(X, ref.X).max() <= 10 * 1e-10 * O.norm_inf(A.to_scipy()) / gap
