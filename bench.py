@@ -271,6 +271,43 @@ def hermitian_leg(args, gsi, inputs, torch):
             "s": round(dt, 3), "iters": it, "status": status, "rho": rho, "ritz_first": float(ritz[0])}
 
 
+# The paper's table for its FD3D matrix (7-point Laplacian on 35 x 40 x 25, n = 35,000): RCG
+# iterations and seconds to ||G_k||_inf / ||G_0||_inf <= 1e-8, checked every 50 iterations,
+# MATLAB in double precision on hardware the paper does not state, X0 not stated (Sec. 6.4,
+# Table). (p, which): (iterations, seconds).
+PAPER_FD3D = {(16, 1): (1801, 10), (16, -1): (451, 2), (32, 1): (1051, 11), (32, -1): (3701, 40),
+              (64, 1): (901, 27), (64, -1): (1401, 42)}
+
+
+def paper_fd3d_leg(args, gsi, inputs, torch):
+    """The paper's FD3D cases on the GPU with the paper's stopping rule: the first iteration
+    with ||G_k||_inf / ||G_0||_inf <= 1e-8 (from the recorded history of a solve run past it),
+    also rounded up to the paper's checking interval of 50, and the time to it."""
+    A = inputs.laplacian_3d(35, 40, 25)
+    out = {"workload": "FD3D: 7-point Dirichlet Laplacian 35x40x25 (n=35000), RCG, X0 ~ N(0,1) seed 0, stop at "
+                       "||G_k||_inf/||G_0||_inf <= 1e-8 (the paper's rule)", "cases": []}
+    for (p, which), (pit, psec) in PAPER_FD3D.items():
+        X0 = inputs.start_block(A.n, p, 0)
+        s = gsi.Solver(A, X0, p, which=which, tol=1e-11, max_iter=8000, check_every=50)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        status, iters = s.solve()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        h = s.history()
+        s.close()
+        g = h["ginf_rel"]
+        hit = np.nonzero(g[1:] <= 1e-8)[0]
+        k = int(hit[0]) + 1 if hit.size else None
+        case = {"p": p, "target": "max" if which > 0 else "min", "paper_iters": pit, "paper_s": psec,
+                "gpu_iters": k, "gpu_iters_checked_every_50": (None if k is None else 50 * ((k - 1 + 49) // 50) + 1),
+                "gpu_s": (None if k is None else round(dt * k / max(iters, 1), 4)),
+                "gpu_ms_per_iter": round(1e3 * dt / max(iters, 1), 3)}
+        out["cases"].append(case)
+        log(f"fd3d p={p} {case['target']}: {k} iterations (paper {pit}), {case['gpu_s']} s (paper {psec} s)")
+    return out
+
+
 def batched_leg(args, gsi, inputs, torch):
     """Many small problems in one persistent launch: the whole batch to rho <= tol with float32
     blocks then float64 refinement, and with float64 blocks, against the plain float64 path
@@ -361,6 +398,7 @@ def main():
     ap.add_argument("--no-stencil", action="store_true",
                     help="skip the matrix-free stencil solve of the headline workload")
     ap.add_argument("--no-tracking", action="store_true", help="skip the subspace-tracking leg")
+    ap.add_argument("--no-paper", action="store_true", help="skip the paper's FD3D cases")
     ap.add_argument("--no-hermitian", action="store_true", help="skip the complex Hermitian leg")
     ap.add_argument("--warm-train", type=int, default=144)
     ap.add_argument("--warm-test", type=int, default=24)
@@ -486,6 +524,7 @@ def main():
     batched = None if args.no_batched else batched_leg(args, gsi, inputs, torch)
     c3 = c3_leg(args, gsi, inputs, torch) if args.c3 else None
     tracking = None if args.no_tracking else tracking_leg(args, gsi, inputs, torch)
+    paper = None if args.no_paper else paper_fd3d_leg(args, gsi, inputs, torch)
     hermitian = None if args.no_hermitian else hermitian_leg(args, gsi, inputs, torch)
     warm = None
     if args.warm:
@@ -532,6 +571,7 @@ def main():
         "random_sparse": c3,
         "warm_start": warm,
         "tracking": tracking,
+        "paper_fd3d": paper,
         "hermitian": hermitian,
         "roofline": roof,
         "cpu_baseline": cpu,
