@@ -100,10 +100,9 @@ __global__ __launch_bounds__(WG) void k_after_dir(int PP, const double* __restri
                                                   Scalars* __restrict__ sc) {
   if (sc->done) return;
   double* S = small + S_S * PP * PP;
-  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) {
-    const int i = e / PP, j = e % PP;
-    S[e] = 0.5 * (red[i * PP + j] + red[j * PP + i]);
-  }
+  // lane j of each wave, rows dealt to the waves (no division by the runtime PP)
+  for (int i = threadIdx.x >> 6; i < PP; i += blockDim.x >> 6)
+    for (int j = threadIdx.x & 63; j < PP; j += 64) S[i * PP + j] = 0.5 * (red[i * PP + j] + red[j * PP + i]);
   if (threadIdx.x == 0) {
     const double gp = red[PP * PP];
     sc->gp = gp;

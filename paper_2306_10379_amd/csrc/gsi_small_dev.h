@@ -115,28 +115,30 @@ __device__ inline int jacobi(int p, int ld, double* A, double* V, double* cs /* 
       __syncthreads();
       const int nrot = *nrot_s;
       if (nrot == 0) continue;  // uniform: every thread read the same value after the barrier
-      // rows: A <- J^T A
-      for (int e = threadIdx.x; e < nrot * p; e += blockDim.x) {
-        const int i = e / p, k = e % p;
-        const int u = uv[i] / MAXP, v = uv[i] % MAXP;
-        const double c = cs[2 * i], s = cs[2 * i + 1];
-        const double au = A[u * ld + k], av = A[v * ld + k];
-        A[u * ld + k] = c * au - s * av;
-        A[v * ld + k] = s * au + c * av;
-      }
+      // rows: A <- J^T A. Lane k of every wave takes column k (p <= 64), the waves take the
+      // rotations in turn: no integer division by the runtime p
+      const int k = threadIdx.x & 63, w0 = threadIdx.x >> 6, nw = blockDim.x >> 6;
+      if (k < p)
+        for (int i = w0; i < nrot; i += nw) {
+          const int u = uv[i] / MAXP, v = uv[i] % MAXP;
+          const double c = cs[2 * i], s = cs[2 * i + 1];
+          const double au = A[u * ld + k], av = A[v * ld + k];
+          A[u * ld + k] = c * au - s * av;
+          A[v * ld + k] = s * au + c * av;
+        }
       __syncthreads();
-      // columns: A <- A J, V <- V J
-      for (int e = threadIdx.x; e < nrot * p; e += blockDim.x) {
-        const int i = e / p, k = e % p;
-        const int u = uv[i] / MAXP, v = uv[i] % MAXP;
-        const double c = cs[2 * i], s = cs[2 * i + 1];
-        const double au = A[k * ld + u], av = A[k * ld + v];
-        A[k * ld + u] = c * au - s * av;
-        A[k * ld + v] = s * au + c * av;
-        const double vu = V[k * ld + u], vv = V[k * ld + v];
-        V[k * ld + u] = c * vu - s * vv;
-        V[k * ld + v] = s * vu + c * vv;
-      }
+      // columns: A <- A J, V <- V J (row k)
+      if (k < p)
+        for (int i = w0; i < nrot; i += nw) {
+          const int u = uv[i] / MAXP, v = uv[i] % MAXP;
+          const double c = cs[2 * i], s = cs[2 * i + 1];
+          const double au = A[k * ld + u], av = A[k * ld + v];
+          A[k * ld + u] = c * au - s * av;
+          A[k * ld + v] = s * au + c * av;
+          const double vu = V[k * ld + u], vv = V[k * ld + v];
+          V[k * ld + u] = c * vu - s * vv;
+          V[k * ld + v] = s * vu + c * vv;
+        }
       __syncthreads();
     }
     __syncthreads();
@@ -379,7 +381,10 @@ __device__ inline void linesearch_dev(const double* PZr, const double* PYr, doub
   // about (number of rotations) * eps, which would let X(mu) drift from orthonormality
   // step after step; one Newton step for the inverse square root of B = I + mu^2 S,
   // M <- M (3 I - M B M) / 2, restores M B M = I to second order.
-  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) T1[e] = V[e] / sqrt(1.0 + mu * mu * terms.b[e % PP]);
+  // (terms.a is free after Get_Mu: it holds the PP column factors (1 + mu^2 b)^{-1/2})
+  for (int i = threadIdx.x; i < PP; i += blockDim.x) terms.a[i] = 1.0 / sqrt(1.0 + mu * mu * terms.b[i]);
+  __syncthreads();
+  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) T1[e] = V[e] * terms.a[e % PP];
   __syncthreads();
   wg_mm<PP>(T1, false, V, true, Mc);  // Mc = V D V^T
   __syncthreads();
