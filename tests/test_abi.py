@@ -58,3 +58,36 @@ def test_network_parameter_count_matches_reference():
         assert L.fno_param_count(ctypes.byref(c)) == F.param_count(cfg)
     for bad in [(20, 6, 5, 2, 4, 1), (16, 40, 5, 2, 4, 1), (16, 6, 33, 2, 4, 1), (16, 6, 5, 2, 0, 1)]:
         assert L.fno_param_count(ctypes.byref(fno.FnoConfig(*bad))) == -1
+
+
+def test_ctypes_structs_match_the_header_layout(tmp_path):
+    # the ctypes mirrors of the C structs must have the header's sizes and field offsets:
+    # a small C program compiled against include/ prints them
+    import shutil
+    import subprocess
+    from paper_2306_10379_amd import fno, gsi
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"gsi_options": gsi.GsiOptions, "gsi_csr": gsi.GsiCsr, "gsi_stencil": gsi.GsiStencil,
+               "gsi_zcsr": gsi.GsiZcsr, "fno_config": fno.FnoConfig}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gsi.h"', '#include "fno.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            a, b, c = line.split()
+            got[(a, b)] = int(c)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
