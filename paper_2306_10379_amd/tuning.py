@@ -32,9 +32,11 @@ def _time(solver, policy):
     return time.perf_counter() - t0
 
 
-def tune(solver, start=DEFAULT, log=None):
-    """Returns (best policy, {policy: seconds}); the solver is left on the best policy."""
-    times = {tuple(start): _time(solver, start)}
+def tune(solver, start=DEFAULT, log=None, timer=None):
+    """Returns (best policy, {policy: seconds}); the solver is left on the best policy.
+    timer(solver, policy) -> seconds defaults to timing one whole solve."""
+    timer = timer or _time
+    times = {tuple(start): timer(solver, start)}
     best = tuple(start)
     if log:
         log(f"tuning {best}: {times[best]:.3f} s")
@@ -45,7 +47,7 @@ def tune(solver, start=DEFAULT, log=None):
             cand = tuple(cand)
             if cand in times:
                 continue
-            times[cand] = _time(solver, cand)
+            times[cand] = timer(solver, cand)
             if log:
                 log(f"tuning {cand}: {times[cand]:.3f} s")
         best = min(times, key=times.get)
