@@ -543,3 +543,46 @@ def test_mixed_precision_at_64_columns(precision):
     assert _true_rho(A, X) <= 1.05e-10
     gap = float(np.min(np.abs(ref.theta[-1] - np.sort(np.linalg.eigvalsh(A.to_dense()))[::-1][p])))
     assert O.principal_angles(X, ref.X).max() <= 10 * 1e-10 * O.norm_inf(A.to_scipy()) / gap
+
+
+def test_solver_options_explicit_grams_restarts_graph_and_timing():
+    # explicit C and W Grams in the retraction pass, periodic CG restarts (the k_restart = 75
+    # setting of Sec. 6.2), launches without a graph, and the per-pass timing mode
+    gsi = _gsi()
+    A = I.laplacian_2d(32)
+    p = 8
+    X0 = I.start_block(A.n, p, 2)
+    lam = laplacian_spectrum(32, 32)[:p]
+    print("options: explicit_c", flush=True)
+    ref = O.rcg(A, X0, tol=1e-10, max_iter=20000)
+    with gsi.Solver(A, X0, p, tol=1e-10, explicit_c=True) as s:
+        r = s.run()
+        X = s.get_x().cpu().numpy()
+    assert r.status == 0
+    assert np.max(np.abs(r.ritz - lam) / lam) <= 1e-10
+    assert O.principal_angles(X, ref.X).max() <= 1e-8
+    assert abs(r.iters - ref.iters) <= max(3, ref.iters // 20)
+    print("options: k_restart", flush=True)
+    ref75 = O.rcg(A, X0, tol=1e-10, max_iter=20000, k_restart=75)
+    with gsi.Solver(A, X0, p, tol=1e-10, k_restart=75) as s:
+        r = s.run()
+        hist = s.history()
+        c = s.counters()
+    assert r.status == 0
+    assert np.max(np.abs(r.ritz - lam) / lam) <= 1e-10
+    assert c["restarts"] >= r.iters // 75
+    k = min(100, len(ref75.mu))  # past the first periodic restart at k = 75
+    assert np.allclose(hist["mu"][:k], ref75.mu[:k], rtol=1e-6)
+    print("options: graph off, timing mode", flush=True)
+    runs = []
+    for graph, timing in ((True, False), (False, False), (True, True)):
+        with gsi.Solver(A, X0, p, tol=1e-10, use_graph=graph) as s:
+            if timing:
+                s.pass_times(1)
+            r = s.run()
+            runs.append((r.iters, s.get_x().cpu().numpy()))
+            if timing:
+                pt = s.pass_times(0)
+                assert pt["spmm"][1] >= r.iters and pt["grad"][0] > 0.0
+    assert runs[0][0] == runs[1][0] == runs[2][0]
+    assert np.array_equal(runs[0][1], runs[1][1]) and np.array_equal(runs[0][1], runs[2][1])
