@@ -586,3 +586,42 @@ def test_solver_options_explicit_grams_restarts_graph_and_timing():
                 assert pt["spmm"][1] >= r.iters and pt["grad"][0] > 0.0
     assert runs[0][0] == runs[1][0] == runs[2][0]
     assert np.array_equal(runs[0][1], runs[1][1]) and np.array_equal(runs[0][1], runs[2][1])
+
+
+def test_stepping_cap_and_argument_errors():
+    gsi = _gsi()
+    A = I.laplacian_2d(24)
+    p = 6
+    X0 = I.start_block(A.n, p, 4)
+    print("stepping", flush=True)
+    ref = O.rcg(A, X0, tol=1e-10, max_iter=20000)
+    # gsi_step in pieces: the iterates follow the same step sizes as one solve
+    with gsi.Solver(A, X0, p, tol=1e-10) as s:
+        for _ in range(4):
+            s.step(10)
+        torch.cuda.synchronize()
+        c = s.counters()
+        hist = s.history()
+        assert c["iters"] == 40
+        assert np.allclose(hist["mu"][:40], ref.mu[:40], rtol=1e-7)
+        r = s.run()
+        assert r.status == 0 and abs(r.iters - ref.iters) <= max(3, ref.iters // 20)
+    # the iteration cap: not converged, the basis still valid and its residual reported
+    with gsi.Solver(A, X0, p, tol=1e-12, max_iter=15) as s:
+        status, iters = s.solve()
+        ritz, res, rho, phi = s.residuals()
+        X = s.get_x().cpu().numpy()
+    assert status == gsi.GSI_NOT_CONVERGED and iters == 15
+    assert rho > 1e-12 and np.allclose(X.T @ X, np.eye(p), atol=1e-12)
+    # steepest descent in mixed precision reaches the float64 answer
+    print("rsd mixed", flush=True)
+    refs = O.rsd(A, X0, tol=1e-9, max_iter=50000)
+    with gsi.Solver(A, X0, p, tol=1e-9, method="rsd", precision="mixed", max_iter=50000) as s:
+        r = s.run()
+    assert r.status == 0 and np.max(np.abs(r.ritz - refs.theta) / np.abs(refs.theta)) <= 1e-9
+    # argument errors come back as statuses with a message, not crashes
+    for kw in (dict(p=A.n), dict(p=0), dict(p=4, which=0), dict(p=4, method=7), dict(p=4, precision=9),
+               dict(p=65), dict(p=4, tol=-1.0)):
+        q = kw.pop("p")
+        with pytest.raises(gsi.GsiError):
+            gsi.Solver(A, I.start_block(A.n, max(q, 1), 0) if 0 < q <= A.n else X0, q, **kw)
