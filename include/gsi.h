@@ -290,8 +290,9 @@ gsi_status gsi_create_batched(gsi_batch_handle* h, int32_t count, const gsi_csr*
  * status: host arrays of count (nullable); iters counts all iterations of both phases;
  * status per problem: 1 converged (rho <= tol), 2 max_iter, 3 breakdown. Returns
  * GSI_BREAKDOWN if any problem broke down, else GSI_NOT_CONVERGED if any reached max_iter,
- * else GSI_OK; GSI_EDEVICE if a team barrier waited longer than 30 s (the launch is then
- * abandoned by every workgroup; status 5). Syncs. */
+ * else GSI_OK; GSI_EDEVICE if a team barrier waited longer than the wait limit (30 s unless
+ * gsi_batched_set_wait_limit changed it): the launch is then abandoned by every team, whose
+ * problems get status 5, while problems solved by one workgroup finish normally. Syncs. */
 gsi_status gsi_solve_batched(gsi_batch_handle h, int32_t* iters, int32_t* status);
 /* Ritz values of problem i (host array of p[i], of A: largest first for which = +1, of -A
  * for which = -1, i.e. the negated smallest eigenvalues of A, largest first), its final rho
@@ -320,6 +321,12 @@ gsi_status gsi_batched_timeline(gsi_batch_handle h, double* begin_us, double* sw
  * paper_2306_10379_amd/tuning.py measures and picks per batch shape. Syncs. */
 gsi_status gsi_batched_set_tuning(gsi_batch_handle h, int32_t tiles_per_member, int32_t recruit_step,
                                   int32_t check_every);
+/* Longest wait of a workgroup at a team barrier, or for a team entry it has reserved, in the
+ * following solves (default 30 s; 0 < seconds <= 3600, else GSI_EINVAL). Every wait of the
+ * persistent launch is bounded by it, so a team whose member never arrives ends the launch
+ * with GSI_EDEVICE instead of holding the GPU. A very small limit forces that path from the
+ * host, which is how the abort handling is tested. Syncs. */
+gsi_status gsi_batched_set_wait_limit(gsi_batch_handle h, double seconds);
 /* Per-problem time per pass of the last solve in microseconds: host array of count x
  * GSI_NPASS, entry [i * GSI_NPASS + GSI_PASS_*] (GSI_PASS_REFRESH also holds the Cholesky
  * QR of the start block and the first A X, GSI_PASS_SMALL the p x p work outside the

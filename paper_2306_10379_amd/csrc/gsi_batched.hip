@@ -1367,6 +1367,21 @@ gsi_status gsi_batched_set_tuning(gsi_batch_handle b, int32_t tiles_per_member, 
   return GSI_OK;
 }
 
+gsi_status gsi_batched_set_wait_limit(gsi_batch_handle b, double seconds) {
+  if (!b || !(seconds > 0.0) || seconds > 3600.0) {
+    if (b) b->err = "wait limit: 0 < seconds <= 3600";
+    return GSI_EINVAL;
+  }
+  const double us = tick_us();
+  if (!(us > 0.0)) { b->err = "wait limit: wall clock rate unavailable"; return GSI_EDEVICE; }
+  BatchCtl ctl;
+  hipError_t e = hipMemcpy(&ctl, b->dctl, sizeof(ctl), hipMemcpyDeviceToHost);
+  ctl.timeout_ticks = (int64_t)(seconds * 1e6 / us) > 0 ? (int64_t)(seconds * 1e6 / us) : 1;
+  if (e == hipSuccess) e = hipMemcpy(b->dctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice);
+  if (e != hipSuccess) { b->err = std::string("wait limit: ") + hipGetErrorString(e); return GSI_EDEVICE; }
+  return GSI_OK;
+}
+
 gsi_status gsi_batched_timeline(gsi_batch_handle b, double* begin_us, double* switch_us, double* end_us,
                                 int32_t* iters_low, int32_t* team) {
   if (!b) return GSI_EINVAL;

@@ -23,7 +23,7 @@ EXPORTS = [
     "gsi_options_default", "gsi_create", "gsi_create_stencil", "gsi_create_hermitian", "gsi_hermitian_results", "gsi_recompute_choice", "gsi_step", "gsi_solve", "gsi_residuals", "gsi_get_x",
     "gsi_set_x0", "gsi_set_values", "gsi_spmm", "gsi_spmm_lowp", "gsi_history", "gsi_counters", "gsi_pass_times", "gsi_destroy",
     "gsi_status_str", "gsi_last_error", "gsi_create_batched", "gsi_solve_batched", "gsi_batched_results",
-    "gsi_batched_get_x", "gsi_batched_set_tuning", "gsi_batched_timeline", "gsi_batched_pass_times", "gsi_batched_last_error", "gsi_destroy_batched",
+    "gsi_batched_get_x", "gsi_batched_set_tuning", "gsi_batched_set_wait_limit", "gsi_batched_timeline", "gsi_batched_pass_times", "gsi_batched_last_error", "gsi_destroy_batched",
 ]
 PASSES = ["grad", "dir", "spmm", "update", "reduce", "small", "linesearch", "refresh", "eig", "gram"]
 
@@ -135,6 +135,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gsi_batched_get_x.restype = ctypes.c_int
     L.gsi_batched_set_tuning.argtypes = [vp, i32, i32, i32]
     L.gsi_batched_set_tuning.restype = ctypes.c_int
+    L.gsi_batched_set_wait_limit.argtypes = [vp, dbl]
+    L.gsi_batched_set_wait_limit.restype = ctypes.c_int
     L.gsi_batched_timeline.argtypes = [vp, P(dbl), P(dbl), P(dbl), P(i32), P(i32)]
     L.gsi_batched_timeline.restype = ctypes.c_int
     L.gsi_batched_pass_times.argtypes = [vp, P(dbl)]
@@ -526,6 +528,9 @@ class BatchedSolver:
     def set_tuning(self, tiles_per_member: int, recruit_step: int, check_every: int):
         _bcheck(self.h, load().gsi_batched_set_tuning(self.h, int(tiles_per_member), int(recruit_step),
                                                       int(check_every)))
+
+    def set_wait_limit(self, seconds: float):
+        _bcheck(self.h, load().gsi_batched_set_wait_limit(self.h, float(seconds)))
 
     def pass_times(self):
         return gsi_batched_pass_times(self.h, len(self.ps))

@@ -1,4 +1,6 @@
 """Parity of the HIP path (through the C ABI) with the FP64 CPU oracle."""
+import ctypes
+
 import numpy as np
 import scipy.sparse.linalg
 import pytest
@@ -216,6 +218,51 @@ def test_batched_team_matches_oracle(precision):
             bound = (rho + ref.rho[-1]) * np.sqrt(p) * nA / delta
             X = b.get_x(i).cpu().numpy()
             assert O.principal_angles(X, ref.X).max() <= max(bound, 1e-12)
+
+
+def test_batched_team_wait_limit_abort_and_recovery():
+    """A wait limit of 100 ns, set from the host, makes the first team barrier that is not
+    met at once end the team: the solve returns GSI_EDEVICE with status 5 for the team's
+    problem, while the problems solved by one workgroup finish and repeat their float64
+    results bit for bit. With the limit back at 30 s the same handle solves everything,
+    the big problem again by a team."""
+    gsi = _gsi()
+    L = gsi.load()
+    mats, X0s, ps = _schrodinger_batch(3, 17, nmin=10, nmax=14, pmin=3, pmax=6)
+    big = I.schrodinger_2d(72, I.random_wells(17_777, count=(4, 6)))
+    mats.insert(0, big)
+    ps.insert(0, 12)
+    X0s.insert(0, I.start_block(big.n, 12, 17_778))
+    tol = 1e-10
+    with gsi.BatchedSolver(mats, X0s, ps, which=-1, precision="fp64", tol=tol, max_iter=20000) as b:
+        with pytest.raises(gsi.GsiError):
+            b.set_wait_limit(0.0)
+        with pytest.raises(gsi.GsiError):
+            b.set_wait_limit(7200.0)
+        b.set_wait_limit(1e-7)
+        iters = (ctypes.c_int32 * len(ps))()
+        status = (ctypes.c_int32 * len(ps))()
+        print("batched wait limit 1e-7 s", flush=True)
+        st = L.gsi_solve_batched(b.h, iters, status)
+        status = np.array(status[:])
+        print(f"status {st} per problem {status}", flush=True)
+        assert st == gsi.GSI_EDEVICE
+        assert "team wait" in L.gsi_batched_last_error(b.h).decode()
+        assert status[0] == 5 and np.all(status[1:] == 1)
+        small = [b.results(i) for i in range(1, len(ps))]
+        b.set_wait_limit(30.0)
+        print("batched wait limit 30 s", flush=True)
+        st, it2, status2 = b.solve()
+        *_, team = b.timeline()
+        assert st == gsi.GSI_OK and np.all(status2 == 1) and team[0] > 1
+        assert np.array_equal(np.array(iters[1:]), it2[1:])
+        for i in range(1, len(ps)):
+            ritz, rho, _ = b.results(i)
+            assert np.array_equal(ritz, small[i - 1][0]) and rho == small[i - 1][1]
+        ritz, rho, _ = b.results(0)
+        assert rho <= tol
+        ref = O.rcg(big, X0s[0], tol=tol, which=-1, max_iter=20000)
+        assert np.max(np.abs(-ritz - ref.theta) / np.abs(ref.theta)) <= 1e-10
 
 
 def test_batched_repeat_solves_from_x0():
