@@ -214,7 +214,8 @@ gsi_status gsi_set_x0(gsi_handle h, const double* X0);
 /* Subspace tracking (Sec. 1 and 2.3: sequences of related eigenproblems, where a method that
  * can start from the previous subspace pays only for the change): replace the matrix values
  * by vals (device array of nnz float64 in the CSR order and sparsity pattern given at
- * creation), recompute ||A||_inf, and restart the iteration from the current basis, which
+ * creation; for a stencil handle, n float64 values that take the place of diag_vec, the
+ * diagonal term added to diag), recompute ||A||_inf, and restart the iteration from the current basis, which
  * stays the iterate (orthonormalized again; the solver state is reset as by gsi_set_x0).
  * Errors: GSI_EINVAL (null), GSI_BREAKDOWN (a non-finite value; the handle keeps the old
  * values), GSI_EDEVICE. */
@@ -224,9 +225,6 @@ gsi_status gsi_set_values(gsi_handle h, const double* vals);
  * device blocks. The same SpMM kernel the iteration uses. Asynchronous. */
 gsi_status gsi_spmm(gsi_handle h, const double* W, double* Z);
 
-/* Per-iteration history, host arrays of length >= count (nullable): rho, phi, mu, beta_pr
- * and ||G||_inf / ||G_0||_inf per recorded iterate. Returns the number of records in
- * *count (at most the capacity passed in *count). Syncs. */
 /* Z = A W (device, n x p float64 row-major in and out) in the handle's low-phase precision:
  * float32 values, W rounded to float32, float32 accumulation (GSI_MIXED_FP32), or bfloat16
  * values and W rounded to bfloat16 (nearest even), float32 accumulation (GSI_MIXED_BF16);
@@ -234,6 +232,10 @@ gsi_status gsi_spmm(gsi_handle h, const double* W, double* Z);
  * handle. For checking the low-precision SpMM; uses the handle's scratch blocks, so call it
  * between solves. */
 gsi_status gsi_spmm_lowp(gsi_handle h, const double* W, double* Z);
+
+/* Per-iteration history, host arrays of length >= count (nullable): rho, phi, mu, beta_pr
+ * and ||G||_inf / ||G_0||_inf per recorded iterate. Returns the number of records in
+ * *count (at most the capacity passed in *count). Syncs. */
 gsi_status gsi_history(gsi_handle h, int32_t* count, double* rho, double* phi, double* mu,
                        double* beta_pr, double* ginf_rel);
 

@@ -993,6 +993,10 @@ gsi_status gsi_create_hermitian(gsi_handle* out, const gsi_zcsr* A, const gsi_op
   if (rp[0] != 0 || rp[n] != nnz) return GSI_EINVAL;
   for (int64_t r = 0; r < n; ++r)
     if (rp[r + 1] < rp[r]) return GSI_EINVAL;
+  // a column index outside [0, n) would land in the other block of the embedding, where the
+  // check of the embedded matrix cannot see it
+  for (int64_t j = 0; j < nnz; ++j)
+    if (ci[j] < 0 || ci[j] >= n) return GSI_EINVAL;
   std::vector<int32_t> erp(2 * n + 1), eci;
   std::vector<double> eva;
   eci.reserve(4 * nnz);

@@ -54,6 +54,14 @@ def _p(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _need(t, name, shape):
+    """The library takes raw float32 device pointers: check what it will read."""
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()) or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must be a contiguous float32 device tensor of shape {tuple(shape)}, "
+                         f"got {t.dtype} {tuple(t.shape)}")
+
+
 class Net:
     """Owns an fno handle. Tensors are float32 (float64 for forward(..., f64=True)) on the
     handle's device; V is (B, N*N), targets (B, N*N, p)."""
@@ -83,12 +91,13 @@ class Net:
         return out
 
     def set_params(self, t):
-        assert t.dtype.is_floating_point and t.numel() == self.count and t.is_contiguous()
+        _need(t, "params", (self.count,))
         self._check(self.L.fno_set_params(self.h, _p(t)))
 
     def forward(self, V, f64=False):
         import torch
         B = V.shape[0]
+        _need(V, "V", (B, self.n))
         out = torch.empty((B, self.n, self.p), dtype=torch.float64 if f64 else torch.float32, device=V.device)
         self._check(self.L.fno_forward(self.h, _p(V), B, None if f64 else _p(out), _p(out) if f64 else None))
         return out
@@ -96,6 +105,8 @@ class Net:
     def loss_grad(self, V, Xs, want_grad=True):
         import torch
         B = V.shape[0]
+        _need(V, "V", (B, self.n))
+        _need(Xs, "Xs", (B, self.n, self.p))
         loss = (ctypes.c_double * B)()
         grad = torch.empty(self.count, dtype=torch.float32, device=V.device) if want_grad else None
         self._check(self.L.fno_loss_grad(self.h, _p(V), _p(Xs), B, loss, _p(grad)))

@@ -159,6 +159,13 @@ def _dptr(t) -> int:
     return int(t.data_ptr())
 
 
+def _need_shape(name, t, shape):
+    """The C ABI takes raw device pointers: a tensor of the wrong size would be read or
+    written out of bounds, so the binding checks every block against the sizes it stands for."""
+    if tuple(t.shape) != tuple(shape) and not (t.dim() == 1 and t.numel() == int(np.prod(shape))):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
 def options(**kw) -> GsiOptions:
     o = GsiOptions()
     load().gsi_options_default(ctypes.byref(o))
@@ -177,6 +184,10 @@ def gsi_create(rowptr, colind, vals, n: int, X0, opt: GsiOptions, stream=None):
                         ("vals", vals, torch.float64), ("X0", X0, torch.float64)):
         if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
             raise TypeError(f"{name} must be a contiguous {dt} device tensor")
+    _need_shape("rowptr", rowptr, (int(n) + 1,))
+    _need_shape("vals", vals, (colind.numel(),))
+    if 1 <= opt.p <= 64 and int(n) >= 1:  # the library rejects other sizes before reading X0
+        _need_shape("X0", X0, (int(n), int(opt.p)))
     csr = GsiCsr(n=int(n), nnz=int(colind.numel()), rowptr=_dptr(rowptr), colind=_dptr(colind), vals=_dptr(vals))
     h = ctypes.c_void_p()
     st = ctypes.c_void_p(stream if stream is not None else torch.cuda.current_stream().cuda_stream)
@@ -197,6 +208,8 @@ def gsi_create_stencil(S: Stencil, dvec, X0, opt: GsiOptions, stream=None):
         raise TypeError("X0 must be a contiguous float64 device tensor")
     if dvec is not None and (not dvec.is_cuda or dvec.dtype != torch.float64 or dvec.numel() != S.n):
         raise TypeError("diag_vec must be a float64 device tensor of n values")
+    if 1 <= opt.p <= 64 and min(int(S.nx), int(S.ny), int(S.nz)) >= 1:
+        _need_shape("X0", X0, (int(S.n), int(opt.p)))
     st_ = GsiStencil(nx=int(S.nx), ny=int(S.ny), nz=int(S.nz), diag=float(S.diag), off=float(S.off),
                      diag_vec=_dptr(dvec) if dvec is not None else None)
     h = ctypes.c_void_p()
@@ -329,6 +342,7 @@ class Solver:
             if b in opts:
                 opts[b] = int(bool(opts[b]))
         self.opt = options(p=self.p, **opts)
+        self.nnz = None if stencil else int(colind.numel())
         if stencil:
             self.h = gsi_create_stencil(A, dvec, X0, self.opt)
         else:
@@ -354,27 +368,36 @@ class Solver:
         import torch
         if not torch.is_tensor(X0):
             X0 = torch.as_tensor(np.ascontiguousarray(X0, dtype=np.float64), device=self.device)
-        gsi_set_x0(self.h, X0.contiguous())
+        X0 = X0.to(device=self.device, dtype=torch.float64).contiguous()
+        _need_shape("X0", X0, (self.n, self.p))
+        gsi_set_x0(self.h, X0)
 
     def set_values(self, vals):
-        """New matrix values (same sparsity pattern); the iteration restarts from the current
-        basis (subspace tracking)."""
+        """New matrix values (same sparsity pattern; for a stencil, the n values of its
+        diagonal term); the iteration restarts from the current basis (subspace tracking)."""
         import torch
         if not torch.is_tensor(vals):
             vals = torch.as_tensor(np.asarray(vals, dtype=np.float64), device=self.device)
-        gsi_set_values(self.h, vals.contiguous())
+        vals = vals.to(device=self.device, dtype=torch.float64).contiguous()
+        # a CSR handle takes nnz values; a stencil handle the n values of its diagonal term
+        _need_shape("vals", vals, (self.n if self.nnz is None else self.nnz,))
+        gsi_set_values(self.h, vals)
 
     def spmm(self, W):
         import torch
+        W = W.to(device=self.device, dtype=torch.float64).contiguous()
+        _need_shape("W", W, (self.n, self.p))
         Z = torch.empty_like(W)
-        gsi_spmm(self.h, W.contiguous(), Z)
+        gsi_spmm(self.h, W, Z)
         torch.cuda.synchronize()
         return Z
 
     def spmm_lowp(self, W):
         import torch
+        W = W.to(device=self.device, dtype=torch.float64).contiguous()
+        _need_shape("W", W, (self.n, self.p))
         Z = torch.empty_like(W)
-        gsi_spmm_lowp(self.h, W.contiguous(), Z)
+        gsi_spmm_lowp(self.h, W, Z)
         torch.cuda.synchronize()
         return Z
 
@@ -431,8 +454,14 @@ def gsi_create_batched(mats, ps, X0s, opt: GsiOptions, stream=None):
     import torch
     L = load()
     count = len(mats)
+    if len(ps) != count or len(X0s) != count:
+        raise ValueError("mats, ps and X0s must have the same length")
     csrs = (GsiCsr * count)()
     for i, (rp, ci, vv, n) in enumerate(mats):
+        _need_shape(f"rowptr[{i}]", rp, (int(n) + 1,))
+        _need_shape(f"vals[{i}]", vv, (ci.numel(),))
+        if 1 <= int(ps[i]) <= 64 and int(n) >= 1:
+            _need_shape(f"X0s[{i}]", X0s[i], (int(n), int(ps[i])))
         csrs[i] = GsiCsr(n=int(n), nnz=int(ci.numel()), rowptr=_dptr(rp), colind=_dptr(ci), vals=_dptr(vv))
     parr = (ctypes.c_int32 * count)(*[int(x) for x in ps])
     xarr = (ctypes.c_void_p * count)(*[_dptr(x) for x in X0s])
@@ -575,10 +604,13 @@ class HermitianSolver(Solver):
         self._vals = torch.as_tensor(np.ascontiguousarray(A.data.astype(np.complex128)).view(np.float64),
                                      device=device)
         if torch.is_tensor(X0):
-            X0r = torch.view_as_real(X0.contiguous()).contiguous()
+            X0r = torch.view_as_real(X0.to(device=device, dtype=torch.complex128).contiguous()).contiguous()
         else:
             X0r = torch.as_tensor(np.ascontiguousarray(np.asarray(X0, dtype=np.complex128)).view(np.float64),
                                   device=device)
+        if A.shape[0] != A.shape[1]:
+            raise ValueError(f"A must be square, got {A.shape}")
+        _need_shape("X0 (real view)", X0r, (n, 2 * int(p)))
         method = opts.pop("method", "rcg")
         opts["method"] = {"rsd": GSI_RSD, "rcg": GSI_RCG}[method] if isinstance(method, str) else method
         for b in ("use_graph", "explicit_c", "check_symmetric"):
@@ -600,6 +632,26 @@ class HermitianSolver(Solver):
             raise GsiError(s, msg)
         self.h = h
         self.device = self._rowptr.device
+
+    # the handle holds the real embedding (2n x 2p): the real-block calls of the base class
+    # would take blocks of the wrong size
+    def set_x0(self, X0):
+        raise GsiError(GSI_EUNSUPPORTED, "create a new HermitianSolver for a new start block")
+
+    def set_values(self, vals):
+        raise GsiError(GSI_EUNSUPPORTED, "create a new HermitianSolver for new values")
+
+    def spmm(self, W):
+        raise GsiError(GSI_EUNSUPPORTED, "spmm of the real embedding is not exposed")
+
+    def spmm_lowp(self, W):
+        raise GsiError(GSI_EUNSUPPORTED, "spmm of the real embedding is not exposed")
+
+    def get_x(self):
+        return self.results()[1]
+
+    def residuals(self):
+        raise GsiError(GSI_EUNSUPPORTED, "use results(): ritz values, complex basis and rho")
 
     def results(self):
         import torch

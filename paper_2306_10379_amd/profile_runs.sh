@@ -2,13 +2,13 @@
 # Regenerates the rocprofv3 summaries under profiles/. Run from the repository root on a
 # machine with the GPU (the library built): bash paper_2306_10379_amd/profile_runs.sh
 # Raw databases go to /tmp/gsi_prof (they are too large to keep with the results); the
-# rocprofv3 logs and the summaries are copied to the results folder K below. Each summary
-# records the command that produced it.
+# rocprofv3 logs go to $GSI_PROF_LOGS (default: prof_logs/ at the repository root). Each
+# summary records the command that produced it.
 # rocprofv3 may exit with a segmentation fault after the profiled program has finished and
 # its database is complete; a step counts as done when its database exists.
 R=$(pwd)
 O=/tmp/gsi_prof
-K=$R/gpurun_out/prof
+K=${GSI_PROF_LOGS:-$R/prof_logs}
 mkdir -p "$O" "$K"
 export TMPDIR=/tmp
 db() { find "$1" -name '*.db' | head -1; }

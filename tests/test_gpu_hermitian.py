@@ -80,6 +80,32 @@ def test_hermitian_rejects_p_above_32():
         gsi.HermitianSolver(H, _start(100, 33, 0), 33)
 
 
+def test_hermitian_rejects_out_of_range_columns_and_wrong_start_block():
+    """A column index of n would land in the other block of the real embedding: the library
+    rejects it (GSI_EINVAL) before building the embedding; a start block of the wrong shape
+    is caught by the binding."""
+    import ctypes
+    gsi = _gsi()
+    H = sps.csr_matrix(I.magnetic_lattice(6, seed=3))
+    H.sort_indices()
+    n, p = H.shape[0], 3
+    with pytest.raises(ValueError):
+        gsi.HermitianSolver(H, _start(n, p + 1, 0), p)
+    ci = H.indices.astype(np.int32).copy()
+    ci[-1] = n
+    rp = torch.as_tensor(H.indptr.astype(np.int32), device="cuda")
+    cd = torch.as_tensor(ci, device="cuda")
+    vv = torch.as_tensor(np.ascontiguousarray(H.data.astype(np.complex128)).view(np.float64), device="cuda")
+    x0 = torch.as_tensor(np.ascontiguousarray(_start(n, p, 1)).view(np.float64), device="cuda")
+    L = gsi.load()
+    z = gsi.GsiZcsr(n=n, nnz=int(H.nnz), rowptr=rp.data_ptr(), colind=cd.data_ptr(), vals=vv.data_ptr())
+    opt = gsi.options(p=p)
+    h = ctypes.c_void_p()
+    st = L.gsi_create_hermitian(ctypes.byref(h), ctypes.byref(z), ctypes.byref(opt), ctypes.c_void_p(x0.data_ptr()),
+                                ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == gsi.GSI_EINVAL and not h.value
+
+
 @pytest.mark.parametrize("N,p", [(23, 1), (23, 7)])
 def test_hermitian_ragged_rows_and_p1(N, p):
     # 2n = 1058 real rows (a partial last tile), p = 1 and an odd p

@@ -672,3 +672,14 @@ def test_stepping_cap_and_argument_errors():
         q = kw.pop("p")
         with pytest.raises(gsi.GsiError):
             gsi.Solver(A, I.start_block(A.n, max(q, 1), 0) if 0 < q <= A.n else X0, q, **kw)
+    # the binding checks block sizes against the handle before passing raw pointers on
+    with gsi.Solver(A, X0, p) as s:
+        for bad in (np.zeros((A.n, p + 1)), np.zeros((A.n - 1, p))):
+            with pytest.raises(ValueError):
+                s.set_x0(bad)
+            with pytest.raises(ValueError):
+                s.spmm(dev(bad))
+        with pytest.raises(ValueError):
+            s.set_values(np.ones(len(A.vals) - 1))
+    with pytest.raises(ValueError):
+        gsi.Solver(A, np.zeros((A.n, p - 1)), p)
