@@ -22,21 +22,26 @@ __device__ __forceinline__ void wave_sync() {
 // ---------------------------------------------------------------- dense PP x PP products
 
 // Cout = alpha * op(A) op(B) for PP x PP row-major operands (any memory space), f64 MFMA,
-// 16 x 16 output blocks dealt to the 4 waves. No barrier inside.
+// 16 x 16 output blocks dealt to the 4 waves. No barrier inside. The operands of a block
+// are all loaded before its products: from global memory the block then waits for one
+// round of loads instead of one per group of K steps (these single-workgroup kernels have
+// no other waves to hide the latency).
 template <int PP>
 __device__ inline void wg_mm(const double* A, bool ta, const double* B, bool tb, double* Cout, double alpha = 1.0) {
   constexpr int NBK = PP / 16;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, c = l & 15;
   for (int blk = w; blk < NBK * NBK; blk += 4) {
     const int ib = blk / NBK, jb = blk % NBK;
-    d4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
+    double a[PP / 4], b[PP / 4];
+#pragma unroll
     for (int s = 0; s < PP / 4; ++s) {
       const int k = 4 * s + g;
-      const double a = ta ? A[k * PP + 16 * ib + c] : A[(16 * ib + c) * PP + k];
-      const double b = tb ? B[(16 * jb + c) * PP + k] : B[k * PP + 16 * jb + c];
-      acc = mfma(a, b, acc);
+      a[s] = ta ? A[k * PP + 16 * ib + c] : A[(16 * ib + c) * PP + k];
+      b[s] = tb ? B[(16 * jb + c) * PP + k] : B[k * PP + 16 * jb + c];
     }
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < PP / 4; ++s) acc = mfma(a[s], b[s], acc);
 #pragma unroll
     for (int r = 0; r < 4; ++r) Cout[(16 * ib + g + 4 * r) * PP + 16 * jb + c] = alpha * acc[r];
   }

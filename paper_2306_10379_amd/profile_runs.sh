@@ -8,7 +8,8 @@
 # its database is complete; a step counts as done when its database exists.
 R=$(pwd)
 O=/tmp/gsi_prof
-K=${GSI_PROF_LOGS:-$R/prof_logs}
+K=${GSI_PROF_LOGS:-prof_logs}
+case "$K" in /*) ;; *) K=$R/$K ;; esac  # the steps run from /tmp
 mkdir -p "$O" "$K"
 export TMPDIR=/tmp
 db() { find "$1" -name '*.db' | head -1; }
