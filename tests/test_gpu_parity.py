@@ -635,6 +635,54 @@ def test_solver_options_explicit_grams_restarts_graph_and_timing():
     assert np.array_equal(runs[0][1], runs[1][1]) and np.array_equal(runs[0][1], runs[2][1])
 
 
+def test_c2_full_size_properties():
+    """The benchmark workload at its full size and in the benchmark's launch configuration
+    (3D Laplacian 128^3, n = 2,097,152, p = 64, float64, tol 1e-8, graph launches polled
+    every 50 iterations, X0 seed 0). Checked on the CPU from what the library returns:
+    the Ritz values against the 64 largest eigenvalues of the closed-form Dirichlet spectrum,
+    X^T X = I, the float64 residual A X - X (X^T A X) recomputed with scipy, the per-column
+    residuals the library reports, and sampled rows of the full-size SpMM."""
+    gsi = _gsi()
+    N, p, tol = 128, 64, 1e-8
+    print("c2 full size: building 128^3", flush=True)
+    A = I.laplacian_3d(N)
+    X0 = I.start_block(A.n, p, 0)
+    dev = torch.device("cuda:0")
+    rowptr = torch.as_tensor(A.rowptr.astype(np.int32), device=dev)
+    colind = torch.as_tensor(A.colind, device=dev)
+    vals = torch.as_tensor(A.vals, device=dev)
+    X0d = torch.as_tensor(X0, device=dev)
+    rows = np.sort(np.random.default_rng(5).choice(A.n, 64, replace=False))
+    with gsi.Solver((rowptr, colind, vals, A.n), X0d, p, tol=tol, max_iter=20000, check_every=50) as s:
+        Zs = s.spmm(X0d)[torch.as_tensor(rows, device=dev)].cpu().numpy()
+        print("c2 full size: solving", flush=True)
+        status, iters = s.solve()
+        ritz, col_res, rho, _ = s.residuals()
+        X = s.get_x().cpu().numpy()
+    print(f"c2 full size: status {status}, {iters} iterations, rho {rho:.3e}", flush=True)
+    As = A.to_scipy()
+    ref = As[rows] @ X0
+    assert np.max(np.abs(Zs - ref)) <= 1e-13 * np.max(np.abs(ref))
+    assert status == gsi.GSI_OK and rho <= tol
+    # the 64 largest sums of three one-dimensional eigenvalues 4 sin^2(k pi / (2 (N + 1)))
+    lam1 = np.sort(4.0 * np.sin(np.arange(1, N + 1) * np.pi / (2 * (N + 1))) ** 2)[-p:]
+    top = np.sort((lam1[:, None, None] + lam1[None, :, None] + lam1[None, None, :]).ravel())[::-1][:p]
+    AX = As @ X
+    C = X.T @ AX
+    R = AX - X @ C
+    nR = np.linalg.norm(R)
+    assert np.max(np.abs(X.T @ X - np.eye(p))) <= 1e-12
+    assert nR / (np.sqrt(p) * O.norm_inf(As)) <= 1.05 * tol
+    # each Ritz value lies within the residual norm of an eigenvalue; the subspace found is
+    # the dominant one, so the sorted values pair with the largest eigenvalues
+    assert np.max(np.abs(ritz - top)) <= nR, (np.max(np.abs(ritz - top)), nR)
+    # C and the column residuals are sums over 2^21 rows: rounding of about eps * 12 * 2^10.5
+    # per entry of C, and a few 1e-12 in norms of order 1e-7
+    assert np.allclose(np.sort(np.linalg.eigvalsh(0.5 * (C + C.T)))[::-1], ritz, rtol=0, atol=1e-10)
+    cr = np.linalg.norm(AX - X * ritz[None, :], axis=0)
+    assert np.allclose(cr, col_res, rtol=1e-3, atol=1e-10)
+
+
 def test_stepping_cap_and_argument_errors():
     gsi = _gsi()
     A = I.laplacian_2d(24)
