@@ -1,7 +1,8 @@
 // Batched solve: many independent eigenproblems of different n and p in one persistent
 // launch. Every workgroup pulls problem indices from an atomic queue (largest problems
 // first) and runs the whole Riemannian CG iteration for one problem with workgroup barriers
-// only: gradient, direction, eigendecomposition of P^T P, SpMM, Grams, line search and
+// (once the queue has drained, a running problem may recruit idle workgroups into a team
+// that splits its rows; see k_batched): gradient, direction, eigendecomposition of P^T P, SpMM, Grams, line search and
 // retraction (the same steps and readings as the single-problem path, see gsi_kernels.hip
 // and gsi_small.hip). The p x p state is float64. Blocks are float64, or float32 first and
 // float64 after: the float32 phase runs until rho <= switch_tol (or rho stops improving),

@@ -1,11 +1,13 @@
 // Host driver and C ABI of libgsi (see include/gsi.h).
 //
-// One handle owns device copies of the CSR matrix and X0, the tall blocks, the p x p
-// small state and the scalars. An iteration is a fixed launch sequence (gradient pass,
-// direction pass, SpMM with Gram epilogue, line search, retraction, optional explicit
-// A X); every kernel reads the control flags from device memory, so the sequence is
-// identical for all iterations, needs no host round trip and is captured once in a HIP
-// graph. The host only polls the convergence flag every check_every iterations.
+// One handle owns device copies of the operator (a CSR matrix or a stencil's diagonal) and
+// X0, the tall blocks, the p x p small state and the scalars. An iteration is a fixed launch
+// sequence (gradient pass, direction pass, eigendecomposition of P^T P on a second stream,
+// SpMM, its Gram pass, line search, retraction, optional explicit A X); subspace iteration
+// has its own sequence (si_iterate). Every kernel reads the control flags from device
+// memory, so the sequence is identical for all iterations, needs no host round trip and is
+// captured once in a HIP graph. The host only polls the convergence flag every check_every
+// iterations.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>

@@ -1,6 +1,7 @@
 // Streaming kernels over the tall n x p blocks: the fused gradient, direction and
-// retraction passes, the block SpMM with its Gram epilogue, generic Gram / product
-// passes and the fixed-order reduction of per-workgroup partial sums.
+// retraction passes, the block SpMM (CSR in float64, float32 or bfloat16, the filter step
+// of subspace iteration, the matrix-free stencil), the Gram and product passes and the
+// fixed-order reduction of per-workgroup partial sums.
 //
 // Every multi-workgroup kernel writes per-workgroup partial sums (Gram matrices and
 // scalars) to partials[blockIdx.x * nv + ...]; k_reduce sums them in a fixed order, so
@@ -219,8 +220,8 @@ __global__ __launch_bounds__(WG) void k_dir(int64_t n, const T* __restrict__ X, 
 }
 
 // ---------------------------------------------------------------- retraction pass
-// X <- (X - mu P) M and Y <- (Y - mu Z) M with M = V D_mu^{-1} V^T (Sec. 5.2, eq. Xnew_P;
-// Sec. 6.1, eq. save_matvec). In place. When the state asks for an explicit A X the Y
+// X <- (X - mu P) M and Y <- (Y - mu Z) M with M = V diag((1 + mu^2 b)^-1/2) V^T, the
+// inverse square root of I + mu^2 P^T P (Sec. 5.2, eq. Xnew_P; Sec. 6.1, eq. save_matvec). In place. When the state asks for an explicit A X the Y
 // update is skipped (Y is formed by the SpMM that follows). With GRAMS the pass also
 // accumulates X^T Y and X^T P of the new X (partials: 2 PP*PP).
 template <typename T, int PP, bool GRAMS>
@@ -299,11 +300,12 @@ __global__ __launch_bounds__(WG) void k_update(int64_t n, T* __restrict__ X, T* 
 
 // ---------------------------------------------------------------- block SpMM
 // Z = A_op W for a full symmetric CSR, W and Z row-major n x PP. One workgroup per TR-row
-// tile; the tiles are dealt so that the workgroups running on one XCD (blockIdx.x congruent
-// mod 8) sweep one contiguous slab of rows, which keeps the stencil neighbours of a slab
-// in that XCD's L2. A row is handled by LPR = PP / 4 lanes, each owning 4 consecutive
-// columns; the column indices and values of up to 8 nonzeros are loaded before the 8
-// gathers are issued, so each lane has up to 8 independent loads in flight.
+// tile; spmm_tile deals the tiles to the XCDs (blockIdx.x mod 8) so that the rows a tile's
+// gathers reach stay in that XCD's L2: one contiguous slab per XCD, or, for a banded matrix,
+// one chunk of every plane of rows after the other. The tile's CSR structure is staged in
+// LDS first (csr_stage). A row is handled by LPR = PP / 4 lanes, each owning 4 consecutive
+// columns; the column indices and values of up to 8 nonzeros are read before the 8 gathers
+// are issued, so each lane has up to 8 independent loads in flight.
 // mode 0: always run, W = W0. mode 1: the iteration's SpMM (skipped when the solve is done
 // or the step is null), W = P of the current iteration (W0/W1 by parity). mode 2: explicit
 // A X (runs only when requested).

@@ -4,8 +4,9 @@
 // the exact line search (bracket from the branch roots, Brent's method on phi'), the
 // retraction factor M, Cholesky QR and Rayleigh-Ritz.
 //
-// The p x p matrices live in the small buffer as PP x PP row-major arrays (PP = p rounded
-// up to 16) whose padding is zero; dense products among them use f64 MFMA.
+// The p x p matrices live in the small buffer as PP x PP row-major arrays (PP = 16, 32 or
+// 64, the smallest that holds p) whose padding is zero; dense products among them use f64
+// MFMA.
 #include <math.h>
 
 #include "gsi_kernels.h"
