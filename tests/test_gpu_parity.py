@@ -635,6 +635,58 @@ def test_solver_options_explicit_grams_restarts_graph_and_timing():
     assert np.array_equal(runs[0][1], runs[1][1]) and np.array_equal(runs[0][1], runs[2][1])
 
 
+def test_degenerate_inputs():
+    """Cases the method degenerates on. A = 3 I: every subspace is invariant, the gradient
+    vanishes at the start, so the solve stops at iteration 0 with Ritz values 3 and the span
+    of X0. Empty rows (every third row of a diagonal matrix stores nothing, spread over
+    several tiles and a ragged tail): the dominant subspace is spanned by unit vectors with
+    the closed-form eigenvalues. Rank-deficient and zero start blocks are rejected with a
+    status (the Cholesky QR of X0 fails), not a crash."""
+    gsi = _gsi()
+    n, p = 500, 8
+    eye = I.CSR(n=n, rowptr=np.arange(n + 1, dtype=np.int32), colind=np.arange(n, dtype=np.int32),
+                vals=np.full(n, 3.0))
+    X0 = I.start_block(n, p, 31)
+    print("degenerate: 3 I", flush=True)
+    with gsi.Solver(eye, X0, p, tol=1e-10) as s:
+        r = s.run()
+        X = s.get_x().cpu().numpy()
+    assert r.status == 0 and r.iters == 0
+    assert np.max(np.abs(r.ritz - 3.0)) <= 1e-13
+    assert O.principal_angles(X, np.linalg.qr(X0)[0]).max() <= 1e-12
+    # empty rows
+    n = 400
+    stored = [r_ for r_ in range(n) if r_ % 3 != 1]
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    for r_ in range(n):
+        rowptr[r_ + 1] = rowptr[r_] + (1 if r_ % 3 != 1 else 0)
+    B = I.CSR(n=n, rowptr=rowptr, colind=np.array(stored, dtype=np.int32),
+              vals=np.array([1.0 + r_ / 100.0 for r_ in stored]))
+    X0 = I.start_block(n, 6, 32)
+    print("degenerate: empty rows", flush=True)
+    with gsi.Solver(B, X0, 6, tol=1e-10, max_iter=20000) as s:
+        Z = s.spmm(dev(X0)).cpu().numpy()
+        r = s.run()
+        X = s.get_x().cpu().numpy()
+    assert np.array_equal(Z[1::3], np.zeros_like(Z[1::3]))
+    assert np.max(np.abs(Z - B.to_scipy() @ X0)) <= 1e-14
+    top = sorted(stored)[-6:][::-1]
+    assert r.status == 0
+    assert np.max(np.abs(r.ritz - np.array([1.0 + t / 100.0 for t in top]))) <= 1e-10 * 5
+    E = np.zeros((n, 6))
+    E[top, np.arange(6)] = 1.0
+    assert O.principal_angles(X, E).max() <= 1e-7
+    ref = O.rcg(B, X0, tol=1e-10, max_iter=20000)
+    assert abs(r.iters - ref.iters) <= max(5, ref.iters // 10)
+    # start blocks without full column rank
+    X0 = I.start_block(n, 6, 33)
+    X0[:, 5] = X0[:, 2]
+    for bad in (X0, np.zeros((n, 6))):
+        with pytest.raises(gsi.GsiError) as e:
+            gsi.Solver(B, bad, 6)
+        assert e.value.status == gsi.GSI_BREAKDOWN
+
+
 def test_c2_full_size_properties():
     """The benchmark workload at its full size and in the benchmark's launch configuration
     (3D Laplacian 128^3, n = 2,097,152, p = 64, float64, tol 1e-8, graph launches polled
