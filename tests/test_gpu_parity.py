@@ -188,6 +188,39 @@ def test_batched_matches_single_problem_oracle(precision):
                 assert abs(iters[i] - ref.iters) <= max(5, 0.1 * ref.iters), (i, iters[i], ref.iters)
 
 
+def test_batched_extreme_block_sizes_and_batch_of_one():
+    """The ends of the batched ranges: p = 32 on a 36-row problem (one tile, p close to n),
+    p = 1 on 4096 and on 81 rows; solved together and as batches of one, each result
+    matches the oracle and the dense eigensolver. An empty batch and p = 33 are rejected."""
+    gsi = _gsi()
+    cases = [(6, 32, 41), (64, 1, 42), (9, 1, 43)]
+    mats = [I.schrodinger_2d(N, I.random_wells(seed)) for N, _, seed in cases]
+    ps = [p for _, p, _ in cases]
+    X0s = [I.start_block(A.n, p, seed + 100) for A, (_, p, seed) in zip(mats, cases)]
+    tol = 1e-10
+    refs = [O.rcg(A, X0, tol=tol, which=-1, max_iter=30000) for A, X0 in zip(mats, X0s)]
+    for sel in ([0, 1, 2], [0], [1]):
+        print(f"batched extremes: problems {sel}", flush=True)
+        with gsi.BatchedSolver([mats[i] for i in sel], [X0s[i] for i in sel], [ps[i] for i in sel], which=-1,
+                               precision="fp64", tol=tol, max_iter=30000) as b:
+            st, iters, status = b.solve()
+            assert st == gsi.GSI_OK and np.all(status == 1)
+            for j, i in enumerate(sel):
+                A, p, ref = mats[i], ps[i], refs[i]
+                ritz, rho, _ = b.results(j)
+                w = np.linalg.eigh(A.to_dense())[0]
+                assert rho <= tol
+                assert np.max(np.abs(-ritz - ref.theta) / np.abs(ref.theta)) <= 1e-10
+                assert np.max(np.abs(-ritz - w[:p]) / np.abs(w[:p])) <= 1e-10
+                bound = (rho + ref.rho[-1]) * np.sqrt(p) * O.norm_inf(A.to_scipy()) / (w[p] - w[p - 1])
+                assert O.principal_angles(b.get_x(j).cpu().numpy(), ref.X).max() <= max(bound, 1e-12)
+                assert abs(iters[j] - ref.iters) <= max(5, 0.1 * ref.iters)
+    with pytest.raises(gsi.GsiError):
+        gsi.BatchedSolver([], [], [], which=-1)
+    with pytest.raises(gsi.GsiError):
+        gsi.BatchedSolver([mats[1]], [I.start_block(mats[1].n, 33, 0)], [33], which=-1)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_batched_team_matches_oracle(precision):
     """A problem of 81 row tiles that outlives the small ones recruits the idle workgroups
