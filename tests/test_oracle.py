@@ -322,6 +322,23 @@ def test_rate_matches_condition_number_estimate():
     assert abs(slope / np.log(g_sd) - 1.0) < 0.5
 
 
+def test_restart_every_step_is_steepest_descent():
+    """A restart sets the direction to the projected gradient (Sec. 5.1), so with a restart
+    at every step (k_restart = 1) RCG takes exactly the steps of RSD; a restart period longer
+    than the solve changes nothing."""
+    A = I.laplacian_2d(10)
+    X0 = I.start_block(A.n, 3, 7)
+    r1 = O.rcg(A, X0, tol=1e-8, max_iter=5000, k_restart=1)
+    rs = O.rsd(A, X0, tol=1e-8, max_iter=5000)
+    assert r1.converged and rs.converged
+    assert r1.iters == rs.iters and np.array_equal(r1.mu, rs.mu)
+    assert all(b == 0.0 for b in r1.beta_pr)
+    r0 = O.rcg(A, X0, tol=1e-8, max_iter=5000)
+    rl = O.rcg(A, X0, tol=1e-8, max_iter=5000, k_restart=10 ** 6)
+    assert r0.iters == rl.iters and np.array_equal(r0.mu, rl.mu)
+    assert r0.iters < rs.iters
+
+
 def test_cholesky_qr2():
     X = I.start_block(500, 7, 3) @ np.diag([1, 10, 100, 1e3, 1e4, 1, 2.0])
     Q = O.cholesky_qr2(X)
@@ -329,15 +346,17 @@ def test_cholesky_qr2():
     assert O.subspace_distance(Q, O.orthonormalize(X)) < 1e-12
 
 
-def test_chebyshev_filter_is_the_scaled_polynomial():
+@pytest.mark.parametrize("lo,hi", [(-1.0, 1.0), (-0.5, 1.5)])
+def test_chebyshev_filter_is_the_scaled_polynomial(lo, hi):
     """The recurrence equals C_d((t - c)/h) / C_d((top - c)/h) applied to the eigenvalues of a
-    dense symmetric matrix (numpy's Chebyshev series evaluation, not the recurrence)."""
+    dense symmetric matrix (numpy's Chebyshev series evaluation, not the recurrence), for a
+    centred unwanted interval and one whose centre c is not 0 (so that the shift by c enters)."""
     import numpy.polynomial.chebyshev as npc
     n, p, d = 60, 4, 9
-    lam = np.concatenate([np.linspace(3.0, 2.2, p), np.linspace(1.0, -1.0, n - p)])
+    lam = np.concatenate([np.linspace(3.0, 2.2, p), np.linspace(hi, lo, n - p)])
     A = I.random_symmetric_dense(n, 3, spectrum=lam)
     X = I.start_block(n, p, 4)
-    lo, hi, top = -1.0, 1.0, 3.0
+    top = 3.0
     got = O.chebyshev_filter(A, X, A @ X, d, lo, hi, top)
     c, h = 0.5 * (lo + hi), 0.5 * (hi - lo)
     coef = np.zeros(d + 1)

@@ -1,5 +1,8 @@
 """The oracle's pins are sensitive: each plausible mistake, planted into the oracle on the
 CPU, makes at least one pin fail."""
+import inspect
+import textwrap
+
 import numpy as np
 import pytest
 
@@ -77,3 +80,76 @@ MUTATIONS = {
 def test_planted_mistake_is_caught(monkeypatch, name):
     monkeypatch.setattr(O, name, MUTATIONS[name])
     assert _some_pin_fails(), f"no pin caught a planted mistake in {name}"
+
+
+# ---- the filter, tracking, stencil and Hermitian parts of the oracle: each mistake is
+# planted by an exact one-place edit of the function's source, and must fail one of the
+# pins written for that part
+
+
+def _source_mutant(fn, old, new):
+    src = textwrap.dedent(inspect.getsource(fn))
+    assert src.count(old) == 1, (fn.__name__, old)
+    ns = {}
+    exec(compile(src.replace(old, new), f"<planted mistake in {fn.__name__}>", "exec"), fn.__globals__, ns)
+    return ns[fn.__name__]
+
+
+_CHEB_PINS = [lambda: T.test_chebyshev_filter_is_the_scaled_polynomial(-1.0, 1.0),
+              lambda: T.test_chebyshev_filter_is_the_scaled_polynomial(-0.5, 1.5),
+              T.test_chebyshev_si_matches_brute_force_and_needs_fewer_products]
+_HERM_PINS = [T.test_hermitian_rcg_magnetic_ring_closed_form, T.test_hermitian_rcg_dense_random_matches_library_eigh,
+              T.test_hermitian_rcg_on_a_real_matrix_follows_the_real_iteration]
+
+SOURCE_MUTATIONS = {
+    "chebyshev: sign of the normalization recurrence": (
+        "chebyshev_filter", "sigma_new = 1.0 / (2.0 / sigma1 - sigma)", "sigma_new = 1.0 / (2.0 / sigma1 + sigma)",
+        _CHEB_PINS),
+    "chebyshev: shift dropped in the recurrence": (
+        "chebyshev_filter", "(A_op @ cur - c * cur)", "(A_op @ cur)", _CHEB_PINS),
+    "chebyshev: first step unshifted": (
+        "chebyshev_filter", "cur = (sigma1 / h) * (Y - c * X)", "cur = (sigma1 / h) * Y", _CHEB_PINS),
+    "rcg: restart period off by one": (
+        "rcg", "(k_restart > 0 and k % k_restart == 0)", "(k_restart > 0 and k % (k_restart + 1) == 0)",
+        [T.test_restart_every_step_is_steepest_descent]),
+    "rcg: Fletcher-Reeves instead of Polak-Ribiere": (
+        "rcg", "beta_pr = (gg - float(np.sum(G_old * G))) / den", "beta_pr = gg / den",
+        [T.test_hermitian_rcg_on_a_real_matrix_follows_the_real_iteration]),
+    "rcg: conjugate direction not projected onto the tangent space": (
+        "rcg", "P = tangent(X, G + beta_pr * P_old)", "P = G + beta_pr * P_old", [T.test_c1_rcg_matches_closed_form]),
+    "rcg: sqrt(p) dropped from rho": (
+        "rcg", "rho = np.sqrt(gg) / (np.sqrt(p) * nA)", "rho = np.sqrt(gg) / nA",
+        [T.test_c1_rsd_matches_closed_form_and_invariants]),
+    "tracking: every matrix restarted from X0": (
+        "track", "X = r.X", "X = X", [T.test_track_restarts_from_previous_subspace]),
+    "stencil: y neighbour at ny instead of nx": (
+        "stencil_matrix", "(j < ny - 1, nx)", "(j < ny - 1, ny)", [T.test_stencil_matrix_spectrum_is_the_closed_form]),
+    "stencil: opposite signs on the two sides of a bond": (
+        "stencil_matrix", "vals += [np.full(a.size, float(off))] * 2",
+        "vals += [np.full(a.size, float(off)), np.full(a.size, -float(off))]",
+        [T.test_stencil_matrix_spectrum_is_the_closed_form]),
+    "hermitian: transpose without conjugation in C": (
+        "rcg_hermitian", "C = herm(X.conj().T @ Y)", "C = herm(X.T @ Y)", _HERM_PINS),
+    "hermitian: transpose without conjugation in the tangent projector": (
+        "rcg_hermitian", "tang = lambda D: D - X @ (X.conj().T @ D)", "tang = lambda D: D - X @ (X.T @ D)",
+        _HERM_PINS),
+    "hermitian: sign of zeta": (
+        "rcg_hermitian", "zeta = -np.real(np.diag(VH @ (P.conj().T @ Y) @ V))",
+        "zeta = np.real(np.diag(VH @ (P.conj().T @ Y) @ V))", _HERM_PINS),
+    "complex principal angles: transpose without conjugation": (
+        "principal_angles_complex", "X - Y @ (Y.conj().T @ X)", "X - Y @ (Y.T @ X)", _HERM_PINS),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SOURCE_MUTATIONS))
+def test_planted_source_mistake_is_caught(monkeypatch, name):
+    fname, old, new, pins = SOURCE_MUTATIONS[name]
+    monkeypatch.setattr(O, fname, _source_mutant(getattr(O, fname), old, new))
+    caught = False
+    for pin in pins:
+        try:
+            pin()
+        except Exception:
+            caught = True
+            break
+    assert caught, f"no pin caught: {name}"
