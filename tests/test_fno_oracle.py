@@ -136,3 +136,47 @@ def test_adam_first_step_moves_each_weight_by_lr():
     m, v = np.zeros(4), np.zeros(4)
     F.adam_step(flat, grad, m, v, 1, lr=0.01)
     assert np.allclose(flat, -0.01 * np.sign(grad) * np.abs(grad) / (np.abs(grad) + 1e-8), atol=1e-15)
+
+
+def test_forward_composes_the_layers_as_defined():
+    """The whole forward pass recomputed from the architecture's definition with scipy's
+    orthonormal DST-I (truncated to the m lowest modes) and erf, numpy products and the
+    flat parameter layout: lift, L hidden layers gelu(K(U) + W U + b), output prior + K(U) +
+    W U + b. Random parameters, several samples."""
+    cfg = F.Config(N=10, m=4, w=3, L=2, p=3)
+    flat = _rand_params(cfg, 21, scale=0.6)
+    V = -20.0 * np.random.default_rng(22).random((2, cfg.N * cfg.N))
+    N, m, w, p = cfg.N, cfg.m, cfg.w, cfg.p
+    off = 0
+
+    def take(*shape):
+        nonlocal off
+        size = int(np.prod(shape))
+        out = flat[off:off + size].reshape(shape)
+        off += size
+        return out
+
+    def K(U, R):
+        Uh = scipy.fft.dstn(U, type=1, norm="ortho", axes=(2, 3))[:, :, :m, :m]
+        full = np.zeros((U.shape[0], R.shape[0], N, N))
+        full[:, :, :m, :m] = np.einsum("ocij,bcij->boij", R, Uh)
+        return scipy.fft.idstn(full, type=1, norm="ortho", axes=(2, 3))
+
+    def pw(U, W, b):
+        return np.einsum("oc,bcij->boij", W, U) + b[None, :, None, None]
+
+    def gelu(t):
+        return 0.5 * t * (1.0 + scipy.special.erf(t / np.sqrt(2.0)))
+
+    t = np.arange(1, N + 1) / (N + 1)
+    In = np.stack([V.reshape(2, N, N) / 20.0, np.broadcast_to(t[None, :], (2, N, N)),
+                   np.broadcast_to(t[:, None], (2, N, N))], axis=1)
+    U = pw(In, take(w, 3), take(w))
+    for _ in range(cfg.L):
+        R, W, b = take(w, w, m, m), take(w, w), take(w)
+        U = gelu(K(U, R) + pw(U, W, b))
+    R, W, b = take(p, w, m, m), take(p, w), take(p)
+    assert off == flat.size
+    ref = F.prior(N, p).numpy()[None] + K(U, R) + pw(U, W, b)
+    got = F.forward(torch.as_tensor(flat), torch.as_tensor(V), cfg).numpy()
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-12)

@@ -153,3 +153,41 @@ def test_planted_source_mistake_is_caught(monkeypatch, name):
             caught = True
             break
     assert caught, f"no pin caught: {name}"
+
+
+# ---- the warm-start network's reference
+
+from oracle import fno_oracle as F  # noqa: E402
+from tests import test_fno_oracle as TF  # noqa: E402
+
+_FNO_PINS = [TF.test_forward_composes_the_layers_as_defined, TF.test_zero_network_outputs_the_prior_plus_output_bias,
+             TF.test_spectral_layer_reproduces_low_sine_modes, TF.test_loss_is_sum_of_squared_principal_angle_sines,
+             TF.test_adam_first_step_moves_each_weight_by_lr, TF.test_gradient_matches_central_differences]
+
+FNO_MUTATIONS = {
+    "network: gelu left out of the hidden layers": (
+        "forward", 'U = gelu(spectral(U, P[f"R{l}"], S) + pointwise(U, P[f"W{l}"], P[f"b{l}"]))',
+        'U = spectral(U, P[f"R{l}"], S) + pointwise(U, P[f"W{l}"], P[f"b{l}"])'),
+    "network: output spectral term dropped": ("forward", '+ spectral(U, P["R_out"], S) +', "+"),
+    "network: prior dropped": ("forward", "return prior(cfg.N, cfg.p)[None] + spectral", "return spectral"),
+    "network: sine transform transposed": ("spectral", "Uh = S @ U @ S.T", "Uh = S.T @ U @ S"),
+    "network: pointwise bias dropped": ("pointwise", " + b[None, :, None, None]", ""),
+    "loss: G^-1 left out": ("subspace_loss", "torch.linalg.solve(G, M)", "M"),
+    "adam: no bias correction of the first moment": ("adam_step", "mh = m / (1.0 - beta1 ** t)", "mh = m"),
+    "adam: second moment not squared": ("adam_step", "(1.0 - beta2) * grad * grad", "(1.0 - beta2) * grad"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(FNO_MUTATIONS))
+def test_planted_network_mistake_is_caught(monkeypatch, name):
+    fname, old, new = FNO_MUTATIONS[name]
+    monkeypatch.setattr(F, fname, _source_mutant(getattr(F, fname), old, new))
+    caught = False
+    for pin in _FNO_PINS:
+        try:
+            with np.errstate(all="ignore"):
+                pin()
+        except Exception:
+            caught = True
+            break
+    assert caught, f"no pin caught: {name}"
