@@ -344,6 +344,39 @@ def test_cholesky_qr2():
     Q = O.cholesky_qr2(X)
     assert np.linalg.norm(Q.T @ Q - np.eye(7)) < 1e-14
     assert O.subspace_distance(Q, O.orthonormalize(X)) < 1e-12
+    # columns that are nearly dependent (condition 1e6 after any column scaling): one
+    # Cholesky QR pass leaves Q^T Q - I near eps * kappa^2 = 1e-4, the second pass removes it
+    g = np.random.default_rng(4)
+    U, _ = np.linalg.qr(g.standard_normal((500, 5)))
+    W, _ = np.linalg.qr(g.standard_normal((5, 5)))
+    X = U @ np.diag([1.0, 1e-2, 1e-3, 1e-5, 1e-6]) @ W
+    Q = O.cholesky_qr2(X)
+    assert np.linalg.norm(Q.T @ Q - np.eye(5)) < 1e-13
+    assert O.subspace_distance(Q, U) < 1e-8
+
+
+def test_norm_inf_is_the_library_matrix_infinity_norm():
+    g = np.random.default_rng(6)
+    D = g.standard_normal((30, 20))
+    assert np.isclose(O.norm_inf(D), np.linalg.norm(D, np.inf), rtol=1e-15)
+    import scipy.sparse as sps
+    B = sps.random(200, 150, density=0.05, random_state=7, format="csr")
+    B.data -= 0.5
+    assert np.isclose(O.norm_inf(B), np.linalg.norm(B.toarray(), np.inf), rtol=1e-15)
+
+
+def test_rayleigh_ritz_on_an_invariant_subspace():
+    """For a basis of an exact invariant subspace (any rotation of dense eigenvectors) the
+    Ritz values are those eigenvalues, largest first, and every column residual vanishes."""
+    lam = np.array([5.0, 4.0, 3.0, 2.5, 1.0, 0.5, -1.0, -2.0])
+    A = I.random_symmetric_dense(8, 9, spectrum=lam)
+    w, V = np.linalg.eigh(A)
+    Wr, _ = np.linalg.qr(np.random.default_rng(3).standard_normal((3, 3)))
+    X = V[:, [7, 5, 6]] @ Wr            # the eigenvalues 5, 3, 4 in a rotated basis
+    th, Vr, res = O.rayleigh_ritz(A, X)
+    assert np.allclose(th, [5.0, 4.0, 3.0], atol=1e-13)
+    assert np.max(res) < 1e-13
+    assert np.allclose(A @ Vr, Vr * th, atol=1e-13)
 
 
 @pytest.mark.parametrize("lo,hi", [(-1.0, 1.0), (-0.5, 1.5)])

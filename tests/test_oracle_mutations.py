@@ -120,6 +120,20 @@ SOURCE_MUTATIONS = {
     "rcg: sqrt(p) dropped from rho": (
         "rcg", "rho = np.sqrt(gg) / (np.sqrt(p) * nA)", "rho = np.sqrt(gg) / nA",
         [T.test_c1_rsd_matches_closed_form_and_invariants]),
+    "norm: column sums instead of row sums": (
+        "norm_inf", "float(abs(A).sum(axis=1).max())", "float(abs(A).sum(axis=0).max())",
+        [T.test_norm_inf_is_the_library_matrix_infinity_norm]),
+    "Rayleigh-Ritz: residuals paired with the reversed Ritz values": (
+        "rayleigh_ritz", "R = AX @ U - V * w", "R = AX @ U - V * w[::-1]", [T.test_rayleigh_ritz_on_an_invariant_subspace]),
+    "Cholesky QR: a single pass": ("cholesky_qr2", "for _ in range(2):", "for _ in range(1):", [T.test_cholesky_qr2]),
+    "Cholesky QR: lower factor used as the upper one": (
+        "cholesky_qr2", "R = np.linalg.cholesky(sym(X.T @ X)).T", "R = np.linalg.cholesky(sym(X.T @ X))",
+        [T.test_cholesky_qr2]),
+    "principal angles: arccos of the cosines only": (
+        "principal_angles", "return np.arctan2(s, c)", "return np.arccos(np.minimum(c[::-1], 1.0))",
+        [T.test_cholesky_qr2, T.test_shift_invariance_and_basis_equivariance]),
+    "tangent projector: wrong sign": (
+        "tangent", "return D - X @ (X.T @ D)", "return D + X @ (X.T @ D)", [T.test_c1_rcg_matches_closed_form]),
     "tracking: every matrix restarted from X0": (
         "track", "X = r.X", "X = X", [T.test_track_restarts_from_previous_subspace]),
     "stencil: y neighbour at ny instead of nx": (
