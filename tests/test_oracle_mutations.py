@@ -134,6 +134,24 @@ SOURCE_MUTATIONS = {
         [T.test_cholesky_qr2, T.test_shift_invariance_and_basis_equivariance]),
     "tangent projector: wrong sign": (
         "tangent", "return D - X @ (X.T @ D)", "return D + X @ (X.T @ D)", [T.test_c1_rcg_matches_closed_form]),
+    "line search: gamma from P^T A X": (
+        "linesearch_diagonals", 'gamma = np.einsum("ki,kl,li->i", V, sym(PtZ), V)',
+        'gamma = np.einsum("ki,kl,li->i", V, sym(PtY), V)', [T.test_get_mu_p1_equals_two_by_two_rayleigh_ritz]),
+    "line search: alpha from P^T P": (
+        "linesearch_diagonals", 'alpha = np.einsum("ki,kl,li->i", V, C, V)',
+        'alpha = np.einsum("ki,kl,li->i", V, sym(S), V)', [T.test_get_mu_p1_equals_two_by_two_rayleigh_ritz]),
+    "Get_Mu: bracket at the last sign change": (
+        "get_mu", "            break\n        lo = float(c)", "        lo = float(c)", [T.test_get_mu_is_minimiser_on_a_scan]),
+    "Get_Mu: descent test at 0 flipped": ("get_mu", "if f(0.0) >= 0.0:", "if f(0.0) <= 0.0:",
+                                          [T.test_get_mu_is_minimiser_on_a_scan]),
+    "Get_Mu: bracket widened by halving": (
+        "get_mu", "c = 2.0 * (lo if lo > 0.0 else 1.0)", "c = 0.5 * (lo if lo > 0.0 else 1.0)",
+        [T.test_get_mu_p1_equals_two_by_two_rayleigh_ritz]),
+    "retraction: no square root in D_mu": (
+        "retraction", "M = (V * (1.0 / np.sqrt(1.0 + mu * mu * b))) @ V.T", "M = (V * (1.0 / (1.0 + mu * mu * b))) @ V.T",
+        [T.test_retraction_is_polar_factor_and_orthonormal]),
+    "retraction: step taken along +P": (
+        "retraction", "return (X - mu * P) @ M, M", "return (X + mu * P) @ M, M", [T.test_c1_rcg_matches_closed_form]),
     "tracking: every matrix restarted from X0": (
         "track", "X = r.X", "X = X", [T.test_track_restarts_from_previous_subspace]),
     "stencil: y neighbour at ny instead of nx": (
