@@ -419,6 +419,39 @@ def test_chebyshev_si_matches_brute_force_and_needs_fewer_products():
     assert r_shift.converged and np.allclose(r_shift.theta, w[:p], rtol=1e-9)
 
 
+class _CountingMatrix(np.ndarray):
+    """A dense matrix that counts the block products A @ X it is asked for."""
+    products = 0
+
+    def __matmul__(self, other):
+        if isinstance(other, np.ndarray) and other.ndim == 2 and not isinstance(other, _CountingMatrix):
+            type(self).products += 1
+        return np.asarray(self) @ np.asarray(other)
+
+
+class _Counted:
+    def __init__(self, dense):
+        self.M = np.asarray(dense, dtype=np.float64).view(_CountingMatrix)
+
+    def to_scipy(self):
+        return self.M
+
+
+def test_block_product_counts_are_the_products_made():
+    """The SpMM counts the subspace iterations report (compared with RCG's per product with A)
+    equal the block products an operator that counts its own multiplications sees, apart
+    from the one Rayleigh-Ritz product at exit."""
+    A = I.laplacian_2d(8).to_dense()
+    w = np.sort(np.linalg.eigvalsh(A))[::-1]
+    X0 = I.start_block(64, 3, 6)
+    for run in (lambda op: O.subspace_iteration(op, X0, tol=1e-8, max_iter=5000),
+                lambda op: O.chebyshev_si(op, X0, 5, w[-1], w[3], w[0], tol=1e-8, max_iter=5000),
+                lambda op: O.rcg(op, X0, tol=1e-8, max_iter=5000)):
+        _CountingMatrix.products = 0
+        r = run(_Counted(A))
+        assert r.converged and _CountingMatrix.products == r.spmm + 1, (_CountingMatrix.products, r.spmm)
+
+
 def test_track_restarts_from_previous_subspace():
     # a repeated matrix converges at once from the previous basis, and the tracked subspace
     # of every step is the one dense diagonalization gives (independent of the start)

@@ -152,6 +152,13 @@ SOURCE_MUTATIONS = {
         [T.test_retraction_is_polar_factor_and_orthonormal]),
     "retraction: step taken along +P": (
         "retraction", "return (X - mu * P) @ M, M", "return (X + mu * P) @ M, M", [T.test_c1_rcg_matches_closed_form]),
+    "SI: the Rayleigh-Ritz product not counted": (
+        "subspace_iteration", "        AQ = A_op @ Q\n        res.spmm += 1", "        AQ = A_op @ Q",
+        [T.test_block_product_counts_are_the_products_made]),
+    "Chebyshev SI: filter products counted as degree": (
+        "chebyshev_si", "res.spmm += degree - 1", "res.spmm += degree", [T.test_block_product_counts_are_the_products_made]),
+    "Chebyshev SI: A X not rotated with the Ritz vectors": (
+        "chebyshev_si", "Y = AQ @ U", "Y = AQ", _CHEB_PINS),
     "tracking: every matrix restarted from X0": (
         "track", "X = r.X", "X = X", [T.test_track_restarts_from_previous_subspace]),
     "stencil: y neighbour at ny instead of nx": (
