@@ -408,8 +408,9 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="short run for hardware-counter profiling: K iterations without the graph, "
                          "then a plain 1 GiB device copy (three times) as the counter calibration; no JSON")
-    ap.add_argument("--profile-matrix", choices=["laplace3d", "spiked"], default="laplace3d",
-                    help="matrix of the profiling run: the 3D Laplacian of --grid, or the random-sparse leg's matrix")
+    ap.add_argument("--profile-matrix", choices=["laplace3d", "stencil", "spiked"], default="laplace3d",
+                    help="operator of the profiling run: the 3D Laplacian of --grid as CSR or matrix-free "
+                         "(stencil), or the random-sparse leg's matrix")
     ap.add_argument("--profile-precision", choices=["fp64", "fp32", "bf16"], default="fp64")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -436,7 +437,10 @@ def main():
     torch.cuda.synchronize()
 
     if args.profile_steps > 0:
-        s = gsi.Solver((rowptr, colind, vals, A.n), X0, p, tol=0.0, max_iter=args.profile_steps + 5,
+        op = (rowptr, colind, vals, A.n)
+        if args.profile_matrix == "stencil":
+            op = gsi.Stencil(N, N, N, diag=6.0, off=-1.0)
+        s = gsi.Solver(op, X0, p, tol=0.0, max_iter=args.profile_steps + 5,
                        use_graph=False, precision=args.profile_precision, switch_tol=0.0)
         s.step(args.profile_steps)
         torch.cuda.synchronize()
