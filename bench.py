@@ -21,6 +21,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+T_START = time.perf_counter()  # wall clock of the whole run (the budget counts from here)
+
+
+def elapsed():
+    return time.perf_counter() - T_START
 
 
 def log(msg):
@@ -75,7 +80,9 @@ def cpu_baseline(A, X0, p, tol, gpu_iters, iters=3):
     per_iter = ((t2 - t1) - (t1 - t0)) / iters
     setup = (t1 - t0) - per_iter
     value = setup + per_iter * gpu_iters
+    model, avail = cpu_info()
     return {"value": value, "unit": "s", "cores": cores, "kind": "oracle",
+            "cpu_model": model, "logical_cpus_available": avail,
             "sample": f"{iters} oracle RCG iterations on the same matrix and X0 "
                       f"({per_iter:.2f} s/iteration, setup {setup:.2f} s), "
                       f"extrapolated to the GPU's {gpu_iters} iterations"}
@@ -180,7 +187,7 @@ def stencil_leg(args, gsi, torch, X0, t_csr, it_csr, spmm_csr_us, csr):
     S = gsi.Stencil(N, N, N, diag=6.0, off=-1.0)
     s = gsi.Solver(S, X0, p, tol=args.tol, max_iter=20000, check_every=50)
     times, iters = [], 0
-    for i in range(1 + args.steps):
+    for i in range(1 + args.leg_steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s.set_x0(X0)
@@ -365,6 +372,42 @@ def batched_leg(args, gsi, inputs, torch):
     return res
 
 
+def cpu_info():
+    """Model name of the host CPU and the number of logical CPUs this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, avail
+
+
+# Extra legs in the order they run while the wall-clock budget lasts, with the estimate of
+# their cost in units of one headline float64 solve (t64) plus fixed seconds.
+LEG_COST = {"mixed": (3.2, 5.0), "stencil": (2.2, 10.0), "paper_fd3d": (0.0, 12.0), "si": (0.7, 10.0),
+            "tracking": (0.0, 12.0), "hermitian": (0.0, 8.0), "batched": (0.0, 120.0)}
+DEFAULT_LEGS = ["mixed", "stencil", "paper_fd3d", "si", "tracking", "hermitian", "batched"]
+
+
+def leg_estimate(leg, t_solve):
+    """Estimated seconds of an extra leg, given the mean headline solve time."""
+    k, c = LEG_COST[leg]
+    return k * t_solve + c
+
+
+def leg_fits(leg, t_solve, now, budget):
+    """Whether an extra leg started at `now` seconds is expected to end within the budget."""
+    return now + leg_estimate(leg, t_solve) <= budget
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -374,11 +417,20 @@ def main():
     ap.add_argument("--p", type=int, default=64)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--budget", type=float, default=500.0,
+                    help="wall-clock seconds from the start of the run: extra legs start only when their "
+                         "estimated cost still fits (the headline solves, the pass timing and the CPU "
+                         "baseline always run)")
+    ap.add_argument("--legs", default=",".join(DEFAULT_LEGS),
+                    help="comma list of extra legs to try after the headline, in this order, while the budget "
+                         f"lasts (any of {','.join(DEFAULT_LEGS)}; 'none' for the headline only)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--pass-iters", type=int, default=300,
+                    help="iterations of the per-kernel event timing run (from X0, direct launches)")
     ap.add_argument("--switch-tol", type=float, default=1e-6)
-    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--leg-steps", type=int, default=2,
+                    help="timed solves (after one untimed) of the mixed-precision and matrix-free legs")
     ap.add_argument("--tune", action="store_true",
                     help="time the batched solve under candidate team policies first and use the fastest")
     ap.add_argument("--legs-only", action="store_true",
@@ -390,16 +442,9 @@ def main():
     ap.add_argument("--c3", action="store_true",
                     help="also run the random-sparse leg: spiked sparse matrix n = 2^22, 24 random nonzeros per "
                          "row, p = 64 (float64, float32-mixed and bfloat16-mixed solves, SpMM rates; ~4 minutes)")
-    ap.add_argument("--no-si", action="store_true",
-                    help="skip the Chebyshev-filtered subspace iteration on the headline workload")
     ap.add_argument("--si-degrees", type=int, nargs="*", default=[64, 128])
     ap.add_argument("--si-full", action="store_true",
                     help="run the Chebyshev-filtered subspace iteration to the tolerance")
-    ap.add_argument("--no-stencil", action="store_true",
-                    help="skip the matrix-free stencil solve of the headline workload")
-    ap.add_argument("--no-tracking", action="store_true", help="skip the subspace-tracking leg")
-    ap.add_argument("--no-paper", action="store_true", help="skip the paper's FD3D cases")
-    ap.add_argument("--no-hermitian", action="store_true", help="skip the complex Hermitian leg")
     ap.add_argument("--warm-train", type=int, default=144)
     ap.add_argument("--warm-test", type=int, default=24)
     ap.add_argument("--batch", type=int, default=512)
@@ -414,8 +459,13 @@ def main():
     ap.add_argument("--profile-precision", choices=["fp64", "fp32", "bf16"], default="fp64")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on one GPU only (every GPU box here has one); "
+                                   "--gpus must be 1"}))
         sys.exit(2)
+    legs = [] if args.legs.strip() in ("", "none") else [x.strip() for x in args.legs.split(",")]
+    for x in legs:
+        if x not in LEG_COST:
+            ap.error(f"unknown leg {x}")
 
     import torch
     from paper_2306_10379_amd import gsi, inputs
@@ -435,6 +485,7 @@ def main():
     vals = torch.as_tensor(A.vals, device=dev)
     X0 = torch.as_tensor(X0h, device=dev)
     torch.cuda.synchronize()
+    log(f"inputs resident after {elapsed():.1f} s")
 
     if args.profile_steps > 0:
         op = (rowptr, colind, vals, A.n)
@@ -465,7 +516,7 @@ def main():
             status, iters = s.solve()
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
-            log(f"{precision} solve {i}: {dt:.3f} s, {iters} iterations, status {status}")
+            log(f"{precision} solve {i}: {dt:.3f} s, {iters} iterations, status {status} (elapsed {elapsed():.0f} s)")
             if i >= warmup:
                 times.append(dt)
         info = s.counters()
@@ -473,17 +524,20 @@ def main():
         return s, times, iters, info, ritz, rho
 
     if args.legs_only:
-        out = {"batched": None if args.no_batched else batched_leg(args, gsi, inputs, torch),
+        out = {"batched": batched_leg(args, gsi, inputs, torch) if "batched" in legs else None,
                "random_sparse": c3_leg(args, gsi, inputs, torch) if args.c3 else None}
         print(json.dumps(out), flush=True)
         return
 
-    # plain float64 solve (the headline), then mixed precision
+    # the headline: plain float64 solves, W untimed, then K timed
     s64, t64, it64, c64, ritz64, rho64 = timed_solves("fp64", args.steps, args.warmup)
-    # per-kernel durations with HIP events on the solver's stream, one extra solve
-    s64.pass_times(1)
+    lam_closed, _ = laplacian3d_top(N, p)
+    ritz_err_closed = float(np.max(np.abs(ritz64 - lam_closed) / np.abs(lam_closed)))
+    # per-kernel durations with HIP events on the stream each kernel runs on: a run of
+    # --pass-iters iterations from X0 with direct launches
     s64.set_x0(X0)
-    s64.solve()
+    s64.pass_times(1)
+    s64.step(args.pass_iters)
     pt = s64.pass_times(0)
     nb = pass_bytes(A.n, p, A.nnz, 8)
     kern = {}
@@ -501,41 +555,15 @@ def main():
     traffic = measured_traffic(f"gsi::k_{kname}<double, {PPd}",
                                f"traffic_laplace3d_{N}_p{p}_fp64.json")
     roof = {"bound": "hbm", "achieved": round(kern[dom]["GBps"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(kern[dom]["GBps"] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+            "frac": round(kern[dom]["GBps"] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": f"k_{kname}",
             "bytes_per_launch": nb[dom], "avg_us": round(kern[dom]["avg_us"], 2)}
     spmm_gbs = kern["spmm"]["GBps"]
+    spmm_roof = {"bound": "hbm", "achieved": round(spmm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": round(spmm_gbs / HBM_PEAK_GBS, 4), "kernel": "k_spmm",
+                 "traffic": measured_traffic(f"gsi::k_spmm<double, {PPd}>", f"traffic_laplace3d_{N}_p{p}_fp64.json"),
+                 "bytes_per_launch": nb["spmm"], "avg_us": round(kern["spmm"]["avg_us"], 2)}
     s64.close()
-
-    mixed = None
-    if not args.no_mixed:
-        s32, t32, it32, c32, ritz32, rho32 = timed_solves("mixed", args.steps, args.warmup)
-        s32.close()
-        mixed = {"value": round(float(np.mean(t32)), 4), "iters": it32, "low_iters": c32["low_iters"],
-                 "switch_tol": args.switch_tol,
-                 "speedup_vs_fp64": round(float(np.mean(t64) / np.mean(t32)), 3),
-                 "ritz_rel_err_vs_fp64": float(np.max(np.abs(ritz32 - ritz64) / np.abs(ritz64))),
-                 "rho": rho32}
-
-    stencil = None
-    if not args.no_stencil:
-        stencil = stencil_leg(args, gsi, torch, X0, float(np.mean(t64)), it64, kern["spmm"]["avg_us"],
-                              (rowptr, colind, vals, A.n))
-
-    si = None
-    if not args.no_si and args.si_degrees:
-        si = si_leg(args, gsi, torch, rowptr, colind, vals, A.n, X0, ritz64, c64["spmm"])
-
-    batched = None if args.no_batched else batched_leg(args, gsi, inputs, torch)
-    c3 = c3_leg(args, gsi, inputs, torch) if args.c3 else None
-    tracking = None if args.no_tracking else tracking_leg(args, gsi, inputs, torch)
-    paper = None if args.no_paper else paper_fd3d_leg(args, gsi, inputs, torch)
-    hermitian = None if args.no_hermitian else hermitian_leg(args, gsi, inputs, torch)
-    warm = None
-    if args.warm:
-        from paper_2306_10379_amd import warmstart
-        warm = warmstart.run_experiment(N=256, p=32, ntrain=args.warm_train, ntest=args.warm_test, epochs=30, batch=16,
-                                        lr=3e-3, tol=args.tol, nsingle=3, chunk=48, chunk_test=12,
-                                        compare_prior=False, warm_max_iter=20000, log=log)
+    log(f"headline done after {elapsed():.0f} s")
 
     cpu = None
     if not args.no_cpu:
@@ -543,7 +571,50 @@ def main():
         cpu = cpu_baseline(A, X0h, p, args.tol, it64, iters=args.cpu_iters)
         cpu["value"] = round(cpu["value"], 2)
 
-    value = float(np.mean(t64))
+    # extra legs while the budget lasts
+    t_solve = float(np.mean(t64))
+    results = {k: None for k in DEFAULT_LEGS}
+    skipped = []
+    for leg in legs:
+        est = leg_estimate(leg, t_solve)
+        if not leg_fits(leg, t_solve, elapsed(), args.budget):
+            skipped.append(leg)
+            log(f"skipping leg {leg}: estimated {est:.0f} s, {elapsed():.0f} of {args.budget:.0f} s used")
+            continue
+        t_leg = time.perf_counter()
+        if leg == "mixed":
+            s32, t32, it32, c32, ritz32, rho32 = timed_solves("mixed", args.leg_steps, 1)
+            s32.close()
+            results[leg] = {"value": round(float(np.mean(t32)), 4), "iters": it32, "low_iters": c32["low_iters"],
+                            "switch_tol": args.switch_tol, "steps": args.leg_steps, "warmup": 1,
+                            "speedup_vs_fp64": round(t_solve / float(np.mean(t32)), 3),
+                            "ritz_rel_err_vs_closed_form": float(np.max(np.abs(ritz32 - lam_closed) /
+                                                                        np.abs(lam_closed))),
+                            "ritz_rel_err_vs_fp64": float(np.max(np.abs(ritz32 - ritz64) / np.abs(ritz64))),
+                            "rho": rho32}
+        elif leg == "stencil":
+            results[leg] = stencil_leg(args, gsi, torch, X0, t_solve, it64, kern["spmm"]["avg_us"],
+                                       (rowptr, colind, vals, A.n))
+        elif leg == "si":
+            results[leg] = si_leg(args, gsi, torch, rowptr, colind, vals, A.n, X0, ritz64, c64["spmm"])
+        elif leg == "batched":
+            results[leg] = batched_leg(args, gsi, inputs, torch)
+        elif leg == "tracking":
+            results[leg] = tracking_leg(args, gsi, inputs, torch)
+        elif leg == "paper_fd3d":
+            results[leg] = paper_fd3d_leg(args, gsi, inputs, torch)
+        elif leg == "hermitian":
+            results[leg] = hermitian_leg(args, gsi, inputs, torch)
+        log(f"leg {leg}: {time.perf_counter() - t_leg:.1f} s (estimated {est:.0f} s), elapsed {elapsed():.0f} s")
+    c3 = c3_leg(args, gsi, inputs, torch) if args.c3 else None
+    warm = None
+    if args.warm:
+        from paper_2306_10379_amd import warmstart
+        warm = warmstart.run_experiment(N=256, p=32, ntrain=args.warm_train, ntest=args.warm_test, epochs=30, batch=16,
+                                        lr=3e-3, tol=args.tol, nsingle=3, chunk=48, chunk_test=12,
+                                        compare_prior=False, warm_max_iter=20000, log=log)
+
+    value = t_solve
     out = {
         "metric": "time to 1e-8 residual per solve (s) + SpMM HBM GB/s; mixed/warm vs plain FP64",
         "value": round(value, 4),
@@ -562,22 +633,28 @@ def main():
                                f"stop at rho=||G||_F/(sqrt(p)||A||_inf) <= {args.tol:g}",
                    "iterations": it64, "spmm_count": c64["spmm"], "restarts": c64["restarts"],
                    "eig_sweeps_per_iter": round(c64["eig_sweeps"] / max(it64, 1), 2),
-                   "final_rho": rho64},
+                   "final_rho": rho64, "ritz_rel_err_vs_closed_form": ritz_err_closed,
+                   "step_times_s": [round(x, 3) for x in t64]},
         "spmm_GBps": round(spmm_gbs, 1),
         "spmm_hbm_frac": round(spmm_gbs / HBM_PEAK_GBS, 4),
         "kernels": {k: {kk: (round(vv, 2) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kern.items()},
         "pass_share": {k: round(v[0] / total_ms, 4) for k, v in pt.items() if total_ms > 0},
-        "mixed_fp32": mixed,
-        "matrix_free": stencil,
-        "si_chebyshev": si,
-        "batched": batched,
+        "pass_timing": f"HIP events around every launch of {args.pass_iters} iterations from X0 (direct launches)",
+        "mixed_fp32": results["mixed"],
+        "matrix_free": results["stencil"],
+        "si_chebyshev": results["si"],
+        "batched": results["batched"],
         "random_sparse": c3,
         "warm_start": warm,
-        "tracking": tracking,
-        "paper_fd3d": paper,
-        "hermitian": hermitian,
+        "tracking": results["tracking"],
+        "paper_fd3d": results["paper_fd3d"],
+        "hermitian": results["hermitian"],
+        "skipped_legs": skipped,
+        "budget_s": args.budget,
+        "elapsed_s": round(elapsed(), 1),
         "roofline": roof,
+        "spmm_roofline": spmm_roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

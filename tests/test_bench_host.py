@@ -62,3 +62,15 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     line = r.stdout.strip().splitlines()[-1]
     assert r.returncode == 2 and "one GPU" in json.loads(line)["error"]
+
+
+def test_extra_legs_start_only_within_the_budget():
+    b = _bench()
+    # 25 headline solves of ~14 s and the CPU sample leave ~120 s of a 500 s budget
+    assert b.leg_fits("hermitian", 14.0, 380.0, 500.0)
+    assert not b.leg_fits("mixed", 14.0, 480.0, 500.0)
+    assert b.leg_estimate("mixed", 10.0) == 3.2 * 10.0 + 5.0
+    assert set(b.DEFAULT_LEGS) == set(b.LEG_COST)
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--legs", "nope"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "unknown leg" in r.stderr
