@@ -266,6 +266,20 @@ enum {
  * launches without the graph and polls every iteration. Syncs. */
 gsi_status gsi_pass_times(gsi_handle h, int32_t enable, double* ms, int32_t* counts);
 
+/* Orthonormalize a caller's block in place by two passes of Cholesky QR: X <- X R^{-1} with
+ * R^T R = X^T X (R upper triangular with a positive diagonal), twice; the result spans the
+ * same space as X with X^T X = I to rounding. This is the re-orthonormalization step the
+ * solver applies to its start block (the paper assumes an orthonormal X0, Sec. 3 and
+ * Algorithm 2; Cholesky QR is one of the admissible ways to produce it), offered as a call of
+ * its own. X: device array, n x p float64, row-major with leading dimension p, owned by the
+ * caller. 1 <= p <= 64 (GSI_EUNSUPPORTED above), n >= p (GSI_EINVAL otherwise, and for a null
+ * X). GSI_BREAKDOWN when a pivot of the factorization is not above 1e-13 times the largest
+ * diagonal entry of X^T X or is not finite (rank deficient or non-finite X): X then holds the
+ * input (first pass failed) or the result of the first pass. Work is ordered on hip_stream
+ * (NULL = default stream); allocates a 4.3 MB scratch buffer for the call and frees it; the
+ * Gram sums are added in a fixed order, so results repeat bit for bit. Syncs. */
+gsi_status gsi_orthonormalize(double* X, int64_t n, int32_t p, void* hip_stream);
+
 void gsi_destroy(gsi_handle h);
 const char* gsi_status_str(gsi_status s);
 const char* gsi_last_error(gsi_handle h);
