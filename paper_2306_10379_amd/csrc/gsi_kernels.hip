@@ -832,12 +832,12 @@ __global__ __launch_bounds__(WG) void k_gram(int64_t n, const T* __restrict__ A0
   }
 }
 
-// The iteration's two Grams P^T Z and P^T Y at PP = 64: wave w owns the 16 columns
+// A^T B1 and (TWO) A^T B2 at PP = 64 (the iteration's P^T Z and P^T Y): wave w owns the 16 columns
 // 16w .. 16w+15 of P (loaded at the top of each tile, so the loads overlap the staging) and
 // the eight 16 x 16 output blocks (w, q) of both Grams; each wave stages its 16 rows of Z
 // and Y in LDS, from where all four waves read them. Every row of P, Z and Y is read from
 // memory once per workgroup. Rows of a tile past n are the zero padding of the blocks.
-template <typename T, int PP>
+template <typename T, int PP, bool TWO>
 __global__ __launch_bounds__(WG) void k_gram2(int64_t n, const T* __restrict__ A0, const T* __restrict__ A1,
                                               const T* __restrict__ B1, const T* __restrict__ B2,
                                               const Scalars* __restrict__ sc, int mode,
@@ -876,7 +876,7 @@ __global__ __launch_bounds__(WG) void k_gram2(int64_t n, const T* __restrict__ A
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         z[k][v] = gld(reinterpret_cast<const V16*>(B1 + (base + r) * PP + sc4) + v);
-        y[k][v] = gld(reinterpret_cast<const V16*>(B2 + (base + r) * PP + sc4) + v);
+        if constexpr (TWO) y[k][v] = gld(reinterpret_cast<const V16*>(B2 + (base + r) * PP + sc4) + v);
       }
     }
 #pragma unroll
@@ -885,7 +885,7 @@ __global__ __launch_bounds__(WG) void k_gram2(int64_t n, const T* __restrict__ A
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         reinterpret_cast<V16*>(to_lds(sZ + r * PP + sc4))[v] = z[k][v];
-        reinterpret_cast<V16*>(to_lds(sY + r * PP + sc4))[v] = y[k][v];
+        if constexpr (TWO) reinterpret_cast<V16*>(to_lds(sY + r * PP + sc4))[v] = y[k][v];
       }
     }
     __syncthreads();
@@ -895,18 +895,18 @@ __global__ __launch_bounds__(WG) void k_gram2(int64_t n, const T* __restrict__ A
       for (int q = 0; q < 4; ++q) {
         const int idx = (4 * s + g) * PP + 16 * q + c;
         accZ[q] = mfma(pcol[s], sZ[idx], accZ[q]);
-        accY[q] = mfma(pcol[s], sY[idx], accY[q]);
+        if constexpr (TWO) accY[q] = mfma(pcol[s], sY[idx], accY[q]);
       }
     __syncthreads();
   }
-  double* out = partials + (int64_t)blockIdx.x * 2 * PP * PP;
+  double* out = partials + (int64_t)blockIdx.x * (TWO ? 2 : 1) * PP * PP;
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t o = (16 * w + rowof<T>(g, r)) * PP + 16 * q + c;
       out[o] = (double)accZ[q][r];
-      out[PP * PP + o] = (double)accY[q][r];
+      if constexpr (TWO) out[PP * PP + o] = (double)accY[q][r];
     }
 }
 
@@ -1130,8 +1130,8 @@ hipError_t set_lds_limits() {
   GSI_SET((k_product<T, PP>), Pass::Product)
   if constexpr (PP == 64) {
     if (e == hipSuccess)
-      e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_gram2<T, PP>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              2 * TR * PP * (int)sizeof(T));
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_gram2<T, PP, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 2 * TR * PP * (int)sizeof(T));
   }
 #undef GSI_SET
   return e;
@@ -1203,10 +1203,13 @@ template <typename T, int PP>
 void Kernels<T, PP>::gram(hipStream_t st, int nb, int64_t n, const T* A0, const T* A1, const T* B1, const T* B2,
                           const Scalars* sc, int mode, double* partials) {
   if constexpr (PP == 64) {
-    if (B2) {
-      k_gram2<T, PP><<<nb, WG, 2 * TR * PP * sizeof(T), st>>>(n, A0, A1, B1, B2, sc, mode, partials);
-      return;
-    }
+    // the staged pass; with one Gram (B2 == nullptr: X^T X of the orthonormalization,
+    // X^T A X of the Rayleigh-Ritz step) only B1 is staged
+    if (B2)
+      k_gram2<T, PP, true><<<nb, WG, 2 * TR * PP * sizeof(T), st>>>(n, A0, A1, B1, B2, sc, mode, partials);
+    else
+      k_gram2<T, PP, false><<<nb, WG, TR * PP * sizeof(T), st>>>(n, A0, A1, B1, B2, sc, mode, partials);
+    return;
   }
   k_gram<T, PP><<<nb, WG, 0, st>>>(n, A0, A1, B1, B2, sc, mode, partials);
 }

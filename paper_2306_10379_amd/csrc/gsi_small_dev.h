@@ -154,6 +154,236 @@ __device__ inline int jacobi(int p, int ld, double* A, double* V, double* cs /* 
   return sweep + 1;
 }
 
+// Reciprocal, reciprocal square root and square root in float64 from the hardware
+// approximations refined by two Newton steps each (the quadratic convergence takes the
+// approximation to the last bits); for positive normal arguments.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+
+// Parallel cyclic Jacobi, register-resident (used by the eigendecomposition of P^T P).
+//
+// The players 0..m-1 (m = p rounded up to even; an odd p gets one zero padding row) meet in
+// the round-robin order of the cyclic-by-rows parallel ordering: in round r, position 0
+// holds player 0 and position i >= 1 player ((i - 1 + r) mod (m - 1)) + 1, and positions
+// i and m-1-i form pair i. The matrix is held in "slot" order, slot 2i for position i and
+// slot 2i+1 for position m-1-i, so that every pair is a diagonal 2 x 2 block. Thread t < R h
+// (h = m / 2 pairs, R = 256 / h) owns pair J = t mod h: the 2 x 2 blocks (I, J) for
+// I = t / h + R q in registers, and the entries of V's columns u_J, v_J (the players of
+// pair J) in rows t / h + R q, V in LDS in player order. A round: every wave's lanes 0..h-1
+// read the diagonal blocks and form the pair rotations into the wave's own LDS table; each
+// thread rotates its blocks (two-sided) and its entries of V (one-sided, in place) and writes
+// its blocks to the other LDS buffer at the slots their rows and columns move to for the
+// next round (a fixed permutation: every player moves one position, position 1 wraps to
+// m-1, position 0 stays); one barrier; each thread reads its blocks back. After m - 1 rounds
+// the slots are back in their first order. A rotation is skipped when its pivot is not
+// above eps ||A||_F and eps sqrt(|a_pp a_qq|); the sweeps stop at the start of a sweep in
+// which no rotation would be made (the whole matrix is tested before the sweep, so no
+// confirming sweep is run). Returns the number of sweeps made.
+//
+// Input: A0 (player order, stride lda, LDS, p x p). Output: eigenvalues into d[0..p),
+// V (LDS, stride LV, PP rows) multiplied by all rotations. Abuf: 2 PP^2 doubles of LDS
+// (may overlap A0: A0 is read before the first write). Whole workgroup (256 threads).
+// FULL: m = PP (p >= PP - 1) and PP >= 32: the pair count and thread layout are compile-time
+// constants and the 256 threads own exactly the (PP/2)^2 blocks and the PP rows of V, so the
+// validity tests of the general case vanish.
+template <int PP, bool FULL>
+__device__ inline int jacobi_regs(int p, const double* A0, int lda, double* Abuf, double* V, int LV, double* d) {
+  constexpr int NBQ = PP * PP / 1024 > 0 ? PP * PP / 1024 : 1;  // blocks per thread
+  constexpr int NVQ = PP * PP / 512 > 0 ? PP * PP / 512 : 1;    // rows of V per thread
+  constexpr int H = PP / 2;
+  static_assert(!FULL || (H * H == WG * NBQ && PP * H == WG * NVQ), "FULL layout needs PP >= 32");
+  struct alignas(16) Rot { double c, s, t, app, aqq; int u, v; };
+  __shared__ Rot rtab[WG / 64][H];
+  __shared__ double fro_part[WG / 64];
+  const int m = FULL ? PP : p + (p & 1), h = FULL ? H : m / 2, R = WG / h;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const bool owner = FULL || tid < R * h;
+  const int J = owner ? tid % h : 0, I0 = owner ? tid / h : 0;
+  auto pos_of_slot = [&](int s) { return (s & 1) ? m - 1 - (s >> 1) : (s >> 1); };
+  auto slot_of_pos = [&](int q) { return q < h ? 2 * q : 2 * (m - 1 - q) + 1; };
+  // slot a row/column moves to for the next round
+  auto next_slot = [&](int s) {
+    const int q = pos_of_slot(s);
+    return slot_of_pos(q == 0 ? 0 : (q == 1 ? m - 1 : q - 1));
+  };
+  auto addr = [&](int i, int j) { return ((i >> 1) * h + (j >> 1)) * 4 + (i & 1) * 2 + (j & 1); };
+  double B[NBQ][4];
+  int bI[NBQ], dst[NBQ][4];
+  double fro2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < NBQ; ++q) {
+    const int I = I0 + R * q;
+    bI[q] = (FULL || (owner && I < h)) ? I : -1;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      B[q][e] = 0.0;
+      dst[q][e] = 0;
+    }
+    if (bI[q] >= 0) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int si = 2 * I + (e >> 1), sj = 2 * J + (e & 1);
+        const int xi = pos_of_slot(si), xj = pos_of_slot(sj);  // round 0: player x sits at position x
+        const double v = (xi < p && xj < p) ? A0[xi * lda + xj] : 0.0;
+        B[q][e] = v;
+        fro2 += v * v;
+        dst[q][e] = addr(next_slot(si), next_slot(sj));
+      }
+    }
+  }
+  int vr[NVQ];
+#pragma unroll
+  for (int q = 0; q < NVQ; ++q) {
+    const int r = I0 + R * q;
+    vr[q] = (FULL || (owner && r < m)) ? r : -1;
+  }
+  fro2 = wave_sum(fro2);
+  if (lane == 0) fro_part[w] = fro2;
+  __syncthreads();  // also: every read of A0 is done before Abuf (which may overlap it) is written
+  double fsum = 0.0;
+  for (int k = 0; k < WG / 64; ++k) fsum += fro_part[k];
+  const double athr2 = EPS * EPS * fsum;  // (eps ||A||_F)^2
+  int cur = 0;
+#pragma unroll
+  for (int q = 0; q < NBQ; ++q)
+    if (FULL || bI[q] >= 0)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) Abuf[addr(2 * bI[q] + (e >> 1), 2 * J + (e & 1))] = B[q][e];
+  __syncthreads();
+  // pair k = lane of every wave (k < h): its players u (position k), v (position m-1-k)
+  int pu = lane, pv = m - 1 - lane;
+  Rot* tab = rtab[w];
+  int sweep = 0;
+  for (; sweep < 40; ++sweep) {
+    bool stop = false;
+    for (int round = 0; round < m - 1; ++round) {
+      const double* Ac = Abuf + cur * PP * PP;
+      double* An = Abuf + (cur ^ 1) * PP * PP;
+      if (lane < h) {
+        const double* blk = Ac + (lane * h + lane) * 4;
+        const double app = blk[0], apq = blk[1], aqq = blk[3];
+        const double apq2 = apq * apq;
+        double c = 1.0, s = 0.0, t = 0.0;
+        if (apq2 > athr2 && apq2 > EPS * EPS * fabs(app * aqq) && fabs(apq) > 1e-300) {
+          // t = tan of the angle that zeroes a_pq: sgn(tau) / (|tau| + sqrt(1 + tau^2)),
+          // tau = (a_qq - a_pp) / (2 a_pq); |tau| <= 1/eps here, so 1 + tau^2 cannot overflow
+          const double tau = (aqq - app) * rcp_nr(2.0 * apq);
+          const double q1 = 1.0 + tau * tau;
+          const double root = q1 * rsq_nr(q1);
+          const double ta = rcp_nr(fabs(tau) + root);
+          t = tau >= 0.0 ? ta : -ta;
+          c = rsq_nr(1.0 + t * t);
+          s = t * c;
+        }
+        Rot rr;
+        rr.c = c; rr.s = s; rr.t = t; rr.app = app; rr.aqq = aqq; rr.u = pu; rr.v = pv;
+        tab[lane] = rr;
+      }
+      wave_sync();
+      if (round == 0) {
+        // would this sweep rotate anything? (the whole matrix against the skip rule)
+        int big = 0;
+        const double dJ0 = tab[J].app, dJ1 = tab[J].aqq;
+#pragma unroll
+        for (int q = 0; q < NBQ; ++q) {
+          if (!FULL && bI[q] < 0) continue;
+          const double dI0 = tab[bI[q]].app, dI1 = tab[bI[q]].aqq;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int a = e >> 1, c = e & 1;
+            if (bI[q] == J && a == c) continue;
+            const double x2 = B[q][e] * B[q][e];
+            const double di = a ? dI1 : dI0, dj = c ? dJ1 : dJ0;
+            if (x2 > athr2 && x2 > EPS * EPS * fabs(di * dj) && fabs(B[q][e]) > 1e-300) big = 1;
+          }
+        }
+        if (!__syncthreads_or(big)) {
+          stop = true;
+          break;
+        }
+      }
+      if (owner) {
+        const Rot rJ = tab[J];
+        // blocks: B <- R_I^T B R_J; the diagonal block gets the rotated diagonal and an
+        // exact zero off the diagonal
+#pragma unroll
+        for (int q = 0; q < NBQ; ++q) {
+          if (!FULL && bI[q] < 0) continue;
+          const double cI = tab[bI[q]].c, sI = tab[bI[q]].s;
+          double* x = B[q];
+          const double r0 = cI * x[0] - sI * x[2], r1 = cI * x[1] - sI * x[3];
+          const double r2 = sI * x[0] + cI * x[2], r3 = sI * x[1] + cI * x[3];
+          double y0 = rJ.c * r0 - rJ.s * r1, y1 = rJ.s * r0 + rJ.c * r1;
+          double y2 = rJ.c * r2 - rJ.s * r3, y3 = rJ.s * r2 + rJ.c * r3;
+          const bool dg = bI[q] == J && rJ.s != 0.0;
+          const double off = x[1];
+          x[0] = dg ? x[0] - rJ.t * off : y0;
+          x[3] = dg ? x[3] + rJ.t * off : y3;
+          x[1] = dg ? 0.0 : y1;
+          x[2] = dg ? 0.0 : y2;
+        }
+        // V <- V R_J on the columns of pair J's players, in place
+        if (rJ.s != 0.0) {
+          double xu[NVQ], xv[NVQ];
+#pragma unroll
+          for (int q = 0; q < NVQ; ++q) {
+            xu[q] = 0.0;
+            xv[q] = 0.0;
+            if (FULL || vr[q] >= 0) {
+              xu[q] = V[vr[q] * LV + rJ.u];
+              xv[q] = V[vr[q] * LV + rJ.v];
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < NVQ; ++q)
+            if (FULL || vr[q] >= 0) {
+              V[vr[q] * LV + rJ.u] = rJ.c * xu[q] - rJ.s * xv[q];
+              V[vr[q] * LV + rJ.v] = rJ.s * xu[q] + rJ.c * xv[q];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NBQ; ++q)
+          if (FULL || bI[q] >= 0)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) An[dst[q][e]] = B[q][e];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < NBQ; ++q)
+        if (FULL || bI[q] >= 0) {
+          const double* blk = An + (bI[q] * h + J) * 4;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) B[q][e] = blk[e];
+        }
+      cur ^= 1;
+      // next round: every player except player 0 moves on (m - 1 wraps to 1)
+      if (lane != 0) pu = pu == m - 1 ? 1 : pu + 1;
+      pv = pv == m - 1 ? 1 : pv + 1;
+    }
+    if (stop) break;
+  }
+  // eigenvalue of player x: the diagonal entry at its slot (the slots are in their first order)
+  const double* Ac = Abuf + cur * PP * PP;
+  for (int x = tid; x < p; x += WG) {
+    const int sx = slot_of_pos(x);
+    d[x] = Ac[addr(sx, sx)];
+  }
+  __syncthreads();
+  return sweep;
+}
+
 // ---------------------------------------------------------------- line search (wave 0)
 
 struct Terms {
@@ -295,43 +525,42 @@ __device__ inline double get_mu(Terms& T, int p, int preal, int* evals) {
 // (small[S_VEC ...]); returns the Jacobi sweep count. Warm start (warm = true): the previous
 // V, made orthonormal again by one Newton-Schulz step V <- V (3 I - V^T V) / 2, turns S
 // into a nearly diagonal V^T S V when the directions change little from step to step.
-// lds: 3 PP (PP + 1) doubles. The products use stride PP, the rotations stride PP + 1 (an
-// odd stride in doubles keeps the column sweeps of the rotations free of LDS bank
-// conflicts). Whole workgroup.
+// lds: 3 PP (PP + 1) doubles: V with the odd stride PP + 1 (the in-place column updates of
+// the rotations are then free of bank conflicts) and the two block buffers of jacobi_regs,
+// which also hold the temporaries of the products (stride PP). Whole workgroup. The
+// arguments cs, uv, nrot, anyr are unused (kept for the callers' shared-memory layout).
 template <int PP>
-__device__ inline int eig_dev(double* small, int p, bool warm, double* lds, double* cs, int* uv, int* nrot,
-                              int* anyr) {
-  constexpr int LP = PP + 1;
-  double* A = lds;
-  double* V = A + PP * LP;
-  double* T = V + PP * LP;
+__device__ inline int eig_dev(double* small, int p, bool warm, double* lds, double* /*cs*/, int* /*uv*/,
+                              int* /*nrot*/, int* /*anyr*/) {
+  constexpr int LV = PP + 1;
+  double* Vv = lds;             // PP x LV
+  double* Ab = lds + PP * LV;   // 2 PP^2: jacobi_regs buffers
+  double* T0 = Ab;              // temporaries, stride PP
+  double* V1 = Ab + PP * PP;
   const double* S = small + S_S * PP * PP;
   double* Vg = small + S_V * PP * PP;
   if (warm) {
-    wg_mm<PP>(Vg, true, Vg, false, T);  // T = V^T V
+    wg_mm<PP>(Vg, true, Vg, false, T0);  // T0 = V^T V
     __syncthreads();
-    for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) T[e] = 0.5 * (((e / PP) == (e % PP) ? 3.0 : 0.0) - T[e]);
+    for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) T0[e] = 0.5 * (((e / PP) == (e % PP) ? 3.0 : 0.0) - T0[e]);
     __syncthreads();
-    wg_mm<PP>(Vg, false, T, false, V);  // V = V (3I - V^T V) / 2
+    wg_mm<PP>(Vg, false, T0, false, V1);  // V1 = V (3I - V^T V) / 2
   } else {
-    for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) V[e] = (e / PP) == (e % PP) ? 1.0 : 0.0;
+    for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) V1[e] = (e / PP) == (e % PP) ? 1.0 : 0.0;
   }
   __syncthreads();
-  wg_mm<PP>(S, false, V, false, T);  // T = S V
+  wg_mm<PP>(S, false, V1, false, Vv);  // Vv (as a stride-PP temporary) = S V
   __syncthreads();
-  wg_mm<PP>(V, true, T, false, A);  // A = V^T S V
+  wg_mm<PP>(V1, true, Vv, false, T0);  // T0 = V^T S V
   __syncthreads();
-  // re-lay A (into T) and V (into A) with stride LP for the rotations
-  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) T[(e / PP) * LP + e % PP] = A[e];
+  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) Vv[(e / PP) * LV + e % PP] = V1[e];
   __syncthreads();
-  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) A[(e / PP) * LP + e % PP] = V[e];
-  __syncthreads();
-  double* Ap = T;
-  double* Vp = A;
-  const int sweeps = jacobi(p, LP, Ap, Vp, cs, uv, nrot, anyr);
   double* b = small + S_VEC * PP * PP;
-  for (int i = threadIdx.x; i < PP; i += blockDim.x) b[i] = i < p ? fmax(Ap[i * LP + i], 0.0) : 0.0;
-  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) Vg[e] = Vp[(e / PP) * LP + e % PP];
+  // the compile-time layout needs every thread to own blocks: PP >= 32 (H^2 = 256 NBQ)
+  const int sweeps = (PP >= 32 && p >= PP - 1) ? jacobi_regs<PP, PP >= 32>(p, T0, PP, Ab, Vv, LV, b)
+                                               : jacobi_regs<PP, false>(p, T0, PP, Ab, Vv, LV, b);
+  for (int i = threadIdx.x; i < PP; i += blockDim.x) b[i] = i < p ? fmax(b[i], 0.0) : 0.0;
+  for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) Vg[e] = Vv[(e / PP) * LV + e % PP];
   __syncthreads();
   return sweeps;
 }
