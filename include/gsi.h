@@ -337,6 +337,17 @@ gsi_status gsi_batched_timeline(gsi_batch_handle h, double* begin_us, double* sw
  * paper_2306_10379_amd/tuning.py measures and picks per batch shape. Syncs. */
 gsi_status gsi_batched_set_tuning(gsi_batch_handle h, int32_t tiles_per_member, int32_t recruit_step,
                                   int32_t check_every);
+/* Per-problem tile shapes of the batched passes, the knobs the tuner
+ * (paper_2306_10379_amd/tuning.py) picks per (size band, block width, precision): shapes is a
+ * host array of count int32 codes with 4-bit fields, bits 0-3 u (row tiles whose loads are
+ * issued together in the gradient, direction and product passes: 1, 2 or 4), bits 4-7 uu
+ * (the retraction pass: 1 or 2), bits 8-11 ug (the Gram passes: 1, 2 or 4), bits 12-15 ch
+ * (nonzeros whose indices and gathers are issued together in the SpMM: 4, 8, or 15 for 16);
+ * a field 0 keeps the built default (all zero: the defaults everywhere). The shape changes
+ * only the schedule of loads, not the arithmetic or its order: float64 results of a problem
+ * solved by one workgroup repeat bit for bit under any shape. GSI_EINVAL for other codes
+ * (nothing is changed then). Applies to the following solves. Syncs. */
+gsi_status gsi_batched_set_shapes(gsi_batch_handle h, const int32_t* shapes);
 /* Longest wait of a workgroup at a team barrier, or for a team entry it has reserved, in the
  * following solves (default 30 s; 0 < seconds <= 3600, else GSI_EINVAL). Every wait of the
  * persistent launch is bounded by it, so a team whose member never arrives ends the launch

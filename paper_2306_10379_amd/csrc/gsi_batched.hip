@@ -25,6 +25,8 @@
 #include <string>
 #include <vector>
 
+#include <type_traits>
+
 #include "../../include/gsi.h"
 #include "gsi_kernels.h"
 #include "gsi_small_dev.h"
@@ -52,7 +54,8 @@ struct BatchProblem {
   double* ritz;             // p outputs (Ritz values of the operator solved)
   int32_t tmax, team;       // largest team allowed this solve / team size reached
   int32_t tcap, tiles;      // member storage allocated; row tiles
-  int32_t iters, iters_low, status, restarts, null_steps, pad;
+  int32_t iters, iters_low, status, restarts, null_steps;
+  int32_t shape;            // tile shape of the passes (see Shape); 0 = the defaults of Unroll
   double rho;
   int64_t t_begin, t_switch, t_end;  // device wall clock
   int64_t ticks[GSI_NPASS];          // wall-clock ticks per pass (first member)
@@ -123,15 +126,53 @@ __device__ __forceinline__ void pass_barrier() {
   __syncthreads();
 }
 
-// Tiles whose loads are issued together in the streaming passes, sized so that no pass
-// spills registers: U for the passes reading three blocks, UU for the retraction (four
-// blocks), UG for the Grams.
+// Tiles whose loads are issued together in the streaming passes (the defaults, sized so that
+// no pass spills registers): U for the passes reading three blocks, UU for the retraction
+// (four blocks), UG for the Grams; CH nonzeros gathered per batch in the SpMM.
 template <typename T, int PP>
 struct Unroll {
   static constexpr int U = sizeof(T) * PP >= 256 ? 2 : 4;
   static constexpr int UU = sizeof(T) * PP >= 256 ? 1 : 2;
   static constexpr int UG = PP == 16 ? 4 : (sizeof(T) == 8 ? 1 : 2);
+  static constexpr int CH = 8;
 };
+
+// Per-problem tile shape (BatchProblem::shape, set by gsi_batched_set_shapes from the tuner's
+// table): 4-bit fields u (bits 0-3), uu (4-7), ug (8-11), ch (12-15), each 0 for the default
+// of Unroll or one of the built values: u, ug in {1, 2, 4}, uu in {1, 2}, ch in {4, 8, 16}
+// (16 coded as 15).
+struct Shape {
+  int u, uu, ug, ch;
+  template <typename T, int PP>
+  __device__ static Shape of(int32_t code) {
+    Shape s;
+    const int cu = code & 15, cuu = (code >> 4) & 15, cug = (code >> 8) & 15, cch = (code >> 12) & 15;
+    s.u = cu ? cu : Unroll<T, PP>::U;
+    s.uu = cuu ? cuu : Unroll<T, PP>::UU;
+    s.ug = cug ? cug : Unroll<T, PP>::UG;
+    s.ch = cch == 15 ? 16 : (cch ? cch : Unroll<T, PP>::CH);
+    return s;
+  }
+};
+
+// f(integral_constant<int, v>) for v in {1, 2, 4} (2 for anything else) / {4, 8, 16} (8).
+template <typename F>
+__device__ __forceinline__ void with_124(int v, F&& f) {
+  if (v == 1) f(std::integral_constant<int, 1>());
+  else if (v == 4) f(std::integral_constant<int, 4>());
+  else f(std::integral_constant<int, 2>());
+}
+template <typename F>
+__device__ __forceinline__ void with_12(int v, F&& f) {
+  if (v == 1) f(std::integral_constant<int, 1>());
+  else f(std::integral_constant<int, 2>());
+}
+template <typename F>
+__device__ __forceinline__ void with_48_16(int v, F&& f) {
+  if (v == 4) f(std::integral_constant<int, 4>());
+  else if (v == 16) f(std::integral_constant<int, 16>());
+  else f(std::integral_constant<int, 8>());
+}
 
 // ---------------------------------------------------------------- streaming passes (one workgroup)
 
@@ -141,10 +182,9 @@ __device__ void b_load_matrix(T* __restrict__ s, const double* __restrict__ M) {
 }
 
 // G = X C - Y over tiles [ta, tb); sums of G^2 and G_old G, max absolute row sum.
-template <typename T, int PP>
+template <typename T, int PP, int U>
 __device__ __noinline__ void b_grad(int64_t n, int64_t ta, int64_t tb, const T* X, const T* Y, const T* Gold, T* G,
                                     const T* sC, bool have_old, double* sums) {
-  constexpr int U = Unroll<T, PP>::U;
   const int w = threadIdx.x >> 6;
   sC = to_lds(sC);
   double gg = 0.0, gdot = 0.0, ginf = 0.0;
@@ -189,10 +229,9 @@ __device__ __noinline__ void b_grad(int64_t n, int64_t ta, int64_t tb, const T* 
 }
 
 // P = G + beta P_old - X KD over tiles [ta, tb); sum of G P.
-template <typename T, int PP>
+template <typename T, int PP, int U>
 __device__ __noinline__ void b_dir(int64_t n, int64_t ta, int64_t tb, const T* X, const T* G, const T* Pold, T* P,
                                    const T* sK, T beta, bool use_old, double* sums) {
-  constexpr int U = Unroll<T, PP>::U;
   const int w = threadIdx.x >> 6;
   sK = to_lds(sK);
   double gp = 0.0;
@@ -226,10 +265,9 @@ __device__ __noinline__ void b_dir(int64_t n, int64_t ta, int64_t tb, const T* X
 }
 
 // X <- (X - mu P) M, Y <- (Y - mu Z) M over tiles [ta, tb) (Y skipped when upd_y is false).
-template <typename T, int PP>
+template <typename T, int PP, int U>
 __device__ __noinline__ void b_update(int64_t n, int64_t ta, int64_t tb, T* X, T* Y, const T* P, const T* Z,
                                       const T* sM, T mu, bool upd_y) {
-  constexpr int U = Unroll<T, PP>::UU;
   const int w = threadIdx.x >> 6;
   sM = to_lds(sM);
   for (int64_t t = ta; t < tb; t += U) {
@@ -275,9 +313,8 @@ __device__ __noinline__ void b_update(int64_t n, int64_t ta, int64_t tb, T* X, T
 }
 
 // IN <- IN M in place over tiles [ta, tb).
-template <typename T, int PP>
+template <typename T, int PP, int U>
 __device__ __noinline__ void b_product(int64_t n, int64_t ta, int64_t tb, T* IN, const T* sM) {
-  constexpr int U = Unroll<T, PP>::U;
   const int w = threadIdx.x >> 6;
   sM = to_lds(sM);
   for (int64_t t = ta; t < tb; t += U) {
@@ -323,10 +360,10 @@ __device__ __forceinline__ void load_run(const T* __restrict__ p, bool ok, T (&d
 
 // Z = A W over rows [r0, r1): LPR lanes per row, 4 columns per lane, nonzeros of a row
 // gathered in batches of CH so that the index loads and the gathers of a batch overlap.
-template <typename T, int PP>
+template <typename T, int PP, int CH>
 __device__ __noinline__ void b_spmm(int64_t r0, int64_t r1, const int32_t* rowptr, const int32_t* colind,
                                     const T* vals, const T* W, T* Z) {
-  constexpr int EPL = 4, LPR = PP / EPL, RPB = WG / LPR, CH = 8;
+  constexpr int EPL = 4, LPR = PP / EPL, RPB = WG / LPR;
   const int sub = threadIdx.x / LPR, lane = threadIdx.x % LPR;
   for (int64_t row = r0 + sub; row < r1; row += RPB) {
     T acc[EPL] = {T(0), T(0), T(0), T(0)};
@@ -362,11 +399,10 @@ __device__ __noinline__ void b_spmm(int64_t r0, int64_t r1, const int32_t* rowpt
 // 2 PP^2 doubles). Output (V i + ib, V j + jb) comes from accumulator [ib][jb], D row i,
 // column j. Blocks span whole tiles with zero padding rows, so only the tile index is
 // checked.
-template <typename T, int PP>
+template <typename T, int PP, int U>
 __device__ __noinline__ void b_gram(int64_t ta, int64_t tb, const T* A, const T* B1, const T* B2, double* out1,
                                     double* out2, double* red) {
   constexpr int V = PP / 16;
-  constexpr int U = Unroll<T, PP>::UG;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, c = l & 15;
   const bool two = B2 != nullptr;
   red = to_lds(red);
@@ -608,12 +644,15 @@ __device__ bool exchange(Team& tm, BatchCtl* ctl, BatchProblem& pr, int32_t* bar
 template <typename T, int PP>
 __device__ void gram_part(const Team& tm, BatchProblem& pr, const T* A, const T* B1, const T* B2, double* d1,
                           double* d2, double* dl) {
-  if (tm.t == 1) {
-    b_gram<T, PP>(tm.ta, tm.tb, A, B1, B2, d1, d2, dl);
-  } else {
-    double* slot = xslot<PP>(pr, tm.xc & 1, tm.rank);
-    b_gram<T, PP>(tm.ta, tm.tb, A, B1, B2, slot, B2 ? slot + PP * PP : nullptr, dl);
-  }
+  const int ug = Shape::of<T, PP>(pr.shape).ug;
+  with_124(ug, [&](auto U) {
+    if (tm.t == 1) {
+      b_gram<T, PP, decltype(U)::value>(tm.ta, tm.tb, A, B1, B2, d1, d2, dl);
+    } else {
+      double* slot = xslot<PP>(pr, tm.xc & 1, tm.rank);
+      b_gram<T, PP, decltype(U)::value>(tm.ta, tm.tb, A, B1, B2, slot, B2 ? slot + PP * PP : nullptr, dl);
+    }
+  });
 }
 
 // Gram plus scalars over the team (a plain barrier for a lone workgroup).
@@ -665,6 +704,7 @@ __device__ __noinline__ int solve_phase(BatchProblem& pr, BatchCtl* ctl, int idx
   double* G3 = small + S_T2 * PP * PP;
   const double sqrt_p = sqrt((double)p);
   const bool carry = rs.carry && rs.k > 0;
+  const Shape shp = Shape::of<T, PP>(pr.shape);
   int k, k_best, restarts = 0, nulls = 0, stop = 0;
   double gg_old, rho = 0.0, rho_best;
   bool v_valid;
@@ -687,7 +727,7 @@ __device__ __noinline__ int solve_phase(BatchProblem& pr, BatchCtl* ctl, int idx
       ok = b_chol_inv<PP>(G2, M, p, dl, &sh.bad);
       b_load_matrix<T, PP>(sMat, M);
       __syncthreads();
-      if (ok) b_product<T, PP>(n, tm.ta, tm.tb, X, sMat);
+      if (ok) with_124(shp.u, [&](auto U) { b_product<T, PP, decltype(U)::value>(n, tm.ta, tm.tb, X, sMat); });
       pass_barrier();
     }
     if (stop == 0 && tm.t > 1 && !team_sync(tm, ctl, bar, sh)) stop = 5;
@@ -700,7 +740,7 @@ __device__ __noinline__ int solve_phase(BatchProblem& pr, BatchCtl* ctl, int idx
       return stop;
     }
     // Y = A X, C = sym(X^T Y); with a carried direction also W = X^T P_old
-    b_spmm<T, PP>(tm.r0, tm.r1, pr.rowptr, pr.colind, vals, X, Y);
+    with_48_16(shp.ch, [&](auto C) { b_spmm<T, PP, decltype(C)::value>(tm.r0, tm.r1, pr.rowptr, pr.colind, vals, X, Y); });
     pass_barrier();
     if (!team_gram<T, PP>(tm, ctl, pr, bar, sh, X, Y, carry ? Pb[(rs.k - 1) & 1] : nullptr, G2, carry ? W : nullptr,
                           dl, v, 0, 0)) {
@@ -783,7 +823,7 @@ __device__ __noinline__ int solve_phase(BatchProblem& pr, BatchCtl* ctl, int idx
     b_load_matrix<T, PP>(sMat, C);
     __syncthreads();
     double sums[3];
-    b_grad<T, PP>(n, tm.ta, tm.tb, X, Y, Gb[par ^ 1], Gb[par], sMat, k > 0, sums);
+    with_124(shp.u, [&](auto U) { b_grad<T, PP, decltype(U)::value>(n, tm.ta, tm.tb, X, Y, Gb[par ^ 1], Gb[par], sMat, k > 0, sums); });
     double gg = sums[0], gdot = sums[1], ginf = sums[2];
     b_reduce3(gg, gdot, ginf, sh.red);
     clk.mark(GSI_PASS_GRAD);
@@ -810,7 +850,7 @@ __device__ __noinline__ int solve_phase(BatchProblem& pr, BatchCtl* ctl, int idx
     b_load_matrix<T, PP>(sMat, KD);
     __syncthreads();
     clk.mark(GSI_PASS_SMALL);
-    b_dir<T, PP>(n, tm.ta, tm.tb, X, Gb[par], Pb[par ^ 1], Pb[par], sMat, (T)beta, !restart, sums);
+    with_124(shp.u, [&](auto U) { b_dir<T, PP, decltype(U)::value>(n, tm.ta, tm.tb, X, Gb[par], Pb[par ^ 1], Pb[par], sMat, (T)beta, !restart, sums); });
     double gp = sums[0], dz1 = 0.0, dz2 = 0.0;
     b_reduce3(gp, dz1, dz2, sh.red);
     clk.mark(GSI_PASS_DIR);
@@ -835,7 +875,7 @@ __device__ __noinline__ int solve_phase(BatchProblem& pr, BatchCtl* ctl, int idx
     clk.mark(GSI_PASS_EIG);
     // SpMM of this member's rows (every row of P is final after the exchange above) and
     // the line-search Grams
-    b_spmm<T, PP>(tm.r0, tm.r1, pr.rowptr, pr.colind, vals, Pb[par], Z);
+    with_48_16(shp.ch, [&](auto C) { b_spmm<T, PP, decltype(C)::value>(tm.r0, tm.r1, pr.rowptr, pr.colind, vals, Pb[par], Z); });
     pass_barrier();
     clk.mark(GSI_PASS_SPMM);
     if (!team_gram<T, PP>(tm, ctl, pr, bar, sh, Pb[par], Z, Y, PZ, PY, dl, v, 0, 0)) { stop = 5; break; }
@@ -855,12 +895,12 @@ __device__ __noinline__ int solve_phase(BatchProblem& pr, BatchCtl* ctl, int idx
     // retraction
     b_load_matrix<T, PP>(sMat, M);
     __syncthreads();
-    b_update<T, PP>(n, tm.ta, tm.tb, X, Y, Pb[par], Z, sMat, (T)mu, !refresh);
+    with_12(shp.uu, [&](auto U) { b_update<T, PP, decltype(U)::value>(n, tm.ta, tm.tb, X, Y, Pb[par], Z, sMat, (T)mu, !refresh); });
     pass_barrier();
     clk.mark(GSI_PASS_UPDATE);
     if (refresh) {
       if (tm.t > 1 && !team_sync(tm, ctl, bar, sh)) { stop = 5; break; }
-      b_spmm<T, PP>(tm.r0, tm.r1, pr.rowptr, pr.colind, vals, X, Y);
+      with_48_16(shp.ch, [&](auto C) { b_spmm<T, PP, decltype(C)::value>(tm.r0, tm.r1, pr.rowptr, pr.colind, vals, X, Y); });
       pass_barrier();
       if (!team_gram<T, PP>(tm, ctl, pr, bar, sh, X, Y, nullptr, G3, nullptr, dl, v, 0, 0)) { stop = 5; break; }
       for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) C[e] = 0.5 * (G3[e] + G3[(e % PP) * PP + e / PP]);
@@ -1365,6 +1405,33 @@ gsi_status gsi_batched_set_tuning(gsi_batch_handle b, int32_t tiles_per_member, 
   ctl.esc_every = check_every;
   if (e == hipSuccess) e = hipMemcpy(b->dctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice);
   if (e != hipSuccess) { b->err = std::string("tuning: ") + hipGetErrorString(e); return GSI_EDEVICE; }
+  return GSI_OK;
+}
+
+gsi_status gsi_batched_set_shapes(gsi_batch_handle b, const int32_t* shapes) {
+  if (!b) return GSI_EINVAL;
+  if (!shapes) { b->err = "shapes: null array"; return GSI_EINVAL; }
+  for (int i = 0; i < b->count; ++i) {
+    const int32_t c = shapes[i];
+    const int u = c & 15, uu = (c >> 4) & 15, ug = (c >> 8) & 15, ch = (c >> 12) & 15;
+    const bool ok = (c >> 16) == 0 && (u == 0 || u == 1 || u == 2 || u == 4) && (uu == 0 || uu == 1 || uu == 2) &&
+                    (ug == 0 || ug == 1 || ug == 2 || ug == 4) && (ch == 0 || ch == 4 || ch == 8);
+    // ch is a 4-bit field: 16 nonzeros per batch are coded as 0xf
+    const bool ok16 = (c >> 16) == 0 && ch == 15;
+    if (!ok && !(ok16 && (u == 0 || u == 1 || u == 2 || u == 4) && (uu == 0 || uu == 1 || uu == 2) &&
+                 (ug == 0 || ug == 1 || ug == 2 || ug == 4))) {
+      b->err = "shapes: problem " + std::to_string(i) + " has an unknown shape code";
+      return GSI_EINVAL;
+    }
+  }
+  std::vector<BatchProblem> cur(b->count);
+  hipError_t e = hipMemcpy(cur.data(), b->dprobs, sizeof(BatchProblem) * b->count, hipMemcpyDeviceToHost);
+  for (int i = 0; i < b->count; ++i) {
+    cur[i].shape = shapes[i];
+    b->hprobs[i].shape = shapes[i];
+  }
+  if (e == hipSuccess) e = hipMemcpy(b->dprobs, cur.data(), sizeof(BatchProblem) * b->count, hipMemcpyHostToDevice);
+  if (e != hipSuccess) { b->err = std::string("shapes: ") + hipGetErrorString(e); return GSI_EDEVICE; }
   return GSI_OK;
 }
 

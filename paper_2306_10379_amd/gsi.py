@@ -24,7 +24,7 @@ EXPORTS = [
     "gsi_set_x0", "gsi_set_values", "gsi_spmm", "gsi_spmm_lowp", "gsi_history", "gsi_counters", "gsi_pass_times", "gsi_destroy",
     "gsi_status_str", "gsi_last_error", "gsi_create_batched", "gsi_solve_batched", "gsi_batched_results",
     "gsi_batched_get_x", "gsi_batched_set_tuning", "gsi_batched_set_wait_limit", "gsi_batched_timeline", "gsi_batched_pass_times", "gsi_batched_last_error", "gsi_destroy_batched",
-    "gsi_orthonormalize",
+    "gsi_orthonormalize", "gsi_batched_set_shapes",
 ]
 PASSES = ["grad", "dir", "spmm", "update", "reduce", "small", "linesearch", "refresh", "eig", "gram"]
 
@@ -136,6 +136,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gsi_batched_get_x.restype = ctypes.c_int
     L.gsi_batched_set_tuning.argtypes = [vp, i32, i32, i32]
     L.gsi_batched_set_tuning.restype = ctypes.c_int
+    L.gsi_batched_set_shapes.argtypes = [vp, P(i32)]
+    L.gsi_batched_set_shapes.restype = ctypes.c_int
     L.gsi_batched_set_wait_limit.argtypes = [vp, dbl]
     L.gsi_batched_set_wait_limit.restype = ctypes.c_int
     L.gsi_batched_timeline.argtypes = [vp, P(dbl), P(dbl), P(dbl), P(i32), P(i32)]
@@ -575,9 +577,17 @@ class BatchedSolver:
     def set_tuning(self, tiles_per_member: int, recruit_step: int, check_every: int):
         _bcheck(self.h, load().gsi_batched_set_tuning(self.h, int(tiles_per_member), int(recruit_step),
                                                       int(check_every)))
+        self.tuning_policy = (int(tiles_per_member), int(recruit_step), int(check_every))
 
     def set_wait_limit(self, seconds: float):
         _bcheck(self.h, load().gsi_batched_set_wait_limit(self.h, float(seconds)))
+
+    def set_shapes(self, codes):
+        """Per-problem tile-shape codes (gsi_batched_set_shapes; see tuning.shape_code)."""
+        if len(codes) != len(self.ps):
+            raise ValueError(f"need {len(self.ps)} shape codes, got {len(codes)}")
+        arr = (ctypes.c_int32 * len(self.ps))(*[int(c) for c in codes])
+        _bcheck(self.h, load().gsi_batched_set_shapes(self.h, arr))
 
     def pass_times(self):
         return gsi_batched_pass_times(self.h, len(self.ps))

@@ -314,6 +314,37 @@ def test_batched_repeat_solves_from_x0():
             assert np.array_equal(x1[i], b.get_x(i).cpu().numpy())
 
 
+def test_batched_tile_shapes_change_no_result():
+    """Every built tile shape of the batched passes (tiles whose loads are issued together,
+    nonzeros gathered together) reproduces the float64 results of the defaults bit for bit
+    (the schedule of loads changes, not the arithmetic or its order); shapes may differ
+    between problems; unknown codes are refused."""
+    gsi = _gsi()
+    from paper_2306_10379_amd import tuning
+    mats, X0s, ps = _schrodinger_batch(8, 13, pmax=30)
+    with gsi.BatchedSolver(mats, X0s, ps, which=-1, precision="fp64", tol=1e-10, max_iter=20000) as b:
+        b.set_tuning(1 << 20, 1, 1 << 20)  # no teams: every problem with one workgroup
+        _, it0, st0 = b.solve()
+        r0 = [b.results(i)[0] for i in range(len(ps))]
+        x0 = [b.get_x(i).cpu().numpy() for i in range(len(ps))]
+        shapes = [dict(u=1, uu=1, ug=1, ch=4), dict(u=4, uu=2, ug=4, ch=16), dict(u=2, uu=1, ug=2, ch=8)]
+        for k in range(len(shapes) + 1):
+            if k < len(shapes):
+                codes = [tuning.shape_code(**shapes[k])] * len(ps)
+            else:  # a different shape per problem
+                codes = [tuning.shape_code(**shapes[i % len(shapes)]) for i in range(len(ps))]
+            print(f"shapes {codes}", flush=True)
+            b.set_shapes(codes)
+            _, it, st = b.solve()
+            assert np.array_equal(it, it0) and np.array_equal(st, st0)
+            for i in range(len(ps)):
+                assert np.array_equal(r0[i], b.results(i)[0])
+                assert np.array_equal(x0[i], b.get_x(i).cpu().numpy())
+        for bad in (3, 3 << 4, 8 << 8, 5 << 12, 1 << 16):
+            with pytest.raises(gsi.GsiError):
+                b.set_shapes([bad] * len(ps))
+
+
 def nA_est(A):
     return O.norm_inf(A.to_scipy())
 
@@ -344,6 +375,30 @@ def test_batched_full_schrodinger_batch():
             assert np.linalg.norm(X.T @ X - np.eye(p)) <= 1e-12 * p
             assert np.linalg.norm(R) / (np.sqrt(p) * nA) <= 1.05 * tol + 1e-14, i
             assert np.allclose(np.sort(-ritz), np.linalg.eigvalsh(0.5 * (Cx + Cx.T)), rtol=1e-12, atol=1e-12 * nA)
+        # the Ritz values are the p smallest eigenvalues: every problem a team solved plus a
+        # stratified sample of the rest (>= 64 in all) against scipy's shift-invert Lanczos,
+        # within the quadratic residual bound ||R||_F^2 / (lambda_{p+1} - theta_p)
+        teamed = [i for i in range(len(mats)) if team[i] > 1]
+        rest = [i for i in range(len(mats)) if team[i] <= 1]
+        sample = sorted(set(teamed) | set(rest[::max(1, len(rest) // max(1, 64 - len(teamed)))]))
+        print(f"eigsh check: {len(sample)} problems ({len(teamed)} solved by teams)", flush=True)
+        assert len(sample) >= 64
+        for i in sample:
+            A, p = mats[i], ps[i]
+            S = A.to_scipy()
+            X = b.get_x(i).cpu().numpy()
+            ritz, rho, _ = b.results(i)
+            theta = np.sort(-ritz)
+            d = S.diagonal()
+            lower = float(np.min(d - (abs(S).sum(axis=1).A1 - np.abs(d)))) - 1.0  # below the spectrum
+            lam = np.sort(scipy.sparse.linalg.eigsh(S.tocsc(), k=p + 1, sigma=lower, which="LM",
+                                                    return_eigenvectors=False))
+            AX = S @ X
+            Cx = X.T @ AX
+            nR = np.linalg.norm(AX - X @ (0.5 * (Cx + Cx.T)))
+            bound = nR ** 2 / (lam[p] - theta[-1]) + 1e-12 * O.norm_inf(S)
+            assert lam[p] - theta[-1] > 0.0, i
+            assert np.max(np.abs(theta - lam[:p])) <= bound, (i, np.max(np.abs(theta - lam[:p])), bound)
         cost = np.array([A.n * p for A, p in zip(mats, ps)]) * iters
         teamed = [i for i in np.argsort(cost) if team[i] > 1]
         for i in list(np.argsort(cost)[:2]) + teamed[:1]:
@@ -722,13 +777,16 @@ def test_degenerate_inputs():
 
 def test_c2_full_size_properties():
     """The benchmark workload at its full size and in the benchmark's launch configuration
-    (3D Laplacian 128^3, n = 2,097,152, p = 64, float64, tol 1e-8, graph launches polled
-    every 50 iterations, X0 seed 0). Checked on the CPU from what the library returns:
-    the Ritz values against the 64 largest eigenvalues of the closed-form Dirichlet spectrum,
-    X^T X = I, the float64 residual A X - X (X^T A X) recomputed with scipy, the per-column
-    residuals the library reports, and sampled rows of the full-size SpMM."""
+    (3D Laplacian 128^3, n = 2,097,152, p = 64, float64, graph launches polled every 50
+    iterations, X0 seed 0), solved to rho <= 1e-9 (one decade below the benchmark's 1e-8, so
+    that the quadratic Ritz error bound ||G||^2 / delta_eff, delta_eff = lambda_64 - lambda_67
+    = 5.96e-4, sits below the stated 1e-10 relative tolerance). Checked on the CPU from what
+    the library returns: the Ritz values against the 64 largest eigenvalues of the closed-form
+    Dirichlet spectrum to 1e-10 relative, X^T X = I, the float64 residual A X - X (X^T A X)
+    recomputed with scipy, the per-column residuals the library reports, and sampled rows of
+    the full-size SpMM."""
     gsi = _gsi()
-    N, p, tol = 128, 64, 1e-8
+    N, p, tol = 128, 64, 1e-9
     print("c2 full size: building 128^3", flush=True)
     A = I.laplacian_3d(N)
     X0 = I.start_block(A.n, p, 0)
@@ -761,6 +819,9 @@ def test_c2_full_size_properties():
     # each Ritz value lies within the residual norm of an eigenvalue; the subspace found is
     # the dominant one, so the sorted values pair with the largest eigenvalues
     assert np.max(np.abs(ritz - top)) <= nR, (np.max(np.abs(ritz - top)), nR)
+    rel = np.max(np.abs(ritz - top) / top)
+    print(f"c2 full size: max Ritz rel err vs closed form {rel:.2e}", flush=True)
+    assert rel <= 1e-10
     # C and the column residuals are sums over 2^21 rows: rounding of about eps * 12 * 2^10.5
     # per entry of C, and a few 1e-12 in norms of order 1e-7
     assert np.allclose(np.sort(np.linalg.eigvalsh(0.5 * (C + C.T)))[::-1], ritz, rtol=0, atol=1e-10)
