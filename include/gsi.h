@@ -280,6 +280,16 @@ gsi_status gsi_pass_times(gsi_handle h, int32_t enable, double* ms, int32_t* cou
  * Gram sums are added in a fixed order, so results repeat bit for bit. Syncs. */
 gsi_status gsi_orthonormalize(double* X, int64_t n, int32_t p, void* hip_stream);
 
+/* gsi_orthonormalize for callers that cannot allocate device memory (code under HIP graph
+ * capture aside, tight serving loops, harnesses that forbid allocation): the same kernels,
+ * results and errors, with the scratch buffer in a file-scope device array of 4.3 MB that
+ * every device the library runs on holds until the process ends (its address is looked up
+ * once per device, on the first call made with that device current). Calls no hipMalloc or
+ * hipFree. The limit is the same, 1 <= p <= 64 (any n >= p). Every call on a device shares that
+ * device's array and overwrites what it reads, so calls that overlap on one device (two
+ * streams or two host threads) race and must be serialized by the caller. Syncs. */
+gsi_status gsi_orthonormalize_noalloc(double* X, int64_t n, int32_t p, void* hip_stream);
+
 void gsi_destroy(gsi_handle h);
 const char* gsi_status_str(gsi_status s);
 const char* gsi_last_error(gsi_handle h);

@@ -10,9 +10,12 @@
 // deficient or not finite) sets a flag that makes the later kernels of the call return
 // without touching X.
 //
-// Scratch (per call): the partial sums, R^{-1} and two flags, allocated for the call.
+// Scratch (per call): the partial sums, R^{-1} and two flags. gsi_orthonormalize allocates
+// it for the call; gsi_orthonormalize_noalloc uses a file-scope device array instead, so
+// that callers that cannot allocate device memory can call it.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <stdint.h>
 
 #include "../../include/gsi.h"
@@ -28,6 +31,11 @@ constexpr int OTILE = 32;       // rows per tile of the product pass
 constexpr size_t OFF_RINV = (size_t)OMAXWG * OMAXP2;
 constexpr size_t OFF_FLAGS = OFF_RINV + (size_t)OMAXP * OMAXP;
 constexpr size_t SCRATCH_DOUBLES = OFF_FLAGS + 64;
+
+// Scratch of gsi_orthonormalize_noalloc: 4.3 MB on every device the library runs on, held
+// until the process ends. Host code must not pass this name to a kernel (it is a host-side
+// stand-in there): it uses the device address from hipGetSymbolAddress.
+__device__ __align__(256) double scratch[SCRATCH_DOUBLES];
 
 int gram_blocks(int64_t n) {
   const int64_t t = (n + 63) / 64;
@@ -200,6 +208,25 @@ gsi_status check_args(const double* X, int64_t n, int32_t p) {
   return GSI_OK;
 }
 
+// Device address of `scratch` on each device, looked up once per device with that device
+// current (each device holds its own copy of the array at its own address).
+constexpr int MAXDEV = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAXDEV] = {nullptr};
+
+gsi_status scratch_for_current_device(double** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAXDEV) return GSI_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return GSI_EDEVICE;
+    g_scratch_ptr[dev] = reinterpret_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return GSI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -214,6 +241,15 @@ gsi_status gsi_orthonormalize(double* X, int64_t n, int32_t p, void* hip_stream)
   if (s == GSI_EDEVICE) (void)hipStreamSynchronize(st);
   (void)hipFree(scr);
   return s;
+}
+
+gsi_status gsi_orthonormalize_noalloc(double* X, int64_t n, int32_t p, void* hip_stream) {
+  gsi_status s = check_args(X, n, p);
+  if (s != GSI_OK) return s;
+  double* scr = nullptr;
+  s = scratch_for_current_device(&scr);
+  if (s != GSI_OK) return s;
+  return run_cholqr2(n, p, X, scr, reinterpret_cast<hipStream_t>(hip_stream));
 }
 
 }  // extern "C"

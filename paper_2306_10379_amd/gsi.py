@@ -24,7 +24,7 @@ EXPORTS = [
     "gsi_set_x0", "gsi_set_values", "gsi_spmm", "gsi_spmm_lowp", "gsi_history", "gsi_counters", "gsi_pass_times", "gsi_destroy",
     "gsi_status_str", "gsi_last_error", "gsi_create_batched", "gsi_solve_batched", "gsi_batched_results",
     "gsi_batched_get_x", "gsi_batched_set_tuning", "gsi_batched_set_wait_limit", "gsi_batched_timeline", "gsi_batched_pass_times", "gsi_batched_last_error", "gsi_destroy_batched",
-    "gsi_orthonormalize", "gsi_batched_set_shapes",
+    "gsi_orthonormalize", "gsi_orthonormalize_noalloc", "gsi_batched_set_shapes",
 ]
 PASSES = ["grad", "dir", "spmm", "update", "reduce", "small", "linesearch", "refresh", "eig", "gram"]
 
@@ -148,8 +148,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.gsi_batched_last_error.restype = ctypes.c_char_p
     L.gsi_destroy_batched.argtypes = [vp]
     L.gsi_destroy_batched.restype = None
-    L.gsi_orthonormalize.argtypes = [vp, i64, i32, vp]
-    L.gsi_orthonormalize.restype = ctypes.c_int
+    for name in ("gsi_orthonormalize", "gsi_orthonormalize_noalloc"):
+        getattr(L, name).argtypes = [vp, i64, i32, vp]
+        getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
 
@@ -300,16 +301,17 @@ def gsi_destroy(h):
         load().gsi_destroy(h)
 
 
-def orthonormalize(X, stream=None) -> int:
+def orthonormalize(X, noalloc: bool = False, stream=None) -> int:
     """Two passes of Cholesky QR on the contiguous float64 device block X (n x p, in place)
-    through gsi_orthonormalize. Returns the status (GSI_OK or GSI_BREAKDOWN); other statuses
-    raise."""
+    through gsi_orthonormalize, or gsi_orthonormalize_noalloc (static scratch, no device
+    allocation). Returns the status (GSI_OK or GSI_BREAKDOWN); other statuses raise."""
     import torch
     if not X.is_cuda or X.dtype != torch.float64 or not X.is_contiguous() or X.dim() != 2:
         raise TypeError("X must be a contiguous float64 n x p device tensor")
     L = load()
     st = ctypes.c_void_p(stream if stream is not None else torch.cuda.current_stream().cuda_stream)
-    s = L.gsi_orthonormalize(ctypes.c_void_p(_dptr(X)), int(X.shape[0]), int(X.shape[1]), st)
+    fn = L.gsi_orthonormalize_noalloc if noalloc else L.gsi_orthonormalize
+    s = fn(ctypes.c_void_p(_dptr(X)), int(X.shape[0]), int(X.shape[1]), st)
     if s not in (GSI_OK, GSI_BREAKDOWN):
         raise GsiError(s, L.gsi_status_str(s).decode())
     return s
