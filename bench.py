@@ -13,6 +13,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -21,6 +22,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+SHAPE_TABLE = os.path.join(ROOT, "paper_2306_10379_amd", "shape_table.json")
+TEAM_TABLE = os.path.join(ROOT, "paper_2306_10379_amd", "team_table.json")
 T_START = time.perf_counter()  # wall clock of the whole run (the budget counts from here)
 
 
@@ -135,6 +138,56 @@ def c3_leg(args, gsi, inputs, torch):
     res["speedup_bf16_vs_fp64"] = round(res["fp64"]["s"] / res["bf16"]["s"], 3)
     res["speedup_fp32_vs_fp64"] = round(res["fp64"]["s"] / res["fp32"]["s"], 3)
     return res
+
+
+def oracle_small_leg(args, gsi, inputs, torch):
+    """The float64 oracle's time to tolerance on the small configurations, next to the GPU's:
+    the 2D Laplacian 32 x 32 (p = 8 largest, rho <= 1e-10, seeds 0-9, medians), and a
+    stratified sample of the 512-problem Schroedinger batch (every 64th problem, p smallest,
+    rho <= tol) whose oracle time is scaled to the batch, against the batched GPU solve's
+    time for the whole batch (from the batched leg when it ran) and the plain GPU solve of
+    the same sample."""
+    from oracle import gsi_oracle as O
+    model, avail = cpu_info()
+    A = inputs.laplacian_2d(32)
+    t_o, t_g, it_o, it_g = [], [], [], []
+    for seed in range(10):
+        X0 = inputs.start_block(A.n, 8, seed)
+        t0 = time.perf_counter()
+        r = O.rcg(A, X0, tol=1e-10)
+        t_o.append(time.perf_counter() - t0)
+        it_o.append(r.iters)
+        s = gsi.Solver(A, X0, 8, tol=1e-10, max_iter=20000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, it = s.solve()
+        torch.cuda.synchronize()
+        t_g.append(time.perf_counter() - t0)
+        it_g.append(it)
+        s.close()
+    c1 = {"workload": "2D Dirichlet Laplacian 32x32 (n=1024), p=8 largest, rho <= 1e-10, X0 seeds 0-9",
+          "oracle_s_median": round(float(np.median(t_o)), 4), "gpu_s_median": round(float(np.median(t_g)), 4),
+          "oracle_iters_median": int(np.median(it_o)), "gpu_iters_median": int(np.median(it_g))}
+    log(f"oracle C1: {c1}")
+    mats, X0s, ps = inputs.schrodinger_batch(512, seed=2024)
+    sample = list(range(0, 512, 64))
+    to, tg = 0.0, 0.0
+    for j in sample:
+        t0 = time.perf_counter()
+        O.rcg(mats[j], X0s[j], tol=args.tol, which=-1, max_iter=30000)
+        to += time.perf_counter() - t0
+        s = gsi.Solver(mats[j], X0s[j], ps[j], which=-1, tol=args.tol, max_iter=30000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.solve()
+        torch.cuda.synchronize()
+        tg += time.perf_counter() - t0
+        s.close()
+    c4 = {"workload": f"512-problem Schroedinger batch, every 64th problem ({len(sample)}), p smallest, "
+                      f"rho <= {args.tol:g}; times scaled by {512 / len(sample):g} to the batch",
+          "oracle_s_scaled": round(to * 512 / len(sample), 2), "plain_gpu_s_scaled": round(tg * 512 / len(sample), 2)}
+    log(f"oracle C4 sample: {c4}")
+    return {"c1": c1, "c4_sample": c4, "cpu_model": model, "logical_cpus_available": avail}
 
 
 def laplacian3d_top(N, count):
@@ -286,6 +339,22 @@ PAPER_FD3D = {(16, 1): (1801, 10), (16, -1): (451, 2), (32, 1): (1051, 11), (32,
               (64, 1): (901, 27), (64, -1): (1401, 42)}
 
 
+def rsd_leg(args, gsi, torch, op, X0, p, lam_closed):
+    """The gradient variant (Algorithm 2, beta = 0) on the headline workload: a solve to the
+    tolerance (capped at --rsd-max-iter iterations) with graph launches as in the headline."""
+    with gsi.Solver(op, X0, p, method="rsd", tol=args.tol, max_iter=args.rsd_max_iter, check_every=50) as s:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        status, iters = s.solve()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ritz, _, rho, _ = s.residuals()
+    log(f"rsd: {dt:.2f} s, {iters} iterations, status {status}, rho {rho:.2e}")
+    return {"s": round(dt, 3), "iters": int(iters), "status": int(status), "rho": float(rho),
+            "ms_per_iteration": round(1e3 * dt / max(1, iters), 4),
+            "ritz_rel_err_vs_closed_form": float(np.max(np.abs(ritz - lam_closed) / np.abs(lam_closed)))}
+
+
 def paper_fd3d_leg(args, gsi, inputs, torch):
     """The paper's FD3D cases on the GPU with the paper's stopping rule: the first iteration
     with ||G_k||_inf / ||G_0||_inf <= 1e-8 (from the recorded history of a solve run past it),
@@ -326,18 +395,39 @@ def batched_leg(args, gsi, inputs, torch):
                        f"wells), p U{{4..32}} smallest, rho <= {args.tol:g}, one persistent launch in a HIP graph",
            "problems": count, "sum_n": int(sum(A.n for A in mats)),
            "sum_np": int(sum(A.n * p for A, p in zip(mats, ps)))}
+    from paper_2306_10379_amd import tuning
     policy = None
+    shape_path = args.shape_table or SHAPE_TABLE
+    team_path = os.path.join(os.path.dirname(os.path.abspath(shape_path)), "team_table.json")
+    team_key = tuning.batch_key([A.n for A in mats], ps, "mixed")
     for prec in ("mixed", "fp64"):
+        if args.tune:
+            # tile shapes per (n band, block width, precision) from the device pass clocks of
+            # the first 300 iterations of every problem (the per-iteration cost does not need
+            # whole solves), recorded in the shape table
+            with gsi.BatchedSolver(mats, X0s, ps, which=-1, precision=prec, tol=args.tol, max_iter=300,
+                                   switch_tol=1e-5) as tb:
+                tsw = time.perf_counter()
+                best, costs = tuning.tune_shapes(tb, prec, log=log)
+                tuning.record_shapes(shape_path, best)
+                res.setdefault("shape_tuning", {})[prec] = {
+                    "groups": best, "seconds": round(time.perf_counter() - tsw, 2),
+                    "us_per_iteration": {k: {f: {str(v): round(c, 1) for v, c in cv.items()} for f, cv in fc.items()}
+                                         for k, fc in costs.items()}}
         with gsi.BatchedSolver(mats, X0s, ps, which=-1, precision=prec, tol=args.tol, max_iter=30000,
                                switch_tol=1e-5) as b:
+            found = tuning.apply_shapes(b, shape_path, prec)
+            res.setdefault("shapes_from_table", {})[prec] = found
             if args.tune and policy is None:
-                from paper_2306_10379_amd import tuning
                 policy, ttimes = tuning.tune(b, log=log)
+                tuning.record(team_path, team_key, policy, ttimes)
                 res["tuning"] = {"best": list(policy),
                                  "seconds": {",".join(map(str, k)): round(v, 3) for k, v in ttimes.items()},
                                  "knobs": "tiles per member, recruits per check, iterations between checks"}
             elif policy is not None:
                 b.set_tuning(*policy)
+            else:  # the team policy recorded for this batch shape, if any (else the built default)
+                res["team_policy_from_table"] = tuning.apply_cached(b, team_path, team_key)
             times = []
             for i in range(2):
                 torch.cuda.synchronize()
@@ -393,8 +483,13 @@ def cpu_info():
 # Extra legs in the order they run while the wall-clock budget lasts, with the estimate of
 # their cost in units of one headline float64 solve (t64) plus fixed seconds.
 LEG_COST = {"mixed": (3.2, 5.0), "stencil": (2.2, 10.0), "paper_fd3d": (0.0, 12.0), "si": (0.7, 10.0),
-            "tracking": (0.0, 12.0), "hermitian": (0.0, 8.0), "batched": (0.0, 120.0)}
-DEFAULT_LEGS = ["mixed", "stencil", "paper_fd3d", "si", "tracking", "hermitian", "batched"]
+            "tracking": (0.0, 12.0), "hermitian": (0.0, 8.0), "batched": (0.0, 120.0), "oracle_small": (0.0, 110.0),
+            "rsd": (0.0, 100.0)}
+DEFAULT_LEGS = ["mixed", "stencil", "paper_fd3d", "si", "tracking", "hermitian", "oracle_small", "batched", "rsd"]
+# key of each leg's result in the JSON line
+LEG_KEY = {"mixed": "mixed_fp32", "stencil": "matrix_free", "si": "si_chebyshev", "batched": "batched",
+           "tracking": "tracking", "paper_fd3d": "paper_fd3d", "hermitian": "hermitian",
+           "oracle_small": "oracle_small_configs", "rsd": "rsd_gradient_variant"}
 
 
 def leg_estimate(leg, t_solve):
@@ -408,6 +503,14 @@ def leg_fits(leg, t_solve, now, budget):
     return now + leg_estimate(leg, t_solve) <= budget
 
 
+def warm_leg(args, log):
+    from paper_2306_10379_amd import warmstart
+    return warmstart.run_experiment(
+        N=256, p=32, ntrain=args.warm_train, ntest=args.warm_test, epochs=30, batch=16, lr=3e-3, tol=args.tol,
+        nsingle=3, chunk=args.warm_chunk, chunk_test=args.warm_chunk, compare_prior=False, warm_max_iter=20000,
+        log=log, bf16_weights=not args.warm_fp32, train_tol=args.warm_train_tol)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -417,7 +520,10 @@ def main():
     ap.add_argument("--p", type=int, default=64)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--budget", type=float, default=500.0,
+    ap.add_argument("--deadline", type=float, default=575.0,
+                    help="wall-clock seconds from the start after which the line is printed with the legs done so "
+                         "far and the run ends")
+    ap.add_argument("--budget", type=float, default=520.0,
                     help="wall-clock seconds from the start of the run: extra legs start only when their "
                          "estimated cost still fits (the headline solves, the pass timing and the CPU "
                          "baseline always run)")
@@ -432,21 +538,30 @@ def main():
     ap.add_argument("--leg-steps", type=int, default=2,
                     help="timed solves (after one untimed) of the mixed-precision and matrix-free legs")
     ap.add_argument("--tune", action="store_true",
-                    help="time the batched solve under candidate team policies first and use the fastest")
+                    help="batched leg: tune the tile shapes per (n band, block width, precision) and record them "
+                         "in the shape table, then time candidate team policies and use the fastest")
+    ap.add_argument("--shape-table", default=None,
+                    help="tile-shape table of the batched leg (default paper_2306_10379_amd/shape_table.json)")
     ap.add_argument("--legs-only", action="store_true",
                     help="skip the 3D Laplacian headline and run only the requested extra legs (for profiling); "
                          "prints a JSON line with those legs only")
     ap.add_argument("--warm", action="store_true",
                     help="also run the learned warm-start leg (256 x 256 Schroedinger operators, 8 wells, p = 32: "
-                         "training data from the method's own solves, training, held-out comparison; ~8 minutes)")
+                         "training data from the method's own solves, training, held-out comparison; minutes to "
+                         "tens of minutes with the default sizes: raise --deadline)")
     ap.add_argument("--c3", action="store_true",
                     help="also run the random-sparse leg: spiked sparse matrix n = 2^22, 24 random nonzeros per "
                          "row, p = 64 (float64, float32-mixed and bfloat16-mixed solves, SpMM rates; ~4 minutes)")
     ap.add_argument("--si-degrees", type=int, nargs="*", default=[64, 128])
     ap.add_argument("--si-full", action="store_true",
                     help="run the Chebyshev-filtered subspace iteration to the tolerance")
-    ap.add_argument("--warm-train", type=int, default=144)
-    ap.add_argument("--warm-test", type=int, default=24)
+    ap.add_argument("--rsd-max-iter", type=int, default=20000)
+    ap.add_argument("--warm-train", type=int, default=2048)
+    ap.add_argument("--warm-test", type=int, default=256)
+    ap.add_argument("--warm-train-tol", type=float, default=1e-6,
+                    help="tolerance of the training-target solves (the held-out solves use --tol)")
+    ap.add_argument("--warm-fp32", action="store_true", help="float32 network weights (default: bfloat16 + fp32 master)")
+    ap.add_argument("--warm-chunk", type=int, default=128, help="problems per batched solve of the warm leg")
     ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--plain-sample", type=int, default=32,
                     help="problems of the batch solved one by one on the plain float64 path")
@@ -525,7 +640,8 @@ def main():
 
     if args.legs_only:
         out = {"batched": batched_leg(args, gsi, inputs, torch) if "batched" in legs else None,
-               "random_sparse": c3_leg(args, gsi, inputs, torch) if args.c3 else None}
+               "random_sparse": c3_leg(args, gsi, inputs, torch) if args.c3 else None,
+               "warm_start": warm_leg(args, log) if args.warm else None}
         print(json.dumps(out), flush=True)
         return
 
@@ -563,6 +679,15 @@ def main():
                  "traffic": measured_traffic(f"gsi::k_spmm<double, {PPd}>", f"traffic_laplace3d_{N}_p{p}_fp64.json"),
                  "bytes_per_launch": nb["spmm"], "avg_us": round(kern["spmm"]["avg_us"], 2)}
     s64.close()
+    # the gradient variant (Algorithm 2) per iteration: a fixed run of 300 iterations from X0
+    # with graph launches, beside the conjugate-gradient solve's time per iteration
+    with gsi.Solver((rowptr, colind, vals, A.n), X0, p, method="rsd", tol=0.0, max_iter=300, check_every=50) as sr:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, it_r = sr.solve()
+        torch.cuda.synchronize()
+        rsd_fixed = {"iterations": int(it_r), "ms_per_iteration": round(1e3 * (time.perf_counter() - t0) / it_r, 4),
+                     "rcg_ms_per_iteration": round(1e3 * float(np.mean(t64)) / it64, 4)}
     log(f"headline done after {elapsed():.0f} s")
 
     cpu = None
@@ -571,58 +696,15 @@ def main():
         cpu = cpu_baseline(A, X0h, p, args.tol, it64, iters=args.cpu_iters)
         cpu["value"] = round(cpu["value"], 2)
 
-    # extra legs while the budget lasts
     t_solve = float(np.mean(t64))
-    results = {k: None for k in DEFAULT_LEGS}
-    skipped = []
-    for leg in legs:
-        est = leg_estimate(leg, t_solve)
-        if not leg_fits(leg, t_solve, elapsed(), args.budget):
-            skipped.append(leg)
-            log(f"skipping leg {leg}: estimated {est:.0f} s, {elapsed():.0f} of {args.budget:.0f} s used")
-            continue
-        t_leg = time.perf_counter()
-        if leg == "mixed":
-            s32, t32, it32, c32, ritz32, rho32 = timed_solves("mixed", args.leg_steps, 1)
-            s32.close()
-            results[leg] = {"value": round(float(np.mean(t32)), 4), "iters": it32, "low_iters": c32["low_iters"],
-                            "switch_tol": args.switch_tol, "steps": args.leg_steps, "warmup": 1,
-                            "speedup_vs_fp64": round(t_solve / float(np.mean(t32)), 3),
-                            "ritz_rel_err_vs_closed_form": float(np.max(np.abs(ritz32 - lam_closed) /
-                                                                        np.abs(lam_closed))),
-                            "ritz_rel_err_vs_fp64": float(np.max(np.abs(ritz32 - ritz64) / np.abs(ritz64))),
-                            "rho": rho32}
-        elif leg == "stencil":
-            results[leg] = stencil_leg(args, gsi, torch, X0, t_solve, it64, kern["spmm"]["avg_us"],
-                                       (rowptr, colind, vals, A.n))
-        elif leg == "si":
-            results[leg] = si_leg(args, gsi, torch, rowptr, colind, vals, A.n, X0, ritz64, c64["spmm"])
-        elif leg == "batched":
-            results[leg] = batched_leg(args, gsi, inputs, torch)
-        elif leg == "tracking":
-            results[leg] = tracking_leg(args, gsi, inputs, torch)
-        elif leg == "paper_fd3d":
-            results[leg] = paper_fd3d_leg(args, gsi, inputs, torch)
-        elif leg == "hermitian":
-            results[leg] = hermitian_leg(args, gsi, inputs, torch)
-        log(f"leg {leg}: {time.perf_counter() - t_leg:.1f} s (estimated {est:.0f} s), elapsed {elapsed():.0f} s")
-    c3 = c3_leg(args, gsi, inputs, torch) if args.c3 else None
-    warm = None
-    if args.warm:
-        from paper_2306_10379_amd import warmstart
-        warm = warmstart.run_experiment(N=256, p=32, ntrain=args.warm_train, ntest=args.warm_test, epochs=30, batch=16,
-                                        lr=3e-3, tol=args.tol, nsingle=3, chunk=48, chunk_test=12,
-                                        compare_prior=False, warm_max_iter=20000, log=log)
-
-    value = t_solve
     out = {
         "metric": "time to 1e-8 residual per solve (s) + SpMM HBM GB/s; mixed/warm vs plain FP64",
-        "value": round(value, 4),
+        "value": round(t_solve, 4),
         "unit": "s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * value, 2),
+        "ms_per_step": round(1e3 * t_solve, 2),
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
@@ -641,23 +723,80 @@ def main():
                     for k, v in kern.items()},
         "pass_share": {k: round(v[0] / total_ms, 4) for k, v in pt.items() if total_ms > 0},
         "pass_timing": f"HIP events around every launch of {args.pass_iters} iterations from X0 (direct launches)",
-        "mixed_fp32": results["mixed"],
-        "matrix_free": results["stencil"],
-        "si_chebyshev": results["si"],
-        "batched": results["batched"],
-        "random_sparse": c3,
-        "warm_start": warm,
-        "tracking": results["tracking"],
-        "paper_fd3d": results["paper_fd3d"],
-        "hermitian": results["hermitian"],
-        "skipped_legs": skipped,
+        "rsd_fixed_300": rsd_fixed,
+        **{key: None for key in LEG_KEY.values()},
+        "random_sparse": None,
+        "warm_start": None,
+        "skipped_legs": [],
         "budget_s": args.budget,
-        "elapsed_s": round(elapsed(), 1),
+        "elapsed_s": None,
         "roofline": roof,
         "spmm_roofline": spmm_roof,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
+    # the line is printed once: at the end, or by the watchdog at the deadline with the legs
+    # finished by then (a leg that overruns its estimate cannot cost the headline its line)
+    emitted = threading.Lock()
+
+    def emit(reason):
+        if not emitted.acquire(blocking=False):
+            return
+        out["elapsed_s"] = round(elapsed(), 1)
+        if reason:
+            out["truncated"] = reason
+        print(json.dumps(out), flush=True)
+
+    def watchdog():
+        log(f"deadline {args.deadline:.0f} s reached: printing the line with the legs done so far")
+        emit(f"deadline {args.deadline:.0f} s reached during the extra legs")
+        os._exit(0)
+
+    timer = threading.Timer(max(1.0, args.deadline - elapsed()), watchdog)
+    timer.daemon = True
+    timer.start()
+
+    # extra legs while the budget lasts
+    for leg in legs:
+        est = leg_estimate(leg, t_solve)
+        if not leg_fits(leg, t_solve, elapsed(), args.budget):
+            out["skipped_legs"].append(leg)
+            log(f"skipping leg {leg}: estimated {est:.0f} s, {elapsed():.0f} of {args.budget:.0f} s used")
+            continue
+        t_leg = time.perf_counter()
+        if leg == "mixed":
+            s32, t32, it32, c32, ritz32, rho32 = timed_solves("mixed", args.leg_steps, 1)
+            s32.close()
+            res = {"value": round(float(np.mean(t32)), 4), "iters": it32, "low_iters": c32["low_iters"],
+                   "switch_tol": args.switch_tol, "steps": args.leg_steps, "warmup": 1,
+                   "speedup_vs_fp64": round(t_solve / float(np.mean(t32)), 3),
+                   "ritz_rel_err_vs_closed_form": float(np.max(np.abs(ritz32 - lam_closed) / np.abs(lam_closed))),
+                   "ritz_rel_err_vs_fp64": float(np.max(np.abs(ritz32 - ritz64) / np.abs(ritz64))),
+                   "rho": rho32}
+        elif leg == "stencil":
+            res = stencil_leg(args, gsi, torch, X0, t_solve, it64, kern["spmm"]["avg_us"],
+                              (rowptr, colind, vals, A.n))
+        elif leg == "si":
+            res = si_leg(args, gsi, torch, rowptr, colind, vals, A.n, X0, ritz64, c64["spmm"])
+        elif leg == "batched":
+            res = batched_leg(args, gsi, inputs, torch)
+        elif leg == "tracking":
+            res = tracking_leg(args, gsi, inputs, torch)
+        elif leg == "paper_fd3d":
+            res = paper_fd3d_leg(args, gsi, inputs, torch)
+        elif leg == "hermitian":
+            res = hermitian_leg(args, gsi, inputs, torch)
+        elif leg == "oracle_small":
+            res = oracle_small_leg(args, gsi, inputs, torch)
+        elif leg == "rsd":
+            res = rsd_leg(args, gsi, torch, (rowptr, colind, vals, A.n), X0, p, lam_closed)
+        out[LEG_KEY[leg]] = res
+        log(f"leg {leg}: {time.perf_counter() - t_leg:.1f} s (estimated {est:.0f} s), elapsed {elapsed():.0f} s")
+    if args.c3:
+        out["random_sparse"] = c3_leg(args, gsi, inputs, torch)
+    if args.warm:
+        out["warm_start"] = warm_leg(args, log)
+    timer.cancel()
+    emit(None)
 
 
 if __name__ == "__main__":

@@ -7,8 +7,9 @@
  * the fallback) needs fewer iterations to the same residual; the solver still runs to the
  * tolerance, so the network can only cost iterations, never accuracy.
  *
- * Network (widths w, sine modes m, L hidden layers, p outputs), all float32 with float32
- * accumulation (the p x p loss algebra in float64):
+ * Network (widths w, sine modes m, L hidden layers, p outputs), float32 activations with
+ * float32 accumulation (the p x p loss algebra in float64); the weights are float32, or,
+ * with bf16_weights set, a bfloat16 working copy of a float32 master (below):
  *   In  = [V / 20, x, y]                       x = (col + 1)/(N + 1), y = (row + 1)/(N + 1)
  *   U_0 = W_lift In + b_lift                   pointwise 3 -> w
  *   U_{l+1} = gelu(K_l(U_l) + W_l U_l + b_l)   l = 0 .. L-1, gelu(t) = t Phi_n(t), Phi_n the normal CDF
@@ -26,8 +27,16 @@
  * layer R (w x w x m x m, [o][c][k1][k2]), W (w x w, [o][c]), b (w); R_out (p x w x m x m),
  * W_out (p x w), b_out (p). The gradient uses the same layout.
  *
+ * bfloat16 weights (bf16_weights = 1): every parameter the forward and backward passes read
+ * comes from a bfloat16 copy of the float32 parameter vector, each entry rounded to nearest
+ * (ties to even) when the vector is set (creation, fno_set_params) and after every Adam step;
+ * the products with those weights widen them to float32 and accumulate in float32. The
+ * gradient is the float32 gradient of the loss at the rounded weights, and Adam updates the
+ * float32 master (fno_get_params returns the master), so steps smaller than a bfloat16 ulp
+ * still accumulate.
+ *
  * Limits: N a multiple of 16, N <= 1024; 1 <= m <= 32, m <= N; 1 <= w <= 32; 1 <= p <= 32;
- * L >= 0; batch 1 .. max_batch. All pointers to data are device pointers owned by the
+ * L >= 0; batch 1 .. max_batch; bf16_weights 0 or 1. All pointers to data are device pointers owned by the
  * caller; calls are ordered on the stream given at creation; no call allocates after
  * fno_create. Errors: GSI_EINVAL for sizes or null pointers, GSI_ENOMEM, GSI_EDEVICE
  * (HIP error, or a singular Gram Y^T Y in the loss: message in fno_last_error). */
@@ -50,6 +59,7 @@ typedef struct {
   int32_t layers;     /* L */
   int32_t p;          /* output columns */
   int32_t max_batch;  /* largest batch of any call */
+  int32_t bf16_weights; /* 0: float32 weights; 1: bfloat16 working copy of a float32 master */
 } fno_config;
 
 /* Number of parameters of cfg (also the gradient length); -1 for an invalid cfg. */

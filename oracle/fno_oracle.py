@@ -167,3 +167,20 @@ def adam_step(flat, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     mh = m / (1.0 - beta1 ** t)
     vh = v / (1.0 - beta2 ** t)
     flat[:] = flat - lr * mh / (np.sqrt(vh) + eps)
+
+
+def round_bf16(x) -> np.ndarray:
+    """bfloat16 value of each float32 entry of x, as float64. bfloat16 keeps binary32's sign
+    and 8-bit exponent and the top 7 fraction bits: the 16 low bits of the binary32 pattern are
+    rounded away to nearest, ties to the even pattern (a carry may step the exponent, and
+    the largest finite values round to infinity); NaN stays NaN. The weights of the network in
+    its bfloat16 mode are these values of the float32 parameters."""
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    u = a.view(np.uint32).astype(np.uint64)
+    kept = u >> 16
+    rest = u & 0xFFFF
+    up = (rest > 0x8000) | ((rest == 0x8000) & (kept & 1 == 1))
+    bits = ((kept + up) << 16).astype(np.uint32)
+    out = bits.view(np.float32).astype(np.float64)
+    out[np.isnan(a)] = np.nan
+    return out

@@ -1,5 +1,6 @@
 // Sine-basis neural operator for warm starts (see include/fno.h): forward pass, subspace
-// loss, gradient and Adam, all as gfx950 kernels on float32 data.
+// loss, gradient and Adam, all as gfx950 kernels on float32 data, with the weights read as
+// float32 or from a bfloat16 working copy (Wp).
 //
 // Data layout: activations channel-major, [sample][channel][N x N grid, row-major], so a
 // channel of a sample is one contiguous n = N^2 vector. The sine transform of a channel,
@@ -34,6 +35,16 @@ using gsi::mfma;
 constexpr int WG = 256;
 
 __device__ __forceinline__ f4 ld4(const float* p) { return gld(reinterpret_cast<const f4*>(p)); }
+
+// A run of weights: the float32 master, or (h set) its bfloat16 working copy, widened on
+// reading. The choice is the same for every thread of a launch.
+struct Wp {
+  const float* f;
+  const uint16_t* h;
+  __device__ __forceinline__ float operator[](int64_t i) const {
+    return h ? gsi::bf16_widen(gld(h + i)) : gld(f + i);
+  }
+};
 
 // ---------------------------------------------------------------- C = alpha P Q^T + beta C
 
@@ -176,8 +187,7 @@ __device__ __forceinline__ float gelu_d(float t) {
 }
 
 // In[b] = [V / 20, x, y]; U0[b][c] = W_lift In + b_lift. Thread per (sample, node).
-__global__ void k_lift(const float* V, int N, int w, const float* W, const float* bias, float* In, float* U0,
-                       int B) {
+__global__ void k_lift(const float* V, int N, int w, Wp W, Wp bias, float* In, float* U0, int B) {
   const int64_t n = (int64_t)N * N;
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= (int64_t)B * n) return;
@@ -188,17 +198,16 @@ __global__ void k_lift(const float* V, int N, int w, const float* W, const float
   gst(In + (b * 3 + 1) * n + j, f1);
   gst(In + (b * 3 + 2) * n + j, f2);
   for (int c = 0; c < w; ++c)
-    gst(U0 + (b * w + c) * n + j, gld(bias + c) + gld(W + 3 * c) * f0 + gld(W + 3 * c + 1) * f1 + gld(W + 3 * c + 2) * f2);
+    gst(U0 + (b * w + c) * n + j, bias[c] + W[3 * c] * f0 + W[3 * c + 1] * f1 + W[3 * c + 2] * f2);
 }
 
 // s = Vs[b][o] + sum_c W[o][c] U[b][c] + bias[o] (+ add[o], the same for every sample);
 // Pre = s (if given); Out = act ? gelu(s) : s.
-__global__ __launch_bounds__(WG) void k_point_fwd(const float* Vs, const float* U, const float* W, const float* bias,
-                                                  const float* add, float* Pre, float* Out, int O, int C, int64_t n,
-                                                  int B, int act) {
+__global__ __launch_bounds__(WG) void k_point_fwd(const float* Vs, const float* U, Wp W, Wp bias, const float* add,
+                                                  float* Pre, float* Out, int O, int C, int64_t n, int B, int act) {
   __shared__ float sW[32 * 32 + 32];
-  for (int e = threadIdx.x; e < O * C; e += WG) sW[e] = gld(W + e);
-  for (int e = threadIdx.x; e < O; e += WG) sW[1024 + e] = gld(bias + e);
+  for (int e = threadIdx.x; e < O * C; e += WG) sW[e] = W[e];
+  for (int e = threadIdx.x; e < O; e += WG) sW[1024 + e] = bias[e];
   __syncthreads();
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= (int64_t)B * n) return;
@@ -217,10 +226,10 @@ __global__ __launch_bounds__(WG) void k_point_fwd(const float* Vs, const float* 
 }
 
 // dPre = act ? dOut * gelu'(Pre) : dOut (stored when dPre is given); dU[b][c] = sum_o W[o][c] dPre[b][o].
-__global__ __launch_bounds__(WG) void k_point_bwd(const float* dOut, const float* Pre, const float* W, float* dPre,
-                                                  float* dU, int O, int C, int64_t n, int B, int act) {
+__global__ __launch_bounds__(WG) void k_point_bwd(const float* dOut, const float* Pre, Wp W, float* dPre, float* dU,
+                                                  int O, int C, int64_t n, int B, int act) {
   __shared__ float sW[32 * 32];
-  for (int e = threadIdx.x; e < O * C; e += WG) sW[e] = gld(W + e);
+  for (int e = threadIdx.x; e < O * C; e += WG) sW[e] = W[e];
   __syncthreads();
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= (int64_t)B * n) return;
@@ -244,7 +253,7 @@ __global__ __launch_bounds__(WG) void k_point_bwd(const float* dOut, const float
 // ---------------------------------------------------------------- mode-wise channel mixing
 
 // Vh[b][o][k] = sum_c R[o][c][k] Uh[b][c][k] on the m x m modes (zero on the padding of MP).
-__global__ void k_mix_fwd(const float* R, const float* Uh, float* Vh, int B, int O, int C, int m, int MP) {
+__global__ void k_mix_fwd(Wp R, const float* Uh, float* Vh, int B, int O, int C, int m, int MP) {
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t per = (int64_t)MP * MP;
   if (id >= (int64_t)B * O * per) return;
@@ -254,12 +263,12 @@ __global__ void k_mix_fwd(const float* R, const float* Uh, float* Vh, int B, int
   float s = 0.f;
   if (k1 < m && k2 < m)
     for (int c = 0; c < C; ++c)
-      s += gld(R + ((o * C + c) * m + k1) * m + k2) * gld(Uh + (b * C + c) * per + k);
+      s += R[((o * C + c) * m + k1) * m + k2] * gld(Uh + (b * C + c) * per + k);
   gst(Vh + id, s);
 }
 
 // dUh[b][c][k] = sum_o R[o][c][k] dVh[b][o][k].
-__global__ void k_mix_bwd(const float* R, const float* dVh, float* dUh, int B, int O, int C, int m, int MP) {
+__global__ void k_mix_bwd(Wp R, const float* dVh, float* dUh, int B, int O, int C, int m, int MP) {
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t per = (int64_t)MP * MP;
   if (id >= (int64_t)B * C * per) return;
@@ -269,7 +278,7 @@ __global__ void k_mix_bwd(const float* R, const float* dVh, float* dUh, int B, i
   float s = 0.f;
   if (k1 < m && k2 < m)
     for (int o = 0; o < O; ++o)
-      s += gld(R + ((o * C + c) * m + k1) * m + k2) * gld(dVh + (b * O + o) * per + k);
+      s += R[((o * C + c) * m + k1) * m + k2] * gld(dVh + (b * O + o) * per + k);
   gst(dUh + id, s);
 }
 
@@ -420,8 +429,9 @@ __global__ void k_from_channels(const float* Y, float* Y32, double* Y64, int p, 
   if (Y64) gst(Y64 + id, (double)v);
 }
 
-__global__ void k_adam(float* w, const float* g, float* m1, float* m2, int64_t count, float lr, float b1, float b2,
-                       float eps, float c1, float c2) {
+// Adam on the float32 master w; wbf (nullable) receives the updated weights rounded to bfloat16.
+__global__ void k_adam(float* w, uint16_t* wbf, const float* g, float* m1, float* m2, int64_t count, float lr, float b1,
+                       float b2, float eps, float c1, float c2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
   const float gi = gld(g + i);
@@ -429,7 +439,14 @@ __global__ void k_adam(float* w, const float* g, float* m1, float* m2, int64_t c
   const float v = b2 * gld(m2 + i) + (1.f - b2) * gi * gi;
   gst(m1 + i, m);
   gst(m2 + i, v);
-  gst(w + i, gld(w + i) - lr * (m / c1) / (sqrtf(v / c2) + eps));
+  const float nw = gld(w + i) - lr * (m / c1) / (sqrtf(v / c2) + eps);
+  gst(w + i, nw);
+  if (wbf) gst(wbf + i, gsi::bf16_round(nw));
+}
+
+__global__ void k_round_bf16(const float* w, uint16_t* wbf, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) gst(wbf + i, gsi::bf16_round(gld(w + i)));
 }
 
 // splitmix64 (Steele, Lea, Flood 2014) and Box-Muller for the seeded initial weights.
@@ -461,6 +478,7 @@ struct fno_net {
   int64_t oWl = 0, obl = 0;
   std::vector<int64_t> oR, oW, ob;  // L + 1 entries, the last is the output layer
   float *params = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr;
+  uint16_t* wbf = nullptr;  // bfloat16 working copy of params (bf16_weights), else null
   int64_t step = 0;
   float *S = nullptr, *St = nullptr, *ones = nullptr, *prior = nullptr;
   float *In = nullptr, *Y = nullptr, *Xc = nullptr, *dY = nullptr, *dPre = nullptr, *dUa = nullptr, *dUb = nullptr;
@@ -476,8 +494,12 @@ namespace {
 
 bool valid(const fno_config* c) {
   return c && c->N >= 16 && c->N <= 1024 && c->N % 16 == 0 && c->modes >= 1 && c->modes <= 32 && c->modes <= c->N &&
-         c->width >= 1 && c->width <= 32 && c->p >= 1 && c->p <= 32 && c->layers >= 0 && c->max_batch >= 1;
+         c->width >= 1 && c->width <= 32 && c->p >= 1 && c->p <= 32 && c->layers >= 0 && c->max_batch >= 1 &&
+         (c->bf16_weights == 0 || c->bf16_weights == 1);
 }
+
+// The weights at parameter offset off, in the format the passes read.
+Wp wp(const fno_net* h, int64_t off) { return Wp{h->params + off, h->wbf ? h->wbf + off : nullptr}; }
 
 int64_t count_params(const fno_config* c) {
   const int64_t w = c->width, m = c->modes, p = c->p;
@@ -533,13 +555,13 @@ void forward(fno_net* h, const float* V, int B) {
   const fno_config& c = h->cfg;
   const int w = c.width, p = c.p, L = c.layers, m = c.modes, MP = h->MP;
   const int64_t n = h->n;
-  k_lift<<<blocks(B * n), WG, 0, h->st>>>(V, c.N, w, h->params + h->oWl, h->params + h->obl, h->In, h->act[0], B);
+  k_lift<<<blocks(B * n), WG, 0, h->st>>>(V, c.N, w, wp(h, h->oWl), wp(h, h->obl), h->In, h->act[0], B);
   for (int l = 0; l <= L; ++l) {
     const int O = l < L ? w : p;
     fwd_transform(h, h->act[l], B * w, h->uh[l]);
-    k_mix_fwd<<<blocks((int64_t)B * O * MP * MP), WG, 0, h->st>>>(h->params + h->oR[l], h->uh[l], h->Vh, B, O, w, m, MP);
+    k_mix_fwd<<<blocks((int64_t)B * O * MP * MP), WG, 0, h->st>>>(wp(h, h->oR[l]), h->uh[l], h->Vh, B, O, w, m, MP);
     inv_transform(h, h->Vh, B * O, h->Vs, 0.f);
-    k_point_fwd<<<blocks(B * n), WG, 0, h->st>>>(h->Vs, h->act[l], h->params + h->oW[l], h->params + h->ob[l],
+    k_point_fwd<<<blocks(B * n), WG, 0, h->st>>>(h->Vs, h->act[l], wp(h, h->oW[l]), wp(h, h->ob[l]),
                                                  l < L ? nullptr : h->prior, l < L ? h->pre[l] : nullptr, l < L ? h->act[l + 1] : h->Y, O, w, n,
                                                  B, l < L ? 1 : 0);
   }
@@ -557,7 +579,7 @@ void backward(fno_net* h, int B) {
     const float* dOut = l < L ? cur : h->dY;
     float* dU = l < L ? nxt : cur;
     // dPre (= dY for the output layer) and the local part of dU
-    k_point_bwd<<<blocks(B * n), WG, 0, h->st>>>(dOut, l < L ? h->pre[l] : nullptr, h->params + h->oW[l],
+    k_point_bwd<<<blocks(B * n), WG, 0, h->st>>>(dOut, l < L ? h->pre[l] : nullptr, wp(h, h->oW[l]),
                                                  l < L ? h->dPre : nullptr, dU, O, w, n, B, l < L ? 1 : 0);
     const float* dP = l < L ? h->dPre : h->dY;
     // W and b gradients: sums over samples and nodes
@@ -566,7 +588,7 @@ void backward(fno_net* h, int B) {
     // spectral part: dVh = S dPre S^T, dR, dUh, dU += S^T dUh S
     fwd_transform(h, dP, B * O, h->Vh);
     k_mix_wgrad<<<blocks((int64_t)O * w * m * m), WG, 0, h->st>>>(h->Vh, h->uh[l], h->grad + h->oR[l], B, O, w, m, MP);
-    k_mix_bwd<<<blocks((int64_t)B * w * MP * MP), WG, 0, h->st>>>(h->params + h->oR[l], h->Vh, h->dUh, B, O, w, m, MP);
+    k_mix_bwd<<<blocks((int64_t)B * w * MP * MP), WG, 0, h->st>>>(wp(h, h->oR[l]), h->Vh, h->dUh, B, O, w, m, MP);
     inv_transform(h, h->dUh, B * w, dU, 1.f);
     if (l < L) std::swap(cur, nxt);
   }
@@ -594,7 +616,7 @@ gsi_status fno_create(fno_handle* out, const fno_config* cfg, uint64_t seed, voi
   if (!h) return GSI_ENOMEM;
   *out = h;
   if (!valid(cfg)) {
-    h->err = "invalid configuration (N a multiple of 16 in 16..1024, 1 <= modes <= 32, width, p <= 32)";
+    h->err = "invalid configuration (N a multiple of 16 in 16..1024, 1 <= modes <= 32, width, p <= 32, bf16_weights 0 or 1)";
     return GSI_EINVAL;
   }
   h->cfg = *cfg;
@@ -623,6 +645,7 @@ gsi_status fno_create(fno_handle* out, const fno_config* cfg, uint64_t seed, voi
   hipError_t e = hipSuccess;
   h->params = nalloc<float>(h, h->count, e);
   h->grad = nalloc<float>(h, h->count, e);
+  if (c.bf16_weights) h->wbf = nalloc<uint16_t>(h, h->count, e);
   h->m1 = nalloc<float>(h, h->count, e);
   h->m2 = nalloc<float>(h, h->count, e);
   h->S = nalloc<float>(h, (size_t)MP * N, e);
@@ -697,13 +720,22 @@ gsi_status fno_create(fno_handle* out, const fno_config* cfg, uint64_t seed, voi
   if (e == hipSuccess) e = hipMemsetAsync(h->m1, 0, h->count * 4, h->st);
   if (e == hipSuccess) e = hipMemsetAsync(h->m2, 0, h->count * 4, h->st);
   if (e == hipSuccess) e = hipMemsetAsync(h->grad, 0, h->count * 4, h->st);
+  if (e == hipSuccess && h->wbf) {
+    k_round_bf16<<<blocks(h->count), WG, 0, h->st>>>(h->params, h->wbf, h->count);
+    e = hipGetLastError();
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(h->st);
   return hip_status(h, e, "create");
 }
 
 gsi_status fno_set_params(fno_handle h, const float* params) {
   if (!h || !params) return GSI_EINVAL;
-  return hip_status(h, hipMemcpyAsync(h->params, params, h->count * 4, hipMemcpyDeviceToDevice, h->st), "set_params");
+  hipError_t e = hipMemcpyAsync(h->params, params, h->count * 4, hipMemcpyDeviceToDevice, h->st);
+  if (e == hipSuccess && h->wbf) {
+    k_round_bf16<<<blocks(h->count), WG, 0, h->st>>>(h->params, h->wbf, h->count);
+    e = hipGetLastError();
+  }
+  return hip_status(h, e, "set_params");
 }
 
 gsi_status fno_get_params(fno_handle h, float* params) {
@@ -751,7 +783,8 @@ gsi_status fno_adam(fno_handle h, float lr, float beta1, float beta2, float eps)
   if (!h) return GSI_EINVAL;
   ++h->step;
   const float c1 = 1.f - powf(beta1, (float)h->step), c2 = 1.f - powf(beta2, (float)h->step);
-  k_adam<<<blocks(h->count), WG, 0, h->st>>>(h->params, h->grad, h->m1, h->m2, h->count, lr, beta1, beta2, eps, c1, c2);
+  k_adam<<<blocks(h->count), WG, 0, h->st>>>(h->params, h->wbf, h->grad, h->m1, h->m2, h->count, lr, beta1, beta2, eps,
+                                              c1, c2);
   return hip_status(h, hipGetLastError(), "adam");
 }
 

@@ -17,7 +17,8 @@ EXPORTS = ["fno_param_count", "fno_create", "fno_set_params", "fno_get_params", 
 
 class FnoConfig(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("modes", ctypes.c_int32), ("width", ctypes.c_int32),
-                ("layers", ctypes.c_int32), ("p", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
+                ("layers", ctypes.c_int32), ("p", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("bf16_weights", ctypes.c_int32)]
 
 
 _ready = False
@@ -64,11 +65,13 @@ def _need(t, name, shape):
 
 class Net:
     """Owns an fno handle. Tensors are float32 (float64 for forward(..., f64=True)) on the
-    handle's device; V is (B, N*N), targets (B, N*N, p)."""
+    handle's device; V is (B, N*N), targets (B, N*N, p). bf16_weights: the passes read a
+    bfloat16 copy of the float32 parameters (which Adam updates)."""
 
-    def __init__(self, N=256, modes=24, width=20, layers=4, p=32, max_batch=16, seed=0, stream=None):
+    def __init__(self, N=256, modes=24, width=20, layers=4, p=32, max_batch=16, seed=0, stream=None,
+                 bf16_weights=False):
         import torch
-        self.cfg = FnoConfig(N, modes, width, layers, p, max_batch)
+        self.cfg = FnoConfig(N, modes, width, layers, p, max_batch, int(bool(bf16_weights)))
         self.L = load()
         self.count = int(self.L.fno_param_count(ctypes.byref(self.cfg)))
         if self.count < 0:

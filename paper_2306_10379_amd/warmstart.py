@@ -153,20 +153,26 @@ def single_solves(mats, p, X0s, tol, precision="fp64"):
 
 def run_experiment(N=256, p=32, ntrain=512, ntest=64, modes=24, width=20, layers=4, epochs=30, batch=16,
                    lr=3e-3, tol=1e-8, seed=1, nsingle=8, chunk=64, chunk_test=None, compare_prior=True,
-                   warm_max_iter=60000, log=None):
+                   warm_max_iter=60000, log=None, bf16_weights=False, train_tol=None):
     """Train on the method's own solves and compare start blocks on held-out potentials.
 
-    Training targets: converged bases of ntrain problems solved from random starts.
-    Held-out comparison (ntest problems, batched, mixed precision to tol): random start,
-    prior start, trained network start (inference time included); plus nsingle plain float64
-    single-problem solves from the random and from the network start."""
+    Training targets: bases of ntrain problems solved from random starts to train_tol
+    (default tol; a looser one only has to beat the network's own error, which is orders of
+    magnitude above it). Held-out comparison (ntest problems, batched, mixed precision to
+    tol): random start, prior start, trained network start (inference time included); plus
+    nsingle plain float64 single-problem solves from the random and from the network start.
+    bf16_weights: the network's passes read bfloat16 weights (float32 master in Adam)."""
     import torch
     log = log or (lambda s: None)
     chunk_test = chunk_test or ntest
-    out = {"grid": N, "p": p, "train": ntrain, "test": ntest, "tol": tol,
-           "network": {"modes": modes, "width": width, "layers": layers}}
+    train_tol = tol if train_tol is None else train_tol
+    out = {"grid": N, "p": p, "train": ntrain, "test": ntest, "tol": tol, "train_tol": train_tol,
+           "network": {"modes": modes, "width": width, "layers": layers,
+                       "weights": "bf16 (fp32 master)" if bf16_weights else "fp32"}}
     log(f"building {ntrain + ntest} problems on {N} x {N} grids")
+    t0 = time.perf_counter()
     mats, V = potential_problems(ntrain + ntest, seed, N)
+    out["build_problems_s"] = round(time.perf_counter() - t0, 2)
     X0r = random_starts(mats, p, seed)
     prior = prior_blocks(N, p, ntrain + ntest)
     Vd = torch.as_tensor(V, dtype=torch.float32, device="cuda")
@@ -174,7 +180,7 @@ def run_experiment(N=256, p=32, ntrain=512, ntest=64, modes=24, width=20, layers
     it_tr, st_tr, dt_tr = [], [], 0.0
     for s0 in range(0, ntrain, chunk):
         s1 = min(ntrain, s0 + chunk)
-        X, it, st, dt = solve_batch(mats[s0:s1], p, X0r[s0:s1], tol)
+        X, it, st, dt = solve_batch(mats[s0:s1], p, X0r[s0:s1], train_tol)
         for i, x in enumerate(X):
             Xd[s0 + i].copy_(x)
         del X
@@ -203,7 +209,8 @@ def run_experiment(N=256, p=32, ntrain=512, ntest=64, modes=24, width=20, layers
         it_p, dt_p, nfp = warm_solve(mats[ntrain:], p, prior[ntrain:], X0r[ntrain:], tol, chunk=chunk_test, log=log,
                                      max_iter=warm_max_iter)
         log(f"held-out, prior start: {dt_p:.1f} s, mean iterations {it_p.mean():.0f}, fallbacks {nfp}")
-    net = fno.Net(N=N, modes=modes, width=width, layers=layers, p=p, max_batch=batch, seed=seed)
+    net = fno.Net(N=N, modes=modes, width=width, layers=layers, p=p, max_batch=batch, seed=seed,
+                  bf16_weights=bf16_weights)
     out["network"]["params"] = net.count
     loss0 = mean_loss(net, Vd[ntrain:], Xtd, batch)
     torch.cuda.synchronize()

@@ -54,9 +54,11 @@ def test_network_parameter_count_matches_reference():
     from paper_2306_10379_amd import fno
     L = fno.load()
     for cfg in [F.Config(), F.Config(N=16, m=6, w=5, L=2, p=4), F.Config(N=32, m=11, w=7, L=0, p=9)]:
-        c = fno.FnoConfig(cfg.N, cfg.m, cfg.w, cfg.L, cfg.p, 4)
-        assert L.fno_param_count(ctypes.byref(c)) == F.param_count(cfg)
-    for bad in [(20, 6, 5, 2, 4, 1), (16, 40, 5, 2, 4, 1), (16, 6, 33, 2, 4, 1), (16, 6, 5, 2, 0, 1)]:
+        for bf16 in (0, 1):
+            c = fno.FnoConfig(cfg.N, cfg.m, cfg.w, cfg.L, cfg.p, 4, bf16)
+            assert L.fno_param_count(ctypes.byref(c)) == F.param_count(cfg)
+    for bad in [(20, 6, 5, 2, 4, 1), (16, 40, 5, 2, 4, 1), (16, 6, 33, 2, 4, 1), (16, 6, 5, 2, 0, 1),
+                (16, 6, 5, 2, 4, 1, 2)]:
         assert L.fno_param_count(ctypes.byref(fno.FnoConfig(*bad))) == -1
 
 

@@ -70,7 +70,7 @@ def test_extra_legs_start_only_within_the_budget():
     assert b.leg_fits("hermitian", 14.0, 380.0, 500.0)
     assert not b.leg_fits("mixed", 14.0, 480.0, 500.0)
     assert b.leg_estimate("mixed", 10.0) == 3.2 * 10.0 + 5.0
-    assert set(b.DEFAULT_LEGS) == set(b.LEG_COST)
+    assert set(b.DEFAULT_LEGS) == set(b.LEG_COST) == set(b.LEG_KEY)
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--legs", "nope"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "unknown leg" in r.stderr

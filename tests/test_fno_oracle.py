@@ -180,3 +180,31 @@ def test_forward_composes_the_layers_as_defined():
     ref = F.prior(N, p).numpy()[None] + K(U, R) + pw(U, W, b)
     got = F.forward(torch.as_tensor(flat), torch.as_tensor(V), cfg).numpy()
     assert np.allclose(got, ref, rtol=1e-12, atol=1e-12)
+
+
+def test_bf16_rounding_is_the_library_conversion():
+    """round_bf16 against torch's float32 -> bfloat16 conversion (round to nearest even): random
+    values over many binades, exact halfway cases of both parities, values one bit either side
+    of a tie, a carry into the exponent, subnormals, signed zeros, infinities and the
+    overflow to infinity."""
+    g = np.random.default_rng(3)
+    vals = [g.standard_normal(20000) * np.exp(g.uniform(-40, 40, 20000))]
+    base = np.float32(1.0).view(np.uint32)
+    ties = []
+    for k in range(64):  # patterns kept | 0x8000 for even and odd kept parts, and neighbours
+        kept = (base >> 16) + k
+        for low in (0x7FFF, 0x8000, 0x8001):
+            ties.append(np.uint32((kept << 16) | low))
+    ties.append(np.uint32(0x3F7FFFFF))             # just below 1: carries into the exponent
+    ties += [np.uint32(0x00008000), np.uint32(0x00018000), np.uint32(0x0000FFFF)]  # subnormal ties
+    ties += [np.uint32(0x7F7FFFFF), np.uint32(0xFF7FFFFF)]  # largest finite: round to +-inf
+    vals.append(np.array(ties, dtype=np.uint32).view(np.float32).astype(np.float64))
+    vals.append(np.array([0.0, -0.0, np.inf, -np.inf, 1e-45, -1e-45]))
+    x = np.concatenate(vals).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    got = F.round_bf16(x)
+    assert np.array_equal(got.view(np.uint64), ref.view(np.uint64))
+    assert np.isnan(F.round_bf16(np.array([np.nan], np.float32))).all()
+    # ties go to the even pattern: 1 + 2^-8 -> 1, 1 + 3 * 2^-8 -> 1 + 2^-6
+    assert F.round_bf16(np.float32(1 + 2 ** -8)) == 1.0
+    assert F.round_bf16(np.float32(1 + 3 * 2 ** -8)) == 1 + 2 ** -6

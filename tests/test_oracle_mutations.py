@@ -201,7 +201,8 @@ from tests import test_fno_oracle as TF  # noqa: E402
 
 _FNO_PINS = [TF.test_forward_composes_the_layers_as_defined, TF.test_zero_network_outputs_the_prior_plus_output_bias,
              TF.test_spectral_layer_reproduces_low_sine_modes, TF.test_loss_is_sum_of_squared_principal_angle_sines,
-             TF.test_adam_first_step_moves_each_weight_by_lr, TF.test_gradient_matches_central_differences]
+             TF.test_adam_first_step_moves_each_weight_by_lr, TF.test_gradient_matches_central_differences,
+             TF.test_bf16_rounding_is_the_library_conversion]
 
 FNO_MUTATIONS = {
     "network: gelu left out of the hidden layers": (
@@ -214,6 +215,9 @@ FNO_MUTATIONS = {
     "loss: G^-1 left out": ("subspace_loss", "torch.linalg.solve(G, M)", "M"),
     "adam: no bias correction of the first moment": ("adam_step", "mh = m / (1.0 - beta1 ** t)", "mh = m"),
     "adam: second moment not squared": ("adam_step", "(1.0 - beta2) * grad * grad", "(1.0 - beta2) * grad"),
+    "bfloat16: truncation instead of rounding": ("round_bf16", "bits = ((kept + up) << 16)", "bits = (kept << 16)"),
+    "bfloat16: ties away from zero": ("round_bf16", "up = (rest > 0x8000) | ((rest == 0x8000) & (kept & 1 == 1))",
+                                      "up = rest >= 0x8000"),
 }
 
 
