@@ -6,6 +6,8 @@
 // Every multi-workgroup kernel writes per-workgroup partial sums (Gram matrices and
 // scalars) to partials[blockIdx.x * nv + ...]; k_reduce sums them in a fixed order, so
 // results are bitwise reproducible run to run.
+#include <type_traits>
+
 #include "gsi_kernels.h"
 
 namespace gsi {
@@ -693,6 +695,163 @@ __global__ __launch_bounds__(WG) void k_spmm_stencil(int64_t n, int32_t nx, int3
   }
 }
 
+// The same product for grids with at least SY rows in y (2D and 3D), with each row of W
+// read from memory about once instead of once per neighbour. A workgroup owns a tile of
+// SX x SY grid points in x and y, a chunk of SCC columns and a run of up to SZC planes, and
+// marches through its planes in z: the current plane of the tile with a one-point halo in x
+// and y sits in LDS (the x and y neighbours and the centre are read from there), the previous
+// plane's centres stay in registers, and the next plane's tile and halo are loaded into
+// registers while the current plane is computed, then written to LDS. Thread t owns the
+// 16-byte piece q = t mod TPP of the chunk at the points t / TPP + PPS s of the tile (point
+// = y SX + x). The seven terms are those of k_spmm_stencil in the same order with the same
+// zero weights outside the grid, so both kernels return the same bits. Grid: (PP / SCC)
+// chunks fastest, then x tiles, y tiles, runs of planes.
+constexpr int SX = 32, SY = 8, SCC = 16, SZC = 32;
+constexpr int SHX = SX + 2, SHY = SY + 2, SNH = 2 * SX + 2 * SY;  // halo points: no corners
+
+// Halo point h of a tile -> its tile coordinates (-1 or SX / SY on the border).
+__device__ __forceinline__ void march_halo_xy(int h, int& lx, int& ly) {
+  if (h < SX) { lx = h; ly = -1; }
+  else if (h < 2 * SX) { lx = h - SX; ly = SY; }
+  else if (h < 2 * SX + SY) { lx = -1; ly = h - 2 * SX; }
+  else { lx = SX; ly = h - 2 * SX - SY; }
+}
+
+inline int64_t march_grid(int PP, const int32_t* dims) {
+  return (int64_t)(PP / SCC) * ((dims[0] + SX - 1) / SX) * ((dims[1] + SY - 1) / SY) * ((dims[2] + SZC - 1) / SZC);
+}
+
+template <typename T, int PP, bool AXPY>
+__global__ __launch_bounds__(WG) void k_spmm_march(int32_t nx, int32_t ny, int32_t nz, const T* __restrict__ diag,
+                                                   T off, const T* __restrict__ W0, const T* __restrict__ W1,
+                                                   T* __restrict__ Z, const Scalars* __restrict__ sc, int mode,
+                                                   const T* __restrict__ V, double alpha, double beta, double gamma) {
+  if (!AXPY && spmm_skip(sc, mode)) return;
+  const T* W = (!AXPY && mode == 1 && (sc->k & 1)) ? W1 : W0;
+  typedef typename std::conditional<sizeof(T) == 8, d2, f4>::type V16;
+  constexpr int E = 16 / (int)sizeof(T);         // elements per piece
+  constexpr int TPP = SCC / E;                   // pieces of a point's chunk
+  constexpr int PPS = WG / TPP;                  // points per pass of the workgroup
+  constexpr int NS = SX * SY / PPS;              // points per thread
+  constexpr int NCC = PP / SCC;
+  constexpr int HQ = (SNH * TPP + WG - 1) / WG;  // halo pieces per thread
+  static_assert(PP % SCC == 0 && (SX * SY) % PPS == 0, "tile shape");
+  __shared__ V16 L[SHX * SHY * TPP];
+  const int tx = (nx + SX - 1) / SX, ty = (ny + SY - 1) / SY;
+  int b = blockIdx.x;
+  const int cc = b % NCC;
+  b /= NCC;
+  const int bx = b % tx;
+  b /= tx;
+  const int by = b % ty;
+  const int z0 = (b / ty) * SZC;
+  if (z0 >= nz) return;  // the whole workgroup, before any barrier
+  const int z1 = z0 + SZC < nz ? z0 + SZC : nz;
+  const int x0 = bx * SX, y0 = by * SY, c0 = cc * SCC;
+  const int q = threadIdx.x % TPP, p0 = threadIdx.x / TPP;
+  const int64_t plane = (int64_t)nx * ny;
+  const V16 zero = {};
+  auto piece = [&](const T* base, int gx, int gy, int z, int qq) -> const V16* {
+    return reinterpret_cast<const V16*>(base + ((int64_t)z * plane + (int64_t)gy * nx + gx) * PP + c0) + qq;
+  };
+  auto load_centres = [&](int z, V16* ctr) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int pt = p0 + PPS * s, gx = x0 + pt % SX, gy = y0 + pt / SX;
+      ctr[s] = (gx < nx && gy < ny) ? gld(piece(W, gx, gy, z, q)) : zero;
+    }
+  };
+  auto load_halo = [&](int z, V16* hl) {
+#pragma unroll
+    for (int hh = 0; hh < HQ; ++hh) {
+      const int idx = threadIdx.x + WG * hh;
+      hl[hh] = zero;
+      if (idx < SNH * TPP) {
+        int lx, ly;
+        march_halo_xy(idx / TPP, lx, ly);
+        const int gx = x0 + lx, gy = y0 + ly;
+        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) hl[hh] = gld(piece(W, gx, gy, z, idx % TPP));
+      }
+    }
+  };
+  auto store_lds = [&](const V16* ctr, const V16* hl) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int pt = p0 + PPS * s;
+      L[((pt / SX + 1) * SHX + pt % SX + 1) * TPP + q] = ctr[s];
+    }
+#pragma unroll
+    for (int hh = 0; hh < HQ; ++hh) {
+      const int idx = threadIdx.x + WG * hh;
+      if (idx < SNH * TPP) {
+        int lx, ly;
+        march_halo_xy(idx / TPP, lx, ly);
+        L[((ly + 1) * SHX + lx + 1) * TPP + idx % TPP] = hl[hh];
+      }
+    }
+  };
+  V16 prv[NS], nxt[NS], hal[HQ];
+  if (z0 > 0) load_centres(z0 - 1, prv);
+  else {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) prv[s] = zero;
+  }
+  load_centres(z0, nxt);
+  load_halo(z0, hal);
+  store_lds(nxt, hal);
+  __syncthreads();
+  for (int z = z0; z < z1; ++z) {
+    // the next plane: its centres (the z + 1 terms) and, inside the run, its halo
+    if (z + 1 < nz) load_centres(z + 1, nxt);
+    else {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) nxt[s] = zero;
+    }
+    if (z + 1 < z1) load_halo(z + 1, hal);
+    const T vzm = z > 0 ? off : T(0), vzp = z + 1 < nz ? off : T(0);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int pt = p0 + PPS * s, lx = pt % SX, ly = pt / SX, gx = x0 + lx, gy = y0 + ly;
+      if (gx >= nx || gy >= ny) continue;
+      const int c = ((ly + 1) * SHX + lx + 1) * TPP + q;
+      const V16 wym = L[c - SHX * TPP], wxm = L[c - TPP], wc = L[c], wxp = L[c + TPP], wyp = L[c + SHX * TPP];
+      const T vym = gy > 0 ? off : T(0), vxm = gx > 0 ? off : T(0);
+      const T vxp = gx + 1 < nx ? off : T(0), vyp = gy + 1 < ny ? off : T(0);
+      const int64_t row = (int64_t)z * plane + (int64_t)gy * nx + gx;
+      const T dg = diag[row];
+      V16 acc;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        T a = T(0);
+        a += vzm * prv[s][e];
+        a += vym * wym[e];
+        a += vxm * wxm[e];
+        a += dg * wc[e];
+        a += vxp * wxp[e];
+        a += vyp * wyp[e];
+        a += vzp * nxt[s][e];
+        acc[e] = a;
+      }
+      const int64_t o = row * PP + c0 + E * q;
+      if constexpr (AXPY) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          double zz = alpha * (double)acc[e] + beta * (double)wc[e];
+          if (V) zz += gamma * (double)gld(V + o + e);
+          acc[e] = (T)zz;
+        }
+      }
+      gst(reinterpret_cast<V16*>(Z + o), acc);
+      prv[s] = wc;
+    }
+    __syncthreads();  // every thread is done with plane z in LDS
+    if (z + 1 < z1) {
+      store_lds(nxt, hal);
+      __syncthreads();
+    }
+  }
+}
+
 // Diagonal of a stencil operator, scaled: out[r] = scale (d + (dv ? dv[r] : 0)).
 template <typename T>
 __global__ void k_stencil_diag(int64_t n, double d, const double* __restrict__ dv, double scale, T* __restrict__ out) {
@@ -1155,9 +1314,16 @@ void Kernels<T, PP>::spmm_axpy(hipStream_t st, int64_t n, const int32_t* rowptr,
   k_spmm_axpy<T, PP><<<dim3((unsigned)grid), dim3(WG), 0, st>>>(n, rowptr, colind, vals, W, V, Z, alpha, beta, gamma,
                                                                plane_tiles);
 }
+// Grids with at least SY rows in y march through their planes (k_spmm_march); lines use
+// the row-tile kernel.
 template <typename T, int PP>
 void Kernels<T, PP>::spmm_stencil(hipStream_t st, int64_t n, const int32_t* dims, const T* diag, double off,
                                   const T* W0, const T* W1, T* Z, const Scalars* sc, int mode, int64_t plane_tiles) {
+  if (dims[1] >= SY) {
+    k_spmm_march<T, PP, false><<<dim3((unsigned)march_grid(PP, dims)), dim3(WG), 0, st>>>(
+        dims[0], dims[1], dims[2], diag, (T)off, W0, W1, Z, sc, mode, nullptr, 1.0, 0.0, 0.0);
+    return;
+  }
   const int64_t grid = spmm_grid((n + TR - 1) / TR, plane_tiles);
   k_spmm_stencil<T, PP, false><<<dim3((unsigned)grid), dim3(WG), 0, st>>>(
       n, dims[0], dims[1], dims[2], diag, (T)off, W0, W1, Z, sc, mode, plane_tiles, nullptr, 1.0, 0.0, 0.0);
@@ -1166,6 +1332,11 @@ template <typename T, int PP>
 void Kernels<T, PP>::spmm_stencil_axpy(hipStream_t st, int64_t n, const int32_t* dims, const T* diag, double off,
                                        const T* W, const T* V, T* Z, double alpha, double beta, double gamma,
                                        int64_t plane_tiles) {
+  if (dims[1] >= SY) {
+    k_spmm_march<T, PP, true><<<dim3((unsigned)march_grid(PP, dims)), dim3(WG), 0, st>>>(
+        dims[0], dims[1], dims[2], diag, (T)off, W, W, Z, nullptr, 0, V, alpha, beta, gamma);
+    return;
+  }
   const int64_t grid = spmm_grid((n + TR - 1) / TR, plane_tiles);
   k_spmm_stencil<T, PP, true><<<dim3((unsigned)grid), dim3(WG), 0, st>>>(
       n, dims[0], dims[1], dims[2], diag, (T)off, W, W, Z, nullptr, 0, plane_tiles, V, alpha, beta, gamma);

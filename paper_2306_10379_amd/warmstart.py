@@ -17,20 +17,21 @@ import numpy as np
 from . import fno, gsi, inputs
 
 
-def potential_problems(count: int, seed: int, N: int, wells: int = 8):
-    """count operators H = -Laplacian + V on an N x N grid, V a sum of `wells` Gaussian
-    wells (depth U(-20, 0), width U(0.02, 0.2), centre U([0,1]^2)); returns (mats, V) with V
-    the potentials at the grid nodes, (count, N*N)."""
+def potential_problems(count: int, seed: int, N: int, wells: int = 8, start: int = 0):
+    """Operators start .. start+count-1 of the seeded family H = -Laplacian + V on an N x N
+    grid, V a sum of `wells` Gaussian wells (depth U(-20, 0), width U(0.02, 0.2), centre
+    U([0,1]^2)); returns (mats, V) with V the potentials at the grid nodes, (count, N*N)."""
     mats, V = [], []
-    for i in range(count):
+    for i in range(start, start + count):
         W = inputs.random_wells(seed * 100_000 + i, count=wells)
         mats.append(inputs.schrodinger_2d(N, W))
         V.append(W.sample(N))
     return mats, np.stack(V)
 
 
-def random_starts(mats, p: int, seed: int):
-    return [inputs.start_block(A.n, p, seed * 100_000 + 50_000 + i) for i, A in enumerate(mats)]
+def random_starts(mats, p: int, seed: int, offset: int = 0):
+    """Seeded random start blocks of problems offset, offset+1, ... (the family's indices)."""
+    return [inputs.start_block(A.n, p, seed * 100_000 + 50_000 + offset + i) for i, A in enumerate(mats)]
 
 
 def solve_batch(mats, p: int, X0s, tol: float, precision: str = "mixed", max_iter: int = 60000):
@@ -169,28 +170,38 @@ def run_experiment(N=256, p=32, ntrain=512, ntest=64, modes=24, width=20, layers
     out = {"grid": N, "p": p, "train": ntrain, "test": ntest, "tol": tol, "train_tol": train_tol,
            "network": {"modes": modes, "width": width, "layers": layers,
                        "weights": "bf16 (fp32 master)" if bf16_weights else "fp32"}}
-    log(f"building {ntrain + ntest} problems on {N} x {N} grids")
-    t0 = time.perf_counter()
-    mats, V = potential_problems(ntrain + ntest, seed, N)
-    out["build_problems_s"] = round(time.perf_counter() - t0, 2)
-    X0r = random_starts(mats, p, seed)
-    prior = prior_blocks(N, p, ntrain + ntest)
-    Vd = torch.as_tensor(V, dtype=torch.float32, device="cuda")
+    # the training problems are built chunk by chunk (operators and start blocks are not kept)
+    Vd = torch.empty((ntrain + ntest, N * N), dtype=torch.float32, device="cuda")
     Xd = torch.empty((ntrain, N * N, p), dtype=torch.float32, device="cuda")
-    it_tr, st_tr, dt_tr = [], [], 0.0
+    it_tr, st_tr, dt_tr, t_build = [], [], 0.0, 0.0
     for s0 in range(0, ntrain, chunk):
         s1 = min(ntrain, s0 + chunk)
-        X, it, st, dt = solve_batch(mats[s0:s1], p, X0r[s0:s1], train_tol)
+        tb = time.perf_counter()
+        mats_c, V_c = potential_problems(s1 - s0, seed, N, start=s0)
+        X0_c = random_starts(mats_c, p, seed, offset=s0)
+        Vd[s0:s1].copy_(torch.as_tensor(V_c, dtype=torch.float32))
+        t_build += time.perf_counter() - tb
+        X, it, st, dt = solve_batch(mats_c, p, X0_c, train_tol)
         for i, x in enumerate(X):
             Xd[s0 + i].copy_(x)
-        del X
+        del X, mats_c, X0_c
         it_tr.append(it)
         st_tr.append(st)
         dt_tr += dt
         log(f"training solves {s0}..{s1 - 1}: {dt:.1f} s, mean iterations {it.mean():.0f}")
     it_tr, st_tr = np.concatenate(it_tr), np.concatenate(st_tr)
-    out["train_solves"] = {"s": round(dt_tr, 2), "iters_mean": float(it_tr.mean()), "converged": int((st_tr == 1).sum())}
-    log(f"training solves: {dt_tr:.1f} s, mean iterations {it_tr.mean():.0f}")
+    tb = time.perf_counter()
+    mats_t, V_t = potential_problems(ntest, seed, N, start=ntrain)
+    X0_t = random_starts(mats_t, p, seed, offset=ntrain)
+    Vd[ntrain:].copy_(torch.as_tensor(V_t, dtype=torch.float32))
+    t_build += time.perf_counter() - tb
+    mats = [None] * ntrain + mats_t  # indices of the family; training operators are gone
+    X0r = [None] * ntrain + X0_t
+    prior = prior_blocks(N, p, ntrain + ntest)
+    out["build_problems_s"] = round(t_build, 2)
+    out["train_solves"] = {"s": round(dt_tr, 2), "iters_mean": float(it_tr.mean()), "converged": int((st_tr == 1).sum()),
+                           "tol": train_tol}
+    log(f"training solves: {dt_tr:.1f} s, mean iterations {it_tr.mean():.0f}; problems built in {t_build:.1f} s")
     log("held-out problems from random starts")
     Xtd = torch.empty((ntest, N * N, p), dtype=torch.float32, device="cuda")
     it_r, dt_r = [], 0.0

@@ -25,7 +25,11 @@ def _csr_of(S):
     return A, M
 
 
-@pytest.mark.parametrize("dims,p", [((20, 17, 13), 8), ((33, 9, 1), 64), ((70, 1, 1), 5), ((16, 16, 40), 32)])
+# grids with >= 8 rows in y take the plane-marching kernel (tiles of 32 x 8 points, runs of 32
+# planes): ragged tiles in x and y, one to three runs of planes, a run of one plane; lines
+# (ny < 8) take the row-tile kernel
+@pytest.mark.parametrize("dims,p", [((20, 17, 13), 8), ((33, 9, 1), 64), ((70, 1, 1), 5), ((16, 16, 40), 32),
+                                    ((45, 23, 70), 64), ((7, 8, 2), 1), ((33, 8, 33), 17), ((40, 5, 3), 30)])
 def test_stencil_spmm_equals_csr_spmm_and_operator(dims, p):
     gsi = _gsi()
     nx, ny, nz = dims

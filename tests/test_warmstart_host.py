@@ -26,3 +26,17 @@ def test_random_starts_are_seeded_and_distinct():
     assert all(np.array_equal(x, y) for x, y in zip(a, b))
     assert a[0].shape == (64, 4) and not np.allclose(a[0], a[1])
     assert not np.allclose(a[0], inputs.start_block(64, 4, 9))
+
+
+def test_chunked_generation_reproduces_the_family():
+    """Problems and start blocks built chunk by chunk (start / offset) are those of the whole
+    family built at once."""
+    mats, V = warmstart.potential_problems(5, seed=3, N=8)
+    X0 = warmstart.random_starts(mats, 4, seed=3)
+    mats_c, V_c = warmstart.potential_problems(3, seed=3, N=8, start=2)
+    X0_c = warmstart.random_starts(mats_c, 4, seed=3, offset=2)
+    assert np.array_equal(V_c, V[2:])
+    for a, b in zip(mats_c, mats[2:]):
+        assert np.array_equal(a.vals, b.vals) and np.array_equal(a.colind, b.colind)
+    for a, b in zip(X0_c, X0[2:]):
+        assert np.array_equal(a, b)
