@@ -187,7 +187,28 @@ def oracle_small_leg(args, gsi, inputs, torch):
                       f"rho <= {args.tol:g}; times scaled by {512 / len(sample):g} to the batch",
           "oracle_s_scaled": round(to * 512 / len(sample), 2), "plain_gpu_s_scaled": round(tg * 512 / len(sample), 2)}
     log(f"oracle C4 sample: {c4}")
-    return {"c1": c1, "c4_sample": c4, "cpu_model": model, "logical_cpus_available": avail}
+    # the warm-start family's operator (256 x 256, 8 wells, p = 32 smallest): the oracle's
+    # time per iteration over a bounded run, extrapolated to the plain GPU solve's iterations
+    from paper_2306_10379_amd import warmstart
+    Aw, _ = warmstart.potential_problems(1, seed=1, N=256, start=2048)
+    X0w = warmstart.random_starts(Aw, 32, seed=1, offset=2048)[0]
+    k5 = 40
+    t0 = time.perf_counter()
+    O.rcg(Aw[0], X0w, tol=0.0, which=-1, max_iter=k5)
+    to5 = time.perf_counter() - t0
+    s = gsi.Solver(Aw[0], X0w, 32, which=-1, tol=args.tol, max_iter=60000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, it5 = s.solve()
+    torch.cuda.synchronize()
+    tg5 = time.perf_counter() - t0
+    s.close()
+    c5 = {"workload": f"2D Schroedinger 256x256, 8 wells (warm-start family, problem 2048), p=32 smallest, "
+                      f"rho <= {args.tol:g}, random X0",
+          "oracle_s_per_iter": round(to5 / k5, 4), "oracle_iters_timed": k5,
+          "oracle_s_extrapolated": round(to5 / k5 * it5, 1), "gpu_plain_fp64_s": round(tg5, 3), "gpu_iters": int(it5)}
+    log(f"oracle C5 problem: {c5}")
+    return {"c1": c1, "c4_sample": c4, "c5_problem": c5, "cpu_model": model, "logical_cpus_available": avail}
 
 
 def laplacian3d_top(N, count):
@@ -272,6 +293,7 @@ def stencil_leg(args, gsi, torch, X0, t_csr, it_csr, spmm_csr_us, csr):
     return {"s": round(value, 4), "iters": iters, "same_iters_as_csr": iters == it_csr,
             "speedup_vs_csr": round(t_csr / value, 3), "spmm_us": round(avg * 1e6, 1),
             "spmm_csr_us": round(spmm_csr_us, 1), "spmm_GBps": round(nbytes / avg / 1e9, 1),
+            "spmm_hbm_frac": round(nbytes / avg / 1e9 / HBM_PEAK_GBS, 4), "spmm_kernel": "k_spmm_march",
             "spmm_bytes": nbytes, "recompute_choice": choice}
 
 
@@ -483,7 +505,7 @@ def cpu_info():
 # Extra legs in the order they run while the wall-clock budget lasts, with the estimate of
 # their cost in units of one headline float64 solve (t64) plus fixed seconds.
 LEG_COST = {"mixed": (3.2, 5.0), "stencil": (2.2, 10.0), "paper_fd3d": (0.0, 12.0), "si": (0.7, 10.0),
-            "tracking": (0.0, 12.0), "hermitian": (0.0, 8.0), "batched": (0.0, 120.0), "oracle_small": (0.0, 110.0),
+            "tracking": (0.0, 12.0), "hermitian": (0.0, 8.0), "batched": (0.0, 120.0), "oracle_small": (0.0, 130.0),
             "rsd": (0.0, 100.0)}
 DEFAULT_LEGS = ["mixed", "stencil", "paper_fd3d", "si", "tracking", "hermitian", "oracle_small", "batched", "rsd"]
 # key of each leg's result in the JSON line
@@ -507,7 +529,7 @@ def warm_leg(args, log):
     from paper_2306_10379_amd import warmstart
     return warmstart.run_experiment(
         N=256, p=32, ntrain=args.warm_train, ntest=args.warm_test, epochs=30, batch=16, lr=3e-3, tol=args.tol,
-        nsingle=3, chunk=args.warm_chunk, chunk_test=args.warm_chunk, compare_prior=False, warm_max_iter=20000,
+        nsingle=3, chunk=args.warm_chunk, chunk_test=args.warm_chunk_test, compare_prior=False, warm_max_iter=20000,
         log=log, bf16_weights=not args.warm_fp32, train_tol=args.warm_train_tol)
 
 
@@ -561,7 +583,8 @@ def main():
     ap.add_argument("--warm-train-tol", type=float, default=1e-6,
                     help="tolerance of the training-target solves (the held-out solves use --tol)")
     ap.add_argument("--warm-fp32", action="store_true", help="float32 network weights (default: bfloat16 + fp32 master)")
-    ap.add_argument("--warm-chunk", type=int, default=128, help="problems per batched solve of the warm leg")
+    ap.add_argument("--warm-chunk", type=int, default=128, help="problems per batched training-target solve")
+    ap.add_argument("--warm-chunk-test", type=int, default=64, help="problems per batched held-out solve")
     ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--plain-sample", type=int, default=32,
                     help="problems of the batch solved one by one on the plain float64 path")
@@ -688,6 +711,14 @@ def main():
         torch.cuda.synchronize()
         rsd_fixed = {"iterations": int(it_r), "ms_per_iteration": round(1e3 * (time.perf_counter() - t0) / it_r, 4),
                      "rcg_ms_per_iteration": round(1e3 * float(np.mean(t64)) / it64, 4)}
+    # the device's own streaming rates (copy, read, write of 2 GiB), the ceiling the
+    # kernels' HBM rates are compared with beside the published peak
+    sr = gsi.stream_rates(1 << 31, 10)
+    ceiling = {"copy_GBps": round(sr["copy"], 1), "read_GBps": round(sr["read"], 1), "write_GBps": round(sr["write"], 1),
+               "how": "gsi_stream_rates: 16-byte grid-stride copy / read / write of 2 GiB, 10 launches each, HIP events"}
+    for r in (roof, spmm_roof):
+        r["vs_copy_rate"] = round(r["achieved"] / ceiling["copy_GBps"], 4)
+    log(f"stream ceiling: {ceiling}")
     log(f"headline done after {elapsed():.0f} s")
 
     cpu = None
@@ -724,6 +755,7 @@ def main():
         "pass_share": {k: round(v[0] / total_ms, 4) for k, v in pt.items() if total_ms > 0},
         "pass_timing": f"HIP events around every launch of {args.pass_iters} iterations from X0 (direct launches)",
         "rsd_fixed_300": rsd_fixed,
+        "stream_ceiling": ceiling,
         **{key: None for key in LEG_KEY.values()},
         "random_sparse": None,
         "warm_start": None,

@@ -290,6 +290,17 @@ gsi_status gsi_orthonormalize(double* X, int64_t n, int32_t p, void* hip_stream)
  * streams or two host threads) race and must be serialized by the caller. Syncs. */
 gsi_status gsi_orthonormalize_noalloc(double* X, int64_t n, int32_t p, void* hip_stream);
 
+/* Measurement aid (no part of the method): the device's streaming rates with the access
+ * pattern of the solver's streaming passes (16-byte loads and stores per lane, grid-stride
+ * over contiguous memory), the ceiling the kernels' HBM rates are compared with next to the
+ * published peak. a and b: device buffers of `bytes` bytes each (16-byte aligned, bytes a
+ * multiple of 16), owned by the caller; a is only read, b is written (it ends equal to a).
+ * us (host, 3 doubles) receives the mean time per launch over `reps` launches after one
+ * untimed launch, timed with HIP events on hip_stream, of: us[0] copy a -> b (2 x bytes
+ * moved), us[1] read a, us[2] write b (run first). GSI_EINVAL for null or misaligned pointers
+ * or sizes, GSI_EDEVICE for a HIP error. Syncs. */
+gsi_status gsi_stream_rates(void* a, void* b, int64_t bytes, int32_t reps, double* us, void* hip_stream);
+
 void gsi_destroy(gsi_handle h);
 const char* gsi_status_str(gsi_status s);
 const char* gsi_last_error(gsi_handle h);

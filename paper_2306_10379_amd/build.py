@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgsi.so")
-SOURCES = ["gsi_kernels.hip", "gsi_small.hip", "gsi_host.hip", "gsi_batched.hip", "gsi_ortho.hip", "fno.hip"]
+SOURCES = ["gsi_kernels.hip", "gsi_small.hip", "gsi_host.hip", "gsi_batched.hip", "gsi_ortho.hip", "gsi_stream.hip", "fno.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # keep the compiler from forming packed FP32 instructions (see the build notes)

@@ -24,7 +24,7 @@ EXPORTS = [
     "gsi_set_x0", "gsi_set_values", "gsi_spmm", "gsi_spmm_lowp", "gsi_history", "gsi_counters", "gsi_pass_times", "gsi_destroy",
     "gsi_status_str", "gsi_last_error", "gsi_create_batched", "gsi_solve_batched", "gsi_batched_results",
     "gsi_batched_get_x", "gsi_batched_set_tuning", "gsi_batched_set_wait_limit", "gsi_batched_timeline", "gsi_batched_pass_times", "gsi_batched_last_error", "gsi_destroy_batched",
-    "gsi_orthonormalize", "gsi_orthonormalize_noalloc", "gsi_batched_set_shapes",
+    "gsi_orthonormalize", "gsi_orthonormalize_noalloc", "gsi_batched_set_shapes", "gsi_stream_rates",
 ]
 PASSES = ["grad", "dir", "spmm", "update", "reduce", "small", "linesearch", "refresh", "eig", "gram"]
 
@@ -151,6 +151,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     for name in ("gsi_orthonormalize", "gsi_orthonormalize_noalloc"):
         getattr(L, name).argtypes = [vp, i64, i32, vp]
         getattr(L, name).restype = ctypes.c_int
+    L.gsi_stream_rates.argtypes = [vp, vp, i64, i32, P(dbl), vp]
+    L.gsi_stream_rates.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -299,6 +301,25 @@ def gsi_pass_times(h, enable: int = -1):
 def gsi_destroy(h):
     if h is not None and h.value:
         load().gsi_destroy(h)
+
+
+def stream_rates(nbytes: int = 1 << 31, reps: int = 10, stream=None) -> dict:
+    """The device's copy, read and write rates (gsi_stream_rates) on two buffers of nbytes:
+    {"copy": GB/s of read + write, "read": GB/s, "write": GB/s, "us": [copy, read, write]}."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    us = (ctypes.c_double * 3)()
+    L = load()
+    st = ctypes.c_void_p(stream if stream is not None else torch.cuda.current_stream().cuda_stream)
+    s = L.gsi_stream_rates(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), int(a.numel() * 8),
+                           int(reps), us, st)
+    if s != GSI_OK:
+        raise GsiError(s, L.gsi_status_str(s).decode())
+    nb = a.numel() * 8
+    del a, b
+    return {"copy": 2 * nb / (us[0] * 1e-6) / 1e9, "read": nb / (us[1] * 1e-6) / 1e9,
+            "write": nb / (us[2] * 1e-6) / 1e9, "us": [us[0], us[1], us[2]], "bytes": nb}
 
 
 def orthonormalize(X, noalloc: bool = False, stream=None) -> int:
