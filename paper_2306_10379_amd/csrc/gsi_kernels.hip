@@ -305,9 +305,12 @@ __global__ __launch_bounds__(WG) void k_update(int64_t n, T* __restrict__ X, T* 
 // tile; spmm_tile deals the tiles to the XCDs (blockIdx.x mod 8) so that the rows a tile's
 // gathers reach stay in that XCD's L2: one contiguous slab per XCD, or, for a banded matrix,
 // one chunk of every plane of rows after the other. The tile's CSR structure is staged in
-// LDS first (csr_stage). A row is handled by LPR = PP / 4 lanes, each owning 4 consecutive
-// columns; the column indices and values of up to 8 nonzeros are read before the 8 gathers
-// are issued, so each lane has up to 8 independent loads in flight.
+// LDS first (csr_stage). A row is handled by LPR lanes, each owning the 16 bytes of
+// consecutive columns that one load moves (2 in float64, 4 in float32): a row of W is one
+// gather instruction's worth of lanes, and at 16 bytes per lane the kernel needs fewer
+// registers (more waves in flight) than with two loads per lane (777 -> 701 us at 128^3,
+// p = 64, float64). The column indices and values of up to 8 nonzeros are read before the
+// 8 gathers are issued, so each lane has up to 8 independent loads in flight.
 // mode 0: always run, W = W0. mode 1: the iteration's SpMM (skipped when the solve is done
 // or the step is null), W = P of the current iteration (W0/W1 by parity). mode 2: explicit
 // A X (runs only when requested).
@@ -373,10 +376,10 @@ __global__ __launch_bounds__(WG) void k_spmm(int64_t n, const int32_t* __restric
                                              const Scalars* __restrict__ sc, int mode, int64_t plane_tiles) {
   if (spmm_skip(sc, mode)) return;
   const T* W = (mode == 1 && (sc->k & 1)) ? W1 : W0;
-  constexpr int EPL = 4;
-  constexpr int LPR = PP / EPL;  // lanes per row
-  constexpr int RPB = WG / LPR;  // rows per block pass
-  constexpr int U = 8;           // nonzeros per batch
+  constexpr int EPL = 16 / (int)sizeof(T);  // columns per lane: one 16-byte gather per nonzero
+  constexpr int LPR = PP / EPL;             // lanes per row
+  constexpr int RPB = WG / LPR;             // rows per block pass
+  constexpr int U = 8;                      // nonzeros per batch
   const int64_t ntiles = (n + TR - 1) / TR;
   const int64_t t = spmm_tile(ntiles, plane_tiles);
   if (t >= ntiles) return;
@@ -388,12 +391,12 @@ __global__ __launch_bounds__(WG) void k_spmm(int64_t n, const int32_t* __restric
   const bool staged = csr_stage(s_rp, s_col, s_val, rowptr, colind, vals, r0, nrows);
   const int32_t base = s_rp[0];
   const int sub = threadIdx.x / LPR, lane = threadIdx.x % LPR;
-#pragma unroll
   for (int pass = 0; pass < TR / RPB; ++pass) {
     const int lr = pass * RPB + sub;
     if (lr >= nrows) continue;
     const int64_t row = r0 + lr;
-    T acc[EPL] = {T(0), T(0), T(0), T(0)};
+    typedef typename std::conditional<sizeof(T) == 8, d2, f4>::type V16;
+    V16 acc = {};
     const int32_t j0 = s_rp[lr], j1 = s_rp[lr + 1];
     for (int32_t j = j0; j < j1; j += U) {
       int32_t col[U];
@@ -409,31 +412,15 @@ __global__ __launch_bounds__(WG) void k_spmm(int64_t n, const int32_t* __restric
           v[u] = ok ? vals[j + u] : T(0);
         }
       }
-      T x[U][EPL];
+      V16 x[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const T* src = W + (int64_t)col[u] * PP + EPL * lane;
-        if constexpr (sizeof(T) == 8) {
-          const double2 q0 = *reinterpret_cast<const double2*>(src);
-          const double2 q1 = *reinterpret_cast<const double2*>(src + 2);
-          x[u][0] = q0.x; x[u][1] = q0.y; x[u][2] = q1.x; x[u][3] = q1.y;
-        } else {
-          const float4 q = *reinterpret_cast<const float4*>(src);
-          x[u][0] = q.x; x[u][1] = q.y; x[u][2] = q.z; x[u][3] = q.w;
-        }
-      }
+      for (int u = 0; u < U; ++u) x[u] = gld(reinterpret_cast<const V16*>(W + (int64_t)col[u] * PP + EPL * lane));
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
         for (int e = 0; e < EPL; ++e) acc[e] += v[u] * x[u][e];
     }
-    T* zr = Z + row * PP + EPL * lane;
-    if constexpr (sizeof(T) == 8) {
-      *reinterpret_cast<double2*>(zr) = make_double2(acc[0], acc[1]);
-      *reinterpret_cast<double2*>(zr + 2) = make_double2(acc[2], acc[3]);
-    } else {
-      *reinterpret_cast<float4*>(zr) = make_float4(acc[0], acc[1], acc[2], acc[3]);
-    }
+    gst(reinterpret_cast<V16*>(Z + row * PP + EPL * lane), acc);
   }
 }
 
@@ -571,7 +558,8 @@ __global__ __launch_bounds__(WG) void k_spmm_axpy(int64_t n, const int32_t* __re
                                                   const int32_t* __restrict__ colind, const T* __restrict__ vals,
                                                   const T* __restrict__ W, const T* __restrict__ V, T* __restrict__ Z,
                                                   double alpha, double beta, double gamma, int64_t plane_tiles) {
-  constexpr int EPL = 4;
+  typedef typename std::conditional<sizeof(T) == 8, d2, f4>::type V16;
+  constexpr int EPL = 16 / (int)sizeof(T);  // one 16-byte gather per nonzero per lane
   constexpr int LPR = PP / EPL;
   constexpr int RPB = WG / LPR;
   constexpr int U = 8;
@@ -586,12 +574,11 @@ __global__ __launch_bounds__(WG) void k_spmm_axpy(int64_t n, const int32_t* __re
   const bool staged = csr_stage(s_rp, s_col, s_val, rowptr, colind, vals, r0, nrows);
   const int32_t base = s_rp[0];
   const int sub = threadIdx.x / LPR, lane = threadIdx.x % LPR;
-#pragma unroll
   for (int pass = 0; pass < TR / RPB; ++pass) {
     const int lr = pass * RPB + sub;
     if (lr >= nrows) continue;
     const int64_t row = r0 + lr;
-    T acc[EPL] = {T(0), T(0), T(0), T(0)};
+    V16 acc = {};
     const int32_t j0 = s_rp[lr], j1 = s_rp[lr + 1];
     for (int32_t j = j0; j < j1; j += U) {
       int32_t col[U];
@@ -607,23 +594,26 @@ __global__ __launch_bounds__(WG) void k_spmm_axpy(int64_t n, const int32_t* __re
           v[u] = ok ? vals[j + u] : T(0);
         }
       }
-      T x[U][EPL];
+      V16 x[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int e = 0; e < EPL; ++e) x[u][e] = gld(W + (int64_t)col[u] * PP + EPL * lane + e);
+      for (int u = 0; u < U; ++u) x[u] = gld(reinterpret_cast<const V16*>(W + (int64_t)col[u] * PP + EPL * lane));
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
         for (int e = 0; e < EPL; ++e) acc[e] += v[u] * x[u][e];
     }
     const int64_t o = row * PP + EPL * lane;
+    const V16 wo = gld(reinterpret_cast<const V16*>(W + o));
+    V16 vo = {};
+    if (V) vo = gld(reinterpret_cast<const V16*>(V + o));
+    V16 zo;
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
-      double z = alpha * (double)acc[e] + beta * (double)gld(W + o + e);
-      if (V) z += gamma * (double)gld(V + o + e);
-      gst(Z + o + e, (T)z);
+      double z = alpha * (double)acc[e] + beta * (double)wo[e];
+      if (V) z += gamma * (double)vo[e];
+      zo[e] = (T)z;
     }
+    gst(reinterpret_cast<V16*>(Z + o), zo);
   }
 }
 
