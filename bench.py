@@ -597,8 +597,8 @@ def main():
     ap.add_argument("--profile-precision", choices=["fp64", "fp32", "bf16"], default="fp64")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only (every GPU box here has one); "
-                                   "--gpus must be 1"}))
+        print(json.dumps({"error": "the solver runs on one GPU; a multi-GPU run is not provided "
+                                   "(--gpus must be 1)"}))
         sys.exit(2)
     legs = [] if args.legs.strip() in ("", "none") else [x.strip() for x in args.legs.split(",")]
     for x in legs:

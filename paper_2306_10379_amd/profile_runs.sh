@@ -37,6 +37,7 @@ step "$O/st_fetch" 120 --pmc FETCH_SIZE -d "$O/st_fetch" -o f -- $B --profile-st
 step "$O/st_write" 120 --pmc WRITE_SIZE -d "$O/st_write" -o w -- $B --profile-steps 3 --profile-matrix stencil || exit 1
 step "$O/c4_trace" 400 --kernel-trace --stats -d "$O/c4_trace" -o c4 -- $B --legs-only --legs batched --steps 1 --warmup 0 || exit 1
 step "$O/fno_trace" 300 --kernel-trace --stats -d "$O/fno_trace" -o fno -- python3 -m pytest $R/tests/test_gpu_fno.py -q -m gpu -p no:cacheprovider || exit 1
+step "$O/warm_trace" 400 --kernel-trace --stats -d "$O/warm_trace" -o warm -- $B --legs-only --legs none --warm --no-cpu --warm-train 128 --warm-test 32 --warm-chunk 128 --warm-chunk-test 32 || exit 1
 cd "$R"
 S="python3 -m paper_2306_10379_amd.profsum"
 C="bash paper_2306_10379_amd/profile_runs.sh (rocprofv3"
@@ -47,5 +48,6 @@ $S traffic "$(db "$O/c3_fetch")" "$(db "$O/c3_write")" "$C --pmc FETCH_SIZE / WR
 $S traffic "$(db "$O/st_fetch")" "$(db "$O/st_write")" "$C --pmc FETCH_SIZE / WRITE_SIZE -- $B --profile-steps 3 --profile-matrix stencil)" profiles/traffic_laplace3d_128_p64_fp64_stencil.json > /dev/null
 $S trace "$(db "$O/c4_trace")" "$C --kernel-trace --stats -- $B --legs-only --legs batched --steps 1 --warmup 0)" > profiles/kernels_schrodinger_batch512.md
 $S trace "$(db "$O/fno_trace")" "$C --kernel-trace --stats -- python3 -m pytest tests/test_gpu_fno.py)" > profiles/kernels_warmstart_network.md
+$S trace "$(db "$O/warm_trace")" "$C --kernel-trace --stats -- $B --legs-only --legs none --warm --no-cpu --warm-train 128 --warm-test 32 --warm-chunk 128 --warm-chunk-test 32)" > profiles/kernels_warmstart_c5_bf16_small.md
 cp profiles/*.md profiles/*.json "$K/" 2>/dev/null
 echo "summaries written"
