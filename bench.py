@@ -715,7 +715,7 @@ def main():
     # kernels' HBM rates are compared with beside the published peak
     sr = gsi.stream_rates(1 << 31, 10)
     ceiling = {"copy_GBps": round(sr["copy"], 1), "read_GBps": round(sr["read"], 1), "write_GBps": round(sr["write"], 1),
-               "how": "gsi_stream_rates: 16-byte grid-stride copy / read / write of 2 GiB, 10 launches each, HIP events"}
+               "how": "gsi_stream_rates: 16-byte grid-stride copy / read / write of 2 GiB (non-temporal stores), 10 launches each, HIP events"}
     for r in (roof, spmm_roof):
         r["vs_copy_rate"] = round(r["achieved"] / ceiling["copy_GBps"], 4)
     log(f"stream ceiling: {ceiling}")

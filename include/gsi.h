@@ -132,19 +132,25 @@ typedef struct {
   int32_t check_symmetric; /* 1: gsi_create also verifies that A equals its transpose (every
                               stored a_ij has a stored a_ji of the same value; GSI_EINVAL
                               otherwise); 0: not checked (the methods assume it, Sec. 2) */
+  uint64_t x0_seed;     /* seed of the start block drawn on the device when X0 == NULL */
 } gsi_options;
 
 /* Fill *opt with defaults: p=8, which=+1, RCG, FP64, recursion, no restart, max_iter=10000,
  * tol=1e-8, switch_tol=1e-5, check_every=25, use_graph=1, explicit_c=0, stall_window=60,
- * cheb_degree=0, check_symmetric=0. */
+ * cheb_degree=0, check_symmetric=0, x0_seed=0. */
 void gsi_options_default(gsi_options* opt);
 
 /* Create a solver for A with options opt, starting block X0 (n x p float64, device; its
  * columns need not be orthonormal: the library orthonormalizes them by two passes of
- * Cholesky QR). X0 == NULL draws nothing and is an error (GSI_EINVAL): starting blocks
- * are always supplied by the caller. Validates sizes and CSR structure (monotone rowptr,
- * column indices in range). On success *h owns device copies of A and X0 and all
- * workspace; gsi_step / gsi_solve never allocate. Syncs. */
+ * Cholesky QR). X0 == NULL: the start block is drawn on the device, entries i.i.d. N(0,1)
+ * (the random start of the experiments, Sec. 6) from opt->x0_seed by a counter-based
+ * generator: entry e = i p + j of the row-major block is sqrt(-2 ln u1) cos(2 pi u2) (Box
+ * and Muller 1958) with u1, u2 = ((o >> 11) + 1/2) 2^-53 for the outputs o number 2e and
+ * 2e + 1 of SplitMix64 (Steele, Lea and Flood 2014) started at state x0_seed, output k being
+ * mix(x0_seed + (k + 1) 0x9E3779B97F4A7C15), mix(z): z ^= z >> 30, z *= 0xBF58476D1CE4E5B9,
+ * z ^= z >> 27, z *= 0x94D049BB133111EB, z ^= z >> 31 (mod 2^64). Validates sizes and CSR
+ * structure (monotone rowptr, column indices in range). On success *h owns device copies of
+ * A and X0 and all workspace; gsi_step / gsi_solve never allocate. Syncs. */
 gsi_status gsi_create(gsi_handle* h, const gsi_csr* A, const gsi_options* opt, const double* X0,
                       void* hip_stream);
 
@@ -291,8 +297,8 @@ gsi_status gsi_orthonormalize(double* X, int64_t n, int32_t p, void* hip_stream)
 gsi_status gsi_orthonormalize_noalloc(double* X, int64_t n, int32_t p, void* hip_stream);
 
 /* Measurement aid (no part of the method): the device's streaming rates with the access
- * pattern of the solver's streaming passes (16-byte loads and stores per lane, grid-stride
- * over contiguous memory), the ceiling the kernels' HBM rates are compared with next to the
+ * pattern of the solver's streaming passes (16-byte loads and non-temporal stores per lane,
+ * grid-stride over contiguous memory), the ceiling the kernels' HBM rates are compared with next to the
  * published peak. a and b: device buffers of `bytes` bytes each (16-byte aligned, bytes a
  * multiple of 16), owned by the caller; a is only read, b is written (it ends equal to a).
  * us (host, 3 doubles) receives the mean time per launch over `reps` launches after one

@@ -543,3 +543,37 @@ def rcg_hermitian(A, X0, tol: float = 1e-10, max_iter: int = 10000, method: str 
     res.X = X @ U
     res.theta = w if which > 0 else -w
     return res
+
+
+# ---------------------------------------------------------------- seeded random start block
+
+_GOLDEN = 0x9E3779B97F4A7C15
+_M64 = (1 << 64) - 1
+
+
+def splitmix64(seed: int, k):
+    """Output number k (0, 1, ...; scalar or integer array) of SplitMix64 started at state
+    `seed` (Steele, Lea and Flood, "Fast splittable pseudorandom number generators", 2014):
+    the state advances by the golden-ratio increment before each output, and the output is
+    the state passed through the variant-13 mixing function (xor-shift 30, multiply,
+    xor-shift 27, multiply, xor-shift 31), all modulo 2^64."""
+    k = np.asarray(k, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed & _M64) + (k + np.uint64(1)) * np.uint64(_GOLDEN)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def seeded_start_block(n: int, p: int, seed: int) -> np.ndarray:
+    """The random start block X0 (n x p, entries i.i.d. N(0,1): the random starts of the
+    experiments, Sec. 6) that the library draws on the device when it is given no X0:
+    entry e = i p + j takes the first Box-Muller normal (Box and Muller 1958)
+    sqrt(-2 ln u1) cos(2 pi u2) of the uniforms u = (floor(o / 2^11) + 1/2) 2^-53 of the
+    SplitMix64 outputs o number 2e and 2e + 1. Not orthonormalized (the solver does that)."""
+    e = np.arange(n * p, dtype=np.uint64)
+    o1 = splitmix64(seed, 2 * e)
+    o2 = splitmix64(seed, 2 * e + np.uint64(1))
+    u1 = ((o1 >> np.uint64(11)).astype(np.float64) + 0.5) * 2.0 ** -53
+    u2 = ((o2 >> np.uint64(11)).astype(np.float64) + 0.5) * 2.0 ** -53
+    return (np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)).reshape(n, p)

@@ -33,6 +33,25 @@ constexpr int MAXP = 64;
 // columns stay zero.
 int padded_width(int p) { return p <= 16 ? 16 : (p <= 32 ? 32 : 64); }
 
+// The seeded start block of gsi_create with X0 == NULL (the generator is stated in gsi.h):
+// SplitMix64 as a counter-based generator (output k is the mixing function of
+// seed + (k + 1) golden-ratio increments; Steele, Lea and Flood 2014) and the first
+// Box-Muller normal of each pair of its outputs.
+__device__ __forceinline__ uint64_t splitmix_out(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_seed_block(int64_t count, uint64_t seed, double* __restrict__ X) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x) {
+    const double u1 = ((double)(splitmix_out(seed, 2 * (uint64_t)e) >> 11) + 0.5) * 0x1.0p-53;
+    const double u2 = ((double)(splitmix_out(seed, 2 * (uint64_t)e + 1) >> 11) + 0.5) * 0x1.0p-53;
+    X[e] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925 * u2);
+  }
+}
+
 struct Dev {
   std::vector<void*> ptrs;
   hipError_t err = hipSuccess;
@@ -834,7 +853,6 @@ gsi_status create_impl(gsi_handle* out, const gsi_csr* A, const gsi_stencil* S, 
   if (opt->precision != GSI_FP64 && opt->precision != GSI_MIXED_FP32 && opt->precision != GSI_MIXED_BF16)
     return bail(GSI_EINVAL, "unknown precision");
   if (!(opt->tol >= 0.0) || opt->max_iter < 0) return bail(GSI_EINVAL, "bad tol or max_iter");
-  if (!X0) return bail(GSI_EINVAL, "X0 is required");
   h->n = n_op;
   h->nnz = A ? A->nnz : n_op;  // values held: the nonzeros, or the stencil's diagonal
   if (S) {
@@ -902,6 +920,25 @@ gsi_status create_impl(gsi_handle* out, const gsi_csr* A, const gsi_stencil* S, 
     launch_stencil_check(st, cb, h->n, h->sdims, S->diag, S->off, S->diag_vec, h->dvec, h->flags);
     (void)hipMemsetAsync(h->dvec + cb, 0, sizeof(double) * cb, st);
   }
+  // X0 == NULL: the seeded start block, drawn into a buffer released after the start
+  double* x0_drawn = nullptr;
+  if (!X0) {
+    if (hipMalloc(&x0_drawn, sizeof(double) * (size_t)h->n * h->p) != hipSuccess)
+      return bail(GSI_ENOMEM, "out of device memory for the start block");
+    hipLaunchKernelGGL(k_seed_block, dim3(2048), dim3(256), 0, st, h->n * (int64_t)h->p, (uint64_t)opt->x0_seed,
+                       x0_drawn);
+    X0 = x0_drawn;
+  }
+  struct FreeOnExit {
+    double* p;
+    hipStream_t s;
+    ~FreeOnExit() {
+      if (p) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(p);
+      }
+    }
+  } x0_guard{x0_drawn, st};
   launch_finite(st, h->n * (int64_t)h->p, X0, h->flags + 1);
   std::vector<double> pm(2 * cb);
   int fl[2] = {0, 0};

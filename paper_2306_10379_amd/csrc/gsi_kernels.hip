@@ -834,7 +834,7 @@ __global__ __launch_bounds__(WG) void k_spmm_march(int32_t nx, int32_t ny, int32
           acc[e] = (T)zz;
         }
       }
-      gst(reinterpret_cast<V16*>(Z + o), acc);
+      __builtin_nontemporal_store(acc, reinterpret_cast<V16*>(Z + o));  // not read again here
       prv[s] = wc;
     }
     __syncthreads();  // every thread is done with plane z in LDS

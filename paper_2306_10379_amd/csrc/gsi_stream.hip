@@ -11,20 +11,23 @@
 namespace gsi {
 namespace {
 
-// 8 workgroups of 256 threads per CU of the 256-CU device
+// Grids as measured fastest for each kind on the 256-CU device: 16384 workgroups of 256
+// threads for the copy and the write (non-temporal stores, as in the kernels whose outputs
+// are not read again by the same launch), 2048 for the read-only pass
 constexpr int SWG = 256;
-constexpr int SGRID = 2048;
+constexpr int SGRID = 16384;
+constexpr int SGRID_READ = 2048;
 
 __global__ __launch_bounds__(SWG) void k_stream_copy(int64_t count, const d2* __restrict__ src, d2* __restrict__ dst) {
   for (int64_t i = (int64_t)blockIdx.x * SWG + threadIdx.x; i < count; i += (int64_t)SGRID * SWG)
-    gst(dst + i, gld(src + i));
+    __builtin_nontemporal_store(gld(src + i), dst + i);
 }
 
 // The sum is stored only in the impossible case that it is NaN-free and equals a sentinel,
 // which keeps the loads without a write per thread.
 __global__ __launch_bounds__(SWG) void k_stream_read(int64_t count, const d2* __restrict__ src, double* __restrict__ sink) {
   double s = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * SWG + threadIdx.x; i < count; i += (int64_t)SGRID * SWG) {
+  for (int64_t i = (int64_t)blockIdx.x * SWG + threadIdx.x; i < count; i += (int64_t)SGRID_READ * SWG) {
     const d2 v = gld(src + i);
     s += v.x + v.y;
   }
@@ -33,7 +36,8 @@ __global__ __launch_bounds__(SWG) void k_stream_read(int64_t count, const d2* __
 
 __global__ __launch_bounds__(SWG) void k_stream_write(int64_t count, d2* __restrict__ dst, double value) {
   const d2 v = {value, value};
-  for (int64_t i = (int64_t)blockIdx.x * SWG + threadIdx.x; i < count; i += (int64_t)SGRID * SWG) gst(dst + i, v);
+  for (int64_t i = (int64_t)blockIdx.x * SWG + threadIdx.x; i < count; i += (int64_t)SGRID * SWG)
+    __builtin_nontemporal_store(v, dst + i);
 }
 
 }  // namespace
@@ -57,7 +61,7 @@ extern "C" gsi_status gsi_stream_rates(void* a, void* b, int64_t bytes, int32_t 
       if (kind == 0)
         k_stream_copy<<<SGRID, SWG, 0, st>>>(count, reinterpret_cast<const d2*>(a), reinterpret_cast<d2*>(b));
       else if (kind == 1)
-        k_stream_read<<<SGRID, SWG, 0, st>>>(count, reinterpret_cast<const d2*>(a), reinterpret_cast<double*>(b));
+        k_stream_read<<<SGRID_READ, SWG, 0, st>>>(count, reinterpret_cast<const d2*>(a), reinterpret_cast<double*>(b));
       else
         k_stream_write<<<SGRID, SWG, 0, st>>>(count, reinterpret_cast<d2*>(b), 1.0);
     };

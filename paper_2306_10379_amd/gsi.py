@@ -66,7 +66,8 @@ class GsiOptions(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("switch_tol", ctypes.c_double),
                 ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("explicit_c", ctypes.c_int32),
                 ("stall_window", ctypes.c_int32), ("cheb_degree", ctypes.c_int32), ("cheb_lo", ctypes.c_double),
-                ("cheb_hi", ctypes.c_double), ("cheb_top", ctypes.c_double), ("check_symmetric", ctypes.c_int32)]
+                ("cheb_hi", ctypes.c_double), ("cheb_top", ctypes.c_double), ("check_symmetric", ctypes.c_int32),
+                ("x0_seed", ctypes.c_uint64)]
 
 
 _lib = None
@@ -190,16 +191,19 @@ def gsi_create(rowptr, colind, vals, n: int, X0, opt: GsiOptions, stream=None):
     L = load()
     for name, t, dt in (("rowptr", rowptr, torch.int32), ("colind", colind, torch.int32),
                         ("vals", vals, torch.float64), ("X0", X0, torch.float64)):
+        if t is None and name == "X0":
+            continue  # drawn on the device from opt.x0_seed
         if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
             raise TypeError(f"{name} must be a contiguous {dt} device tensor")
     _need_shape("rowptr", rowptr, (int(n) + 1,))
     _need_shape("vals", vals, (colind.numel(),))
-    if 1 <= opt.p <= 64 and int(n) >= 1:  # the library rejects other sizes before reading X0
+    if X0 is not None and 1 <= opt.p <= 64 and int(n) >= 1:  # the library rejects other sizes first
         _need_shape("X0", X0, (int(n), int(opt.p)))
     csr = GsiCsr(n=int(n), nnz=int(colind.numel()), rowptr=_dptr(rowptr), colind=_dptr(colind), vals=_dptr(vals))
     h = ctypes.c_void_p()
     st = ctypes.c_void_p(stream if stream is not None else torch.cuda.current_stream().cuda_stream)
-    s = L.gsi_create(ctypes.byref(h), ctypes.byref(csr), ctypes.byref(opt), ctypes.c_void_p(_dptr(X0)), st)
+    s = L.gsi_create(ctypes.byref(h), ctypes.byref(csr), ctypes.byref(opt),
+                     ctypes.c_void_p(_dptr(X0) if X0 is not None else None), st)
     if s != GSI_OK:
         msg = L.gsi_last_error(h).decode() if h.value else L.gsi_status_str(s).decode()
         if h.value:
@@ -212,17 +216,18 @@ def gsi_create_stencil(S: Stencil, dvec, X0, opt: GsiOptions, stream=None):
     """Create a handle for a matrix-free stencil; dvec: float64 device tensor of n values or None."""
     import torch
     L = load()
-    if not X0.is_cuda or X0.dtype != torch.float64 or not X0.is_contiguous():
+    if X0 is not None and (not X0.is_cuda or X0.dtype != torch.float64 or not X0.is_contiguous()):
         raise TypeError("X0 must be a contiguous float64 device tensor")
     if dvec is not None and (not dvec.is_cuda or dvec.dtype != torch.float64 or dvec.numel() != S.n):
         raise TypeError("diag_vec must be a float64 device tensor of n values")
-    if 1 <= opt.p <= 64 and min(int(S.nx), int(S.ny), int(S.nz)) >= 1:
+    if X0 is not None and 1 <= opt.p <= 64 and min(int(S.nx), int(S.ny), int(S.nz)) >= 1:
         _need_shape("X0", X0, (int(S.n), int(opt.p)))
     st_ = GsiStencil(nx=int(S.nx), ny=int(S.ny), nz=int(S.nz), diag=float(S.diag), off=float(S.off),
                      diag_vec=_dptr(dvec) if dvec is not None else None)
     h = ctypes.c_void_p()
     st = ctypes.c_void_p(stream if stream is not None else torch.cuda.current_stream().cuda_stream)
-    s = L.gsi_create_stencil(ctypes.byref(h), ctypes.byref(st_), ctypes.byref(opt), ctypes.c_void_p(_dptr(X0)), st)
+    s = L.gsi_create_stencil(ctypes.byref(h), ctypes.byref(st_), ctypes.byref(opt),
+                             ctypes.c_void_p(_dptr(X0) if X0 is not None else None), st)
     if s != GSI_OK:
         msg = L.gsi_last_error(h).decode() if h.value else L.gsi_status_str(s).decode()
         if h.value:
@@ -351,7 +356,8 @@ class Result:
 
 class Solver:
     """Convenience wrapper owning a handle. A is an inputs.CSR (host arrays, copied to the
-    device) or a tuple (rowptr, colind, vals, n) of device tensors."""
+    device) or a tuple (rowptr, colind, vals, n) of device tensors. X0 = None draws the start
+    block on the device from the option x0_seed (gsi_create)."""
 
     def __init__(self, A, X0, p: int, device="cuda", **opts):
         import torch
@@ -368,7 +374,7 @@ class Solver:
             colind = torch.as_tensor(np.asarray(A.colind, dtype=np.int32), device=device)
             vals = torch.as_tensor(np.asarray(A.vals, dtype=np.float64), device=device)
             n = A.n
-        if not torch.is_tensor(X0):
+        if X0 is not None and not torch.is_tensor(X0):
             X0 = torch.as_tensor(np.ascontiguousarray(X0, dtype=np.float64), device=device)
         self.n, self.p = int(n), int(p)
         method = opts.pop("method", "rcg")
@@ -390,7 +396,7 @@ class Solver:
             self.h = gsi_create_stencil(A, dvec, X0, self.opt)
         else:
             self.h = gsi_create(rowptr, colind, vals, self.n, X0, self.opt)
-        self.device = X0.device
+        self.device = X0.device if X0 is not None else torch.device(device)
 
     def step(self, n_iter: int):
         gsi_step(self.h, n_iter)

@@ -877,3 +877,31 @@ def test_stepping_cap_and_argument_errors():
             s.set_values(np.ones(len(A.vals) - 1))
     with pytest.raises(ValueError):
         gsi.Solver(A, np.zeros((A.n, p - 1)), p)
+
+
+def test_seeded_start_block_drawn_on_the_device():
+    """gsi_create with X0 = NULL draws the start block on the device from the option x0_seed
+    (SplitMix64 outputs through Box-Muller, as stated in gsi.h); the oracle's own
+    implementation of the same definition gives the same block: after the orthonormalization
+    both sides apply (two Cholesky QR passes) the bases agree element by element. The C1 solve
+    from the drawn block matches the oracle's solve from its block. The grid-stride draw is
+    exercised with a block of more entries than one pass of the draw covers."""
+    gsi = _gsi()
+    A = I.laplacian_2d(32)
+    p, seed = 8, 12345
+    Xo = O.seeded_start_block(A.n, p, seed)
+    print("seeded X0: C1", flush=True)
+    with gsi.Solver(A, None, p, x0_seed=seed, tol=1e-10, max_iter=20000) as s:
+        X = s.get_x().cpu().numpy()
+        assert np.max(np.abs(X - O.cholesky_qr2(Xo))) <= 1e-13
+        r = s.run()
+    ref = O.rcg(A, Xo, tol=1e-10, max_iter=20000)
+    assert r.status == 0
+    assert np.max(np.abs(r.ritz - ref.theta) / np.abs(ref.theta)) <= 1e-10
+    assert abs(r.iters - ref.iters) <= max(2, ref.iters // 20)
+    # 64,000 rows x 13 columns: 832,000 entries, above the 524,288 threads of one draw pass
+    B = I.laplacian_3d(40)
+    print("seeded X0: 40^3, p=13", flush=True)
+    with gsi.Solver(B, None, 13, x0_seed=2**63 + 5, max_iter=1) as s:
+        X = s.get_x().cpu().numpy()
+    assert np.max(np.abs(X - O.cholesky_qr2(O.seeded_start_block(B.n, 13, 2**63 + 5)))) <= 1e-13

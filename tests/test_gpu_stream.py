@@ -15,7 +15,9 @@ def test_stream_rates_move_the_bytes_they_time():
     from paper_2306_10379_amd import gsi
     L = gsi.load()
     g = np.random.default_rng(5)
-    for n in ((1 << 22) + 6, 3 * (1 << 20) + 2, 2):  # tails shorter than one grid sweep; one piece
+    # more pieces than one sweep of the grid (16384 x 256 threads) covers, a ragged count within
+    # one sweep, and a single 16-byte piece
+    for n in (9_000_002, 3 * (1 << 20) + 2, 2):
         src = torch.as_tensor(g.standard_normal(n), device="cuda")
         keep = src.clone()
         dst = torch.zeros_like(src)

@@ -546,3 +546,29 @@ def test_hermitian_rcg_dense_random_matches_library_eigh():
     assert r.converged
     assert np.allclose(r.theta, w[::-1][:p], atol=1e-10)
     assert O.principal_angles_complex(r.X, V[:, ::-1][:, :p]).max() < 1e-8
+
+
+def test_splitmix64_published_outputs():
+    """The first two outputs of SplitMix64 started at state 0, as published with the
+    generator (0xe220a8397b1dcdaf, 0x6e789e6aa1b965f4), and a restart from any state continues
+    the same stream (outputs are a function of seed + k increments)."""
+    out = O.splitmix64(0, np.arange(2))
+    assert [int(v) for v in out] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4]
+    g = 0x9E3779B97F4A7C15
+    assert int(O.splitmix64(5 * g, 0)) == int(O.splitmix64(0, 5))
+
+
+def test_seeded_start_block_is_standard_normal():
+    """Entries of the seeded start block: mean 0, variance 1, the standard normal distribution
+    (Kolmogorov-Smirnov), no correlation between neighbouring entries, distinct seeds give
+    distinct blocks, and a given seed repeats."""
+    import scipy.stats
+    X = O.seeded_start_block(50000, 4, 7)
+    x = X.ravel()
+    assert abs(x.mean()) < 0.01 and abs(x.var() - 1.0) < 0.01
+    assert scipy.stats.kstest(x, "norm").pvalue > 1e-3
+    assert abs(np.corrcoef(x[:-1], x[1:])[0, 1]) < 0.01
+    assert np.array_equal(X, O.seeded_start_block(50000, 4, 7))
+    assert not np.allclose(X[:100], O.seeded_start_block(50000, 4, 8)[:100])
+    # u1 = ((o >> 11) + 1/2) 2^-53 never reaches 0 or 1: the logarithm stays finite
+    assert np.isfinite(X).all()

@@ -126,6 +126,12 @@ SOURCE_MUTATIONS = {
     "Rayleigh-Ritz: residuals paired with the reversed Ritz values": (
         "rayleigh_ritz", "R = AX @ U - V * w", "R = AX @ U - V * w[::-1]", [T.test_rayleigh_ritz_on_an_invariant_subspace]),
     "Cholesky QR: a single pass": ("cholesky_qr2", "for _ in range(2):", "for _ in range(1):", [T.test_cholesky_qr2]),
+    "SplitMix64: second shift 28 instead of 27": (
+        "splitmix64", "z = (z ^ (z >> np.uint64(27)))", "z = (z ^ (z >> np.uint64(28)))",
+        [T.test_splitmix64_published_outputs]),
+    "Box-Muller: the factor 2 under the square root dropped": (
+        "seeded_start_block", "np.sqrt(-2.0 * np.log(u1))", "np.sqrt(-np.log(u1))",
+        [T.test_seeded_start_block_is_standard_normal]),
     "Cholesky QR: lower factor used as the upper one": (
         "cholesky_qr2", "R = np.linalg.cholesky(sym(X.T @ X)).T", "R = np.linalg.cholesky(sym(X.T @ X))",
         [T.test_cholesky_qr2]),
