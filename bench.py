@@ -253,6 +253,35 @@ def si_leg(args, gsi, torch, rowptr, colind, vals, n, X0, ritz_ref, rcg_spmm):
     return out
 
 
+def clean_cut_leg(args, gsi, torch, csr, X0full, N):
+    """The headline operator at the clean cut p = 60 (lambda_60 > lambda_61; p = 64 cuts the
+    triple lambda_64 = lambda_65 = lambda_66): one float64 and one float32-mixed solve to
+    --tol from the first 60 columns of the headline X0, each with its Ritz error against the
+    closed-form spectrum."""
+    p = 60
+    X0 = X0full[:, :p].contiguous()
+    lam, _ = laplacian3d_top(N, p)
+    res = {"p": p, "workload": f"3D Laplacian {N}^3, p={p} largest (a clean cut), rho <= {args.tol:g}"}
+    for prec in ("fp64", "mixed"):
+        with gsi.Solver(csr, X0, p, tol=args.tol, max_iter=20000, precision=prec, check_every=50,
+                        switch_tol=args.switch_tol) as s:
+            s.solve()  # warm-up (graph capture, first launches)
+            s.set_x0(X0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            status, iters = s.solve()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            ritz, _, rho, _ = s.residuals()
+            c = s.counters()
+        res[prec] = {"s": round(dt, 3), "iters": int(iters), "status": int(status), "rho": float(rho),
+                     "low_iters": int(c.get("low_iters", 0)),
+                     "ritz_rel_err_vs_closed_form": float(np.max(np.abs(ritz - lam) / np.abs(lam)))}
+        log(f"clean cut p={p} {prec}: {dt:.2f} s, {iters} iterations, status {status}")
+    res["speedup_mixed_vs_fp64"] = round(res["fp64"]["s"] / res["mixed"]["s"], 3)
+    return res
+
+
 def stencil_leg(args, gsi, torch, X0, t_csr, it_csr, spmm_csr_us, csr):
     """The headline solve with the operator applied matrix-free (gsi_create_stencil): same
     matrix, same arithmetic and order, so the same iterates; the SpMM reads the block once
@@ -504,14 +533,16 @@ def cpu_info():
 
 # Extra legs in the order they run while the wall-clock budget lasts, with the estimate of
 # their cost in units of one headline float64 solve (t64) plus fixed seconds.
-LEG_COST = {"mixed": (3.2, 5.0), "stencil": (2.2, 10.0), "paper_fd3d": (0.0, 12.0), "si": (0.7, 10.0),
+LEG_COST = {"mixed": (3.2, 5.0), "clean_cut": (1.2, 10.0), "stencil": (2.2, 10.0), "paper_fd3d": (0.0, 12.0),
+            "si": (0.7, 10.0),
             "tracking": (0.0, 12.0), "hermitian": (0.0, 8.0), "batched": (0.0, 120.0), "oracle_small": (0.0, 130.0),
             "rsd": (0.0, 100.0)}
-DEFAULT_LEGS = ["mixed", "stencil", "paper_fd3d", "si", "tracking", "hermitian", "oracle_small", "batched", "rsd"]
+DEFAULT_LEGS = ["mixed", "clean_cut", "stencil", "paper_fd3d", "si", "tracking", "hermitian", "oracle_small", "batched",
+                "rsd"]
 # key of each leg's result in the JSON line
 LEG_KEY = {"mixed": "mixed_fp32", "stencil": "matrix_free", "si": "si_chebyshev", "batched": "batched",
            "tracking": "tracking", "paper_fd3d": "paper_fd3d", "hermitian": "hermitian",
-           "oracle_small": "oracle_small_configs", "rsd": "rsd_gradient_variant"}
+           "oracle_small": "oracle_small_configs", "rsd": "rsd_gradient_variant", "clean_cut": "clean_cut_p60"}
 
 
 def leg_estimate(leg, t_solve):
@@ -804,6 +835,8 @@ def main():
                    "ritz_rel_err_vs_closed_form": float(np.max(np.abs(ritz32 - lam_closed) / np.abs(lam_closed))),
                    "ritz_rel_err_vs_fp64": float(np.max(np.abs(ritz32 - ritz64) / np.abs(ritz64))),
                    "rho": rho32}
+        elif leg == "clean_cut":
+            res = clean_cut_leg(args, gsi, torch, (rowptr, colind, vals, A.n), X0, N)
         elif leg == "stencil":
             res = stencil_leg(args, gsi, torch, X0, t_solve, it64, kern["spmm"]["avg_us"],
                               (rowptr, colind, vals, A.n))
