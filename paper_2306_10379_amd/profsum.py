@@ -49,14 +49,21 @@ def trace(db: str, command: str) -> str:
         else:
             live[short(name)].append(d)
     out = [f"# rocprofv3 kernel trace summary", "", f"command: `{command}`", "",
-           "| kernel | launches (>= 8 us) | total ms | avg us | min us | max us | short launches |",
-           "|---|---|---|---|---|---|---|"]
+           "Launches under 8 us are counted as short (a pass that returned at once). A kernel with "
+           "launch sites of different sizes (the iteration's SpMM and the explicit A X product, which "
+           "most iterations skip after dispatching its grid) has a mean over all its launches; the "
+           "last two columns are the count and mean of its full launches (at least half its longest).",
+           "",
+           "| kernel | launches (>= 8 us) | total ms | avg us | min us | max us | short launches | full launches "
+           "| full avg us |",
+           "|---|---|---|---|---|---|---|---|---|"]
     for k, v in sorted(live.items(), key=lambda kv: -sum(kv[1])):
+        full = [x for x in v if x >= 0.5 * max(v)]
         out.append(f"| {k} | {len(v)} | {sum(v) / 1e3:.1f} | {sum(v) / len(v):.1f} | {min(v):.1f} | {max(v):.1f} | "
-                   f"{idle.get(k, 0)} |")
+                   f"{idle.get(k, 0)} | {len(full)} | {sum(full) / len(full):.1f} |")
     for k, c in idle.items():
         if k not in live:
-            out.append(f"| {k} | 0 | 0 | - | - | - | {c} |")
+            out.append(f"| {k} | 0 | 0 | - | - | - | {c} | 0 | - |")
     return "\n".join(out) + "\n"
 
 
