@@ -35,16 +35,18 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def pass_bytes(n, p, nnz, s):
-    """Algorithmic HBM bytes per launch of each streaming kernel (element size s)."""
+def pass_bytes(n, p, nnz, s, fused=True):
+    """Algorithmic HBM bytes per launch of each streaming kernel (element size s). fused: the
+    float64 retraction pass also forms the next gradient (k_update_grad)."""
     blk = n * p * s
     a_bytes = nnz * (s + 4) + 4 * (n + 1)
     return {
-        "grad": 4 * blk,            # read X, Y, G_old; write G
+        "grad": 4 * blk,            # read X, Y, G_old; write G (the separate gradient pass)
         "dir": 4 * blk,             # read X, G, P_old; write P
         "spmm": a_bytes + 2 * blk,  # read A, P (once); write Z
         "gram": 3 * blk,            # read P, Z, Y (P^T A P, P^T A X)
-        "update": 6 * blk,          # read X, P, Y, Z; write X, Y
+        # read X, P, Y, Z; write X, Y; fused: also read G_old and write G
+        "update": (8 if fused else 6) * blk,
     }
 
 
@@ -709,19 +711,27 @@ def main():
     s64.pass_times(1)
     s64.step(args.pass_iters)
     pt = s64.pass_times(0)
-    nb = pass_bytes(A.n, p, A.nnz, 8)
+    # the float64 RCG solve forms each gradient in its retraction pass (k_update_grad); the
+    # separate gradient pass runs only for the first iterate and after explicit A X products,
+    # so its launches (most return at once) are left out of the per-kernel rates
+    fused = True
+    nb = pass_bytes(A.n, p, A.nnz, 8, fused=fused)
     kern = {}
-    for name in ("grad", "dir", "spmm", "gram", "update"):
+    for name in ("dir", "spmm", "gram", "update") if fused else ("grad", "dir", "spmm", "gram", "update"):
         ms, cnt = pt[name]
         if cnt:
             avg = ms / cnt
             kern[name] = {"avg_us": 1e3 * avg, "launches": cnt, "bytes": nb[name],
                           "GBps": nb[name] / (avg * 1e-3) / 1e9}
+    if fused:
+        kern["update"]["kernel"] = "k_update_grad"
     total_ms = sum(v[0] for v in pt.values())
     dom = max(kern, key=lambda k: pt[k][0])
     log("pass times (ms, launches): " + json.dumps(pt))
     PPd = 16 if p <= 16 else (32 if p <= 32 else 64)
     kname = "gram2" if (dom == "gram" and PPd == 64) else dom  # the two-Gram pass at 64 columns
+    if dom == "update" and fused:
+        kname = "update_grad"
     traffic = measured_traffic(f"gsi::k_{kname}<double, {PPd}",
                                f"traffic_laplace3d_{N}_p{p}_fp64.json")
     roof = {"bound": "hbm", "achieved": round(kern[dom]["GBps"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

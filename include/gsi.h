@@ -228,7 +228,9 @@ gsi_status gsi_set_x0(gsi_handle h, const double* X0);
 gsi_status gsi_set_values(gsi_handle h, const double* vals);
 
 /* Z = A_op W for the handle's operator (A, or -A when which = -1), W and Z n x p float64
- * device blocks. The same SpMM kernel the iteration uses. Asynchronous. */
+ * device blocks. The same SpMM kernel the iteration uses. It stages through the handle's
+ * gradient buffer: called between steps, the next step forms the gradient again and restarts
+ * the conjugate direction. Asynchronous. */
 gsi_status gsi_spmm(gsi_handle h, const double* W, double* Z);
 
 /* Z = A W (device, n x p float64 row-major in and out) in the handle's low-phase precision:
@@ -236,7 +238,7 @@ gsi_status gsi_spmm(gsi_handle h, const double* W, double* Z);
  * values and W rounded to bfloat16 (nearest even), float32 accumulation (GSI_MIXED_BF16);
  * A is the operator solved (negated for which = -1). GSI_EUNSUPPORTED for a float64
  * handle. For checking the low-precision SpMM; uses the handle's scratch blocks, so call it
- * between solves. */
+ * between solves (a following step restarts as after gsi_spmm). */
 gsi_status gsi_spmm_lowp(gsi_handle h, const double* W, double* Z);
 
 /* Per-iteration history, host arrays of length >= count (nullable): rho, phi, mu, beta_pr
@@ -258,7 +260,12 @@ enum {
   GSI_PASS_GRAD = 0,       /* gradient pass */
   GSI_PASS_DIR = 1,        /* direction pass */
   GSI_PASS_SPMM = 2,       /* block SpMM A P */
-  GSI_PASS_UPDATE = 3,     /* retraction pass */
+  GSI_PASS_UPDATE = 3,     /* retraction pass; for the float64 gradient-type iterations with C
+                              and W carried by the recursion (explicit_c = 0) the retraction
+                              pass also forms the next gradient and its sums, and GSI_PASS_GRAD
+                              then counts the gradient passes launched at the top of every
+                              iteration, which run only after an explicit A X, a void step or
+                              a restart of the state (the others return at once) */
   GSI_PASS_REDUCE = 4,     /* fixed-order reductions of partial sums */
   GSI_PASS_SMALL = 5,      /* p x p kernels other than the line search */
   GSI_PASS_LINESEARCH = 6, /* line-search diagonals, Get_Mu, M and the next C, W */

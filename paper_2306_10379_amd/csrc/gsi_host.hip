@@ -87,6 +87,9 @@ struct Engine {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   bool explicit_grams = false;
+  // the retraction pass also forms the next gradient (k_update_grad): the float64 engine of the
+  // gradient-type methods with C and W carried by the recursion
+  bool fused = false;
 
   bool alloc(Dev& d, int64_t n_, int p_, int nb_, int64_t nnz, bool bf16 = false) {
     n = n_; p = p_; PP = padded_width(p_); nb = nb_;
@@ -335,21 +338,28 @@ gsi_status init_state(gsi_ctx* h, Engine<T>& e, double tol, int max_iter, int hi
   return hip_check(h, hipGetLastError(), "init_state launch");
 }
 
-// One iteration's launch sequence.
+// One iteration's launch sequence. Unfused: gradient pass and its bookkeeping, direction
+// pass, eigendecomposition of P^T P (second stream) beside the SpMM and its Gram pass, line
+// search, retraction, explicit A X when asked for. Fused (e.fused): the gradient pass at the
+// top runs only when the gradient is not current (the first iteration, after an explicit A X, a
+// void step or a host-side change of the state); the retraction pass forms the next gradient
+// and its partial sums, whose bookkeeping runs at the end of the iteration.
 template <typename T>
 void launch_iteration(gsi_ctx* h, Engine<T>& e, double* hist) {
   const int recompute = h->rax;
+  const bool fused = e.fused;
+  const int gcond = fused ? GRAD_PENDING : GRAD_ALWAYS;
   dispatch_pp<T>(e.PP, [&](auto PPc) {
     constexpr int PP = decltype(PPc)::value;
     const int64_t P2 = (int64_t)PP * PP;
     {
       PassTimer t(h, GSI_PASS_GRAD);
-      Kernels<T, PP>::grad(h->st, e.nb, e.n, e.X, e.Y, e.G0, e.G1, e.small, e.sc, h->partials);
+      Kernels<T, PP>::grad(h->st, e.nb, e.n, e.X, e.Y, e.G0, e.G1, e.small, e.sc, h->partials, gcond);
     }
-    reduce(h, e.nb, P2 + 3, P2 + 2, e.sc, 3);
+    reduce(h, e.nb, P2 + 3, P2 + 2, e.sc, fused ? GRAD_PENDING : 3);
     {
       PassTimer t(h, GSI_PASS_SMALL);
-      Small::after_grad(h->st, PP, h->red, e.small, e.sc, hist);
+      Small::after_grad(h->st, PP, h->red, e.small, e.sc, hist, gcond);
     }
     {
       PassTimer t(h, GSI_PASS_DIR);
@@ -395,12 +405,24 @@ void launch_iteration(gsi_ctx* h, Engine<T>& e, double* hist) {
     if (!h->timing) (void)hipStreamWaitEvent(h->st, h->ev_join, 0);
     {
       PassTimer t(h, GSI_PASS_LINESEARCH);
-      Small::linesearch(h->st, PP, h->red, e.small, e.sc, hist, recompute);
+      Small::linesearch(h->st, PP, h->red, e.small, e.sc, hist, recompute, fused);
     }
     {
       PassTimer t(h, GSI_PASS_UPDATE);
-      Kernels<T, PP>::update(h->st, e.nb, e.n, e.X, e.Y, e.P0, e.P1, e.Z, e.small, e.sc, h->partials,
+      if (fused)
+        Kernels<T, PP>::update_grad(h->st, e.nb, e.n, e.X, e.Y, e.P0, e.P1, e.Z, e.G0, e.G1, e.small, e.sc,
+                                    h->partials);
+      else
+        Kernels<T, PP>::update(h->st, e.nb, e.n, e.X, e.Y, e.P0, e.P1, e.Z, e.small, e.sc, h->partials,
                                e.explicit_grams);
+    }
+    if (fused) {
+      // the new gradient's bookkeeping, when the retraction formed it (the partials of the
+      // explicit A X below go to other entries of the reduced vector: red is reused only
+      // after this reduction has been consumed)
+      reduce(h, e.nb, P2 + 3, P2 + 2, e.sc, GRAD_AFTER_FUSED);
+      PassTimer t(h, GSI_PASS_SMALL);
+      Small::after_grad(h->st, PP, h->red, e.small, e.sc, hist, GRAD_AFTER_FUSED);
     }
     if (e.explicit_grams) {
       reduce(h, e.nb, 2 * P2, 2 * P2, e.sc, 1);
@@ -517,6 +539,7 @@ gsi_status run_until_done(gsi_ctx* h, Engine<T>& e, double* hist, Scalars* out, 
       out->done = 0;
       out->stall_window = 0;
       out->restart_next = 1;
+      out->grad_ready = 0;  // the gradient of the new A X is formed at the top of the next iteration
       GSI_TRY(hip_check(h, hipMemcpyAsync(e.sc, out, sizeof(Scalars), hipMemcpyHostToDevice, h->st), "resume"));
       continue;
     }
@@ -532,6 +555,7 @@ gsi_status run_until_done(gsi_ctx* h, Engine<T>& e, double* hist, Scalars* out, 
         launch_set_sym(h->st, PP, h->red, e.small + S_C * PP * PP);
       });
       out->done = 0;
+      out->grad_ready = 0;
       GSI_TRY(hip_check(h, hipMemcpyAsync(e.sc, out, sizeof(Scalars), hipMemcpyHostToDevice, h->st), "resume"));
       continue;
     }
@@ -987,6 +1011,7 @@ gsi_status create_impl(gsi_handle* out, const gsi_csr* A, const gsi_stencil* S, 
   }
   h->e64.explicit_grams = opt->explicit_c != 0;
   h->e32.explicit_grams = opt->explicit_c != 0;
+  h->e64.fused = !h->e64.explicit_grams && (opt->method == GSI_RCG || opt->method == GSI_RSD);
   s = start(h, X0);
   if (s != GSI_OK) return bail(s, h->err);
   *out = h;
@@ -1175,6 +1200,9 @@ gsi_status gsi_residuals(gsi_handle h, double* ritz, double* col_res, double* rh
     GSI_TRY(hip_check(h, hipMemcpyAsync(&e.sc->done, &done, sizeof(int), hipMemcpyHostToDevice, h->st), "reset"));
     GSI_TRY(hip_check(h, hipMemcpyAsync(&e.sc->restart_next, &one, sizeof(int), hipMemcpyHostToDevice, h->st),
                       "reset"));
+    // the rotated basis has its own gradient, formed at the top of the next iteration
+    GSI_TRY(hip_check(h, hipMemcpyAsync(&e.sc->grad_ready, &done, sizeof(int), hipMemcpyHostToDevice, h->st),
+                      "reset"));
     dispatch_pp<double>(e.PP, [&](auto PPc) {
       constexpr int PP = decltype(PPc)::value;
       Kernels<double, PP>::gram(h->st, e.nb, e.n, e.X, e.X, e.Y, nullptr, e.sc, 0, h->partials);
@@ -1256,9 +1284,27 @@ gsi_status gsi_recompute_choice(gsi_handle h, int32_t* recompute_ax, double* ms_
   return GSI_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// A product staged through an engine's G0 between steps: the gradient of the next step is
+// formed again and its direction restarts (G0 may have held the current or the previous
+// gradient).
+template <typename T>
+void invalidate_gradient(gsi_ctx* h, Engine<T>& e) {
+  if (!e.sc) return;
+  static const int zero = 0, one = 1;
+  (void)hipMemcpyAsync(&e.sc->grad_ready, &zero, sizeof(int), hipMemcpyHostToDevice, h->st);
+  (void)hipMemcpyAsync(&e.sc->restart_next, &one, sizeof(int), hipMemcpyHostToDevice, h->st);
+}
+}  // namespace
+
+extern "C" {
+
 gsi_status gsi_spmm(gsi_handle h, const double* W, double* Z) {
   if (!h || !W || !Z) return GSI_EINVAL;
   Engine<double>& e = h->e64;
+  invalidate_gradient(h, e);
   // stage through the engine's Z / G0 buffers (padded layout)
   launch_pack<double>(h->st, h->n, h->p, h->PP, W, e.G0, 1.0);
   dispatch_pp<double>(e.PP, [&](auto PPc) {
@@ -1276,6 +1322,8 @@ gsi_status gsi_spmm_lowp(gsi_handle h, const double* W, double* Z) {
     return GSI_EUNSUPPORTED;
   }
   Engine<float>& e = h->e32;
+  invalidate_gradient(h, e);
+  invalidate_gradient(h, h->e64);
   const int64_t rows = (h->n + TR - 1) / TR * TR;
   dispatch_pp<float>(e.PP, [&](auto PPc) {
     constexpr int PP = decltype(PPc)::value;

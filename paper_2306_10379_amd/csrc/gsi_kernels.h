@@ -8,7 +8,15 @@
 
 namespace gsi {
 
-enum class Pass { Grad, Dir, Update, UpdateGrams, Spmm, SpmmPlain, Gram, Product };
+enum class Pass { Grad, Dir, Update, UpdateGrams, UpdateGrad, Spmm, SpmmPlain, Gram, Product };
+
+// When a gradient pass, its reduction and its bookkeeping (after_grad) run. ALWAYS: every
+// iteration (the unfused sequence). PENDING: at the top of an iteration of the fused sequence,
+// only when the gradient is not current (the solve's first iteration, after an explicit A X, a
+// void step or a host-side change of the state). AFTER_FUSED: at the end of an iteration of the
+// fused sequence, when its retraction pass formed the gradient (a step was taken and A X was
+// carried by the recursion).
+enum GradCond { GRAD_ALWAYS = 0, GRAD_PENDING = 4, GRAD_AFTER_FUSED = 5 };
 
 template <typename T, int PP>
 int lds_bytes(Pass pass);
@@ -18,13 +26,16 @@ template <typename T, int PP>
 struct Kernels {
   static hipError_t init();
   static void grad(hipStream_t st, int nb, int64_t n, const T* X, const T* Y, T* G0, T* G1, const double* small,
-                   const Scalars* sc, double* partials);
+                   const Scalars* sc, double* partials, int cond = GRAD_ALWAYS);
   // P16 / P32 (nullable): bfloat16 / float32 copy of P written beside it
   static void dir(hipStream_t st, int nb, int64_t n, const T* X, const T* G0, const T* G1, T* P0, T* P1,
                   const double* small, const Scalars* sc, double* partials, uint16_t* P16 = nullptr,
                   float* P32 = nullptr);
   static void update(hipStream_t st, int nb, int64_t n, T* X, T* Y, const T* P0, const T* P1, const T* Z,
                      const double* small, const Scalars* sc, double* partials, bool grams);
+  // the retraction fused with the next gradient (k_update_grad); partials as for grad
+  static void update_grad(hipStream_t st, int nb, int64_t n, T* X, T* Y, const T* P0, const T* P1, const T* Z,
+                          T* G0, T* G1, const double* small, const Scalars* sc, double* partials);
   // plane_tiles > 0: banded tile order (see spmm_tile in gsi_kernels.hip); 0: one slab per XCD
   static void spmm(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind, const T* vals,
                    const T* W0, const T* W1, T* Z, const Scalars* sc, int mode, int64_t plane_tiles = 0);
@@ -80,15 +91,18 @@ void launch_stencil_check(hipStream_t st, int nb, int64_t n, const int32_t* dims
 // scalars; `red` is the reduced partial-sum vector of the preceding pass.
 struct Small {
   static hipError_t init();
-  // after the gradient pass: rho, history, stop test, Polak-Ribiere beta, K + beta W
-  static void after_grad(hipStream_t st, int PP, const double* red, double* small, Scalars* sc, double* hist);
+  // after the gradient pass: rho, history, stop test, Polak-Ribiere beta, K + beta W; marks the
+  // gradient current (grad_ready). cond (GradCond): when it runs
+  static void after_grad(hipStream_t st, int PP, const double* red, double* small, Scalars* sc, double* hist,
+                         int cond = 0);
   // after the direction pass: S = P^T P, descent test
   static void after_dir(hipStream_t st, int PP, const double* red, double* small, Scalars* sc);
   // eigendecomposition of P^T P (warm-started); independent of the SpMM
   static void eig(hipStream_t st, int PP, double* small, Scalars* sc);
-  // after the SpMM: line-search diagonals, Get_Mu, M, next C and W
+  // after the SpMM: line-search diagonals, Get_Mu, M, next C and W (and M C_next for the fused
+  // retraction-gradient pass); marks the gradient stale (the step changes X, or is void)
   static void linesearch(hipStream_t st, int PP, const double* red, double* small, Scalars* sc, double* hist,
-                         int recompute_ax);
+                         int recompute_ax, bool want_mc = false);
   // after an update with Gram epilogue: C = sym(X^T Y), W = X^T P (explicit)
   static void after_update_grams(hipStream_t st, int PP, const double* red, double* small, Scalars* sc);
   // after an explicit A X: C = sym(X^T Y) (runs only when sc->refresh)

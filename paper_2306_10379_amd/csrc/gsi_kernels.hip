@@ -27,8 +27,9 @@ template <typename T, int PP>
 __global__ __launch_bounds__(WG) void k_grad(int64_t n, const T* __restrict__ X, const T* __restrict__ Y,
                                              T* __restrict__ G0, T* __restrict__ G1,
                                              const double* __restrict__ small, const Scalars* __restrict__ sc,
-                                             double* __restrict__ partials) {
+                                             double* __restrict__ partials, int cond) {
   if (sc->done) return;
+  if (cond == GRAD_PENDING && sc->grad_ready) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* sC = reinterpret_cast<T*>(lds_raw);
   T* sG = sC + PP * PP;
@@ -297,6 +298,150 @@ __global__ __launch_bounds__(WG) void k_update(int64_t n, T* __restrict__ X, T* 
     double* out = partials + (int64_t)blockIdx.x * (2 * PP * PP);
     gram_store<T, PP>(out, cacc);
     gram_store<T, PP>(out + PP * PP, wacc);
+  }
+}
+
+// The retraction pass fused with the next iteration's gradient pass. With a1 = X - mu P and
+// a2 = Y - mu Z (rows in the A-operand layout):
+//   X <- a1 M,  Y <- a2 M,  G <- X_new C_next - Y_new = a1 (M C_next) - a2 M,
+// where C_next is the line search's p x p recursion for X_new^T A X_new and M C_next is formed
+// there (small[S_MC]); and the gradient pass's partial sums of G: K = X_new^T G, <G, G>,
+// <G_old, G>, ||G||_inf (Sec. 3.1 eq. gradPhi; Sec. 5.2 eq. Xnew_P; Sec. 6.1 eq. save_matvec).
+// X_new and G are both in the D layout, where the four rows of register r of the 16 x 16
+// blocks are the contraction index of one MFMA step, so K accumulates without LDS: every wave
+// keeps all (PP/16)^2 blocks of its rows' K and the four waves' blocks are added in wave order
+// in LDS at the end. When the step asks for an explicit A X (refresh) only X is updated and the
+// gradient pass runs after the product; a void step or a finished solve returns at once. X and
+// Y come out bit for bit as from k_update; G differs from the separate pass's X_new C - Y_new
+// by rounding only (the product with C is taken before the rounding of X_new).
+template <typename T, int PP>
+__global__ __launch_bounds__(WG) void k_update_grad(int64_t n, T* __restrict__ X, T* __restrict__ Y,
+                                                    const T* __restrict__ P0, const T* __restrict__ P1,
+                                                    const T* __restrict__ Z, T* __restrict__ G0, T* __restrict__ G1,
+                                                    const double* __restrict__ small, const Scalars* __restrict__ sc,
+                                                    double* __restrict__ partials) {
+  if (sc->done || sc->null_step) return;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* sM = reinterpret_cast<T*>(lds_raw);
+  T* sMC = sM + PP * PP;
+  __shared__ double red[4 * 3];
+  const int par = (sc->k - 1) & 1;  // the step was accepted: k already counts it
+  const T* P = par ? P1 : P0;
+  const int gpar = sc->k & 1;       // G_k, in the gradient pass's buffer convention
+  T* G = gpar ? G1 : G0;
+  const T* Gold = gpar ? G0 : G1;
+  const T mu = (T)sc->mu;
+  const bool full = !sc->refresh;
+  load_matrix_lds<T, PP>(sM, small + S_M * PP * PP);
+  if (full) load_matrix_lds<T, PP>(sMC, small + S_MC * PP * PP);
+  __syncthreads();
+  const int w = threadIdx.x >> 6;
+  const int64_t ntiles = (n + TR - 1) / TR;
+  int64_t t0, t1;
+  tile_range(ntiles, t0, t1);
+  constexpr int NB = PP / 16;
+  typedef typename Vec4<T>::type V4;
+  V4 kacc[NB * NB];
+#pragma unroll
+  for (int q = 0; q < NB * NB; ++q) kacc[q] = V4{0, 0, 0, 0};
+  double gg = 0.0, gdot = 0.0, ginf = 0.0;
+  for (int64_t t = t0; t < t1; ++t) {
+    const int64_t row0 = t * TR + 16 * w;
+    T a1[PP / 4], a2[PP / 4], b[PP / 4];
+    load_al<T, PP>(X, row0, n, a1);
+    load_al<T, PP>(P, row0, n, b);
+#pragma unroll
+    for (int s = 0; s < PP / 4; ++s) a1[s] = a1[s] - mu * b[s];
+    V4 xacc[NB];
+    zero_acc<T, PP>(xacc);
+    if (full) {
+      load_al<T, PP>(Y, row0, n, a2);
+      load_al<T, PP>(Z, row0, n, b);
+#pragma unroll
+      for (int s = 0; s < PP / 4; ++s) a2[s] = a2[s] - mu * b[s];
+      V4 yacc[NB], gacc[NB];
+      zero_acc<T, PP>(yacc);
+      zero_acc<T, PP>(gacc);
+      product2<T, PP>(a1, a2, sM, xacc, yacc);
+      product<T, PP>(a1, sMC, gacc);
+      T xo[NB][4], yo[NB][4], g[NB][4];
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          xo[cb][r] = xacc[cb][r];
+          yo[cb][r] = yacc[cb][r];
+          g[cb][r] = gacc[cb][r] - yacc[cb][r];
+        }
+      store_rl<T, PP>(X, row0, n, xo);
+      store_rl<T, PP>(Y, row0, n, yo);
+      store_rl<T, PP>(G, row0, n, g);
+      double rs[4] = {0.0, 0.0, 0.0, 0.0};
+      T go[NB][4];
+      load_rl<T, PP>(Gold, row0, n, go);
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double gv = (double)g[cb][r];
+          gg += gv * gv;
+          rs[r] += fabs(gv);
+          gdot += (double)go[cb][r] * gv;
+        }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) ginf = fmax(ginf, group16_sum(rs[r]));
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+          for (int cb2 = 0; cb2 < NB; ++cb2) kacc[cb * NB + cb2] = mfma(xo[cb][r], g[cb2][r], kacc[cb * NB + cb2]);
+    } else {
+      product<T, PP>(a1, sM, xacc);
+      T xo[NB][4];
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) xo[cb][r] = xacc[cb][r];
+      store_rl<T, PP>(X, row0, n, xo);
+    }
+  }
+  if (!full) return;
+  // the waves' K blocks added in wave order in LDS (the factors are no longer needed; the
+  // dynamic LDS holds 2 PP^2 elements of T, at least PP^2 doubles)
+  double* sK = reinterpret_cast<double*>(lds_raw);
+  const int l = threadIdx.x & 63, lg = l >> 4, lc = l & 15;
+  __syncthreads();
+  for (int ww = 0; ww < 4; ++ww) {
+    if (w == ww) {
+#pragma unroll
+      for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+        for (int cb2 = 0; cb2 < NB; ++cb2)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int e = (16 * cb + rowof<T>(lg, r)) * PP + 16 * cb2 + lc;
+            sK[e] = (ww ? sK[e] : 0.0) + (double)kacc[cb * NB + cb2][r];
+          }
+    }
+    __syncthreads();
+  }
+  const int64_t nv = PP * PP + 3;
+  double* out = partials + (int64_t)blockIdx.x * nv;
+  for (int e = threadIdx.x; e < PP * PP; e += WG) out[e] = sK[e];
+  {
+    const double s0 = wave_sum(gg), s1 = wave_sum(gdot), s2 = wave_max(ginf);
+    if (l == 0) {
+      red[w * 3 + 0] = s0;
+      red[w * 3 + 1] = s1;
+      red[w * 3 + 2] = s2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      out[PP * PP + 0] = red[0] + red[3] + red[6] + red[9];
+      out[PP * PP + 1] = red[1] + red[4] + red[7] + red[10];
+      out[PP * PP + 2] = fmax(fmax(red[2], red[5]), fmax(red[8], red[11]));
+    }
   }
 }
 
@@ -1126,6 +1271,8 @@ __global__ __launch_bounds__(WG) void k_reduce(const double* __restrict__ partia
   if (cond == 1 && (sc->done || sc->null_step)) return;
   if (cond == 2 && (sc->done || sc->null_step || !sc->refresh)) return;
   if (cond == 3 && sc->done) return;
+  if (cond == GRAD_PENDING && (sc->done || sc->grad_ready)) return;
+  if (cond == GRAD_AFTER_FUSED && (sc->done || sc->null_step || sc->refresh || sc->grad_ready)) return;
   __shared__ double part[4][64];
   const int q = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int64_t v = (int64_t)blockIdx.x * 64 + l;
@@ -1260,6 +1407,7 @@ int lds_bytes(Pass pass) {
     case Pass::Dir: return m + tile;
     case Pass::Update: return m;
     case Pass::UpdateGrams: return m + 3 * tile;
+    case Pass::UpdateGrad: return 2 * m;
     case Pass::Spmm: return 0;
     case Pass::SpmmPlain: return 0;
     case Pass::Gram: return 0;
@@ -1279,6 +1427,7 @@ hipError_t set_lds_limits() {
   GSI_SET((k_dir<T, PP>), Pass::Dir)
   GSI_SET((k_update<T, PP, false>), Pass::Update)
   GSI_SET((k_update<T, PP, true>), Pass::UpdateGrams)
+  GSI_SET((k_update_grad<T, PP>), Pass::UpdateGrad)
   GSI_SET((k_product<T, PP>), Pass::Product)
   if constexpr (PP == 64) {
     if (e == hipSuccess)
@@ -1291,8 +1440,15 @@ hipError_t set_lds_limits() {
 
 template <typename T, int PP>
 void Kernels<T, PP>::grad(hipStream_t st, int nb, int64_t n, const T* X, const T* Y, T* G0, T* G1,
-                          const double* small, const Scalars* sc, double* partials) {
-  k_grad<T, PP><<<nb, WG, lds_bytes<T, PP>(Pass::Grad), st>>>(n, X, Y, G0, G1, small, sc, partials);
+                          const double* small, const Scalars* sc, double* partials, int cond) {
+  k_grad<T, PP><<<nb, WG, lds_bytes<T, PP>(Pass::Grad), st>>>(n, X, Y, G0, G1, small, sc, partials, cond);
+}
+template <typename T, int PP>
+void Kernels<T, PP>::update_grad(hipStream_t st, int nb, int64_t n, T* X, T* Y, const T* P0, const T* P1,
+                                 const T* Z, T* G0, T* G1, const double* small, const Scalars* sc,
+                                 double* partials) {
+  k_update_grad<T, PP><<<nb, WG, lds_bytes<T, PP>(Pass::UpdateGrad), st>>>(n, X, Y, P0, P1, Z, G0, G1, small, sc,
+                                                                          partials);
 }
 template <typename T, int PP>
 void Kernels<T, PP>::dir(hipStream_t st, int nb, int64_t n, const T* X, const T* G0, const T* G1, T* P0, T* P1,

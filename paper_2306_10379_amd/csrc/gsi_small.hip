@@ -17,8 +17,10 @@ namespace gsi {
 // ---------------------------------------------------------------- kernels
 
 __global__ __launch_bounds__(WG) void k_after_grad(int PP, const double* __restrict__ red, double* __restrict__ small,
-                                                   Scalars* __restrict__ sc, double* __restrict__ hist) {
+                                                   Scalars* __restrict__ sc, double* __restrict__ hist, int cond) {
   if (sc->done) return;
+  if (cond == GRAD_PENDING && sc->grad_ready) return;
+  if (cond == GRAD_AFTER_FUSED && (sc->null_step || sc->refresh || sc->grad_ready)) return;
   __shared__ double sbeta, sphi;
   // the scalars and the trace of C are read by all threads at once (one round trip) and the
   // sequential decisions below work on the LDS copy: dependent global reads one after the
@@ -84,6 +86,7 @@ __global__ __launch_bounds__(WG) void k_after_grad(int PP, const double* __restr
       if (k < lsc->hist_cap) hist[(int64_t)k * H_FIELDS + H_BETA] = beta;
     }
     sbeta = beta;
+    sc->grad_ready = 1;
   }
   __syncthreads();
   if (ls.done) return;
@@ -114,6 +117,7 @@ __global__ __launch_bounds__(WG) void k_after_dir(int PP, const double* __restri
         sc->null_step = 1;
         sc->restart_next = 1;
         sc->n_null += 1;
+        sc->grad_ready = 0;  // the next iteration forms the gradient again (and restarts)
       }
     }
   }
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(WG) void k_eig(double* __restrict__ small, Scalars*
 template <int PP>
 __global__ __launch_bounds__(WG) void k_linesearch(const double* __restrict__ red, double* __restrict__ small,
                                                    Scalars* __restrict__ sc, double* __restrict__ hist,
-                                                   int recompute_ax) {
+                                                   int recompute_ax, int want_mc) {
   if (sc->done || sc->null_step) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ Terms terms;
@@ -157,9 +161,10 @@ __global__ __launch_bounds__(WG) void k_linesearch(const double* __restrict__ re
   __syncthreads();
   const int p = ls.p;
   linesearch_dev<PP>(red, red + PP * PP, small, p, reinterpret_cast<double*>(lds_raw), terms, &smu, &sok, &sevals,
-                     &sbmax);
+                     &sbmax, want_mc != 0);
   if (threadIdx.x == 0) {
     sc->brent_evals = sevals;
+    sc->grad_ready = 0;  // X changes (or the step is void and the next iteration restarts)
     if (!sok) {
       if (ls.restart) {
         sc->done = 3;
@@ -357,8 +362,8 @@ hipError_t Small::init() {
   if (e == hipSuccess) e = init_pp<64>();
   return e;
 }
-void Small::after_grad(hipStream_t st, int PP, const double* red, double* small, Scalars* sc, double* hist) {
-  hipLaunchKernelGGL(k_after_grad, dim3(1), dim3(WG), 0, st, PP, red, small, sc, hist);
+void Small::after_grad(hipStream_t st, int PP, const double* red, double* small, Scalars* sc, double* hist, int cond) {
+  hipLaunchKernelGGL(k_after_grad, dim3(1), dim3(WG), 0, st, PP, red, small, sc, hist, cond);
 }
 void Small::after_dir(hipStream_t st, int PP, const double* red, double* small, Scalars* sc) {
   hipLaunchKernelGGL(k_after_dir, dim3(1), dim3(WG), 0, st, PP, red, small, sc);
@@ -371,11 +376,12 @@ void Small::eig(hipStream_t st, int PP, double* small, Scalars* sc) {
   }
 }
 void Small::linesearch(hipStream_t st, int PP, const double* red, double* small, Scalars* sc, double* hist,
-                       int recompute_ax) {
+                       int recompute_ax, bool want_mc) {
+  const int mc = want_mc ? 1 : 0;
   switch (PP) {
-    case 16: k_linesearch<16><<<1, WG, 4 * 16 * 16 * 8, st>>>(red, small, sc, hist, recompute_ax); break;
-    case 32: k_linesearch<32><<<1, WG, 4 * 32 * 32 * 8, st>>>(red, small, sc, hist, recompute_ax); break;
-    case 64: k_linesearch<64><<<1, WG, 4 * 64 * 64 * 8, st>>>(red, small, sc, hist, recompute_ax); break;
+    case 16: k_linesearch<16><<<1, WG, 4 * 16 * 16 * 8, st>>>(red, small, sc, hist, recompute_ax, mc); break;
+    case 32: k_linesearch<32><<<1, WG, 4 * 32 * 32 * 8, st>>>(red, small, sc, hist, recompute_ax, mc); break;
+    case 64: k_linesearch<64><<<1, WG, 4 * 64 * 64 * 8, st>>>(red, small, sc, hist, recompute_ax, mc); break;
   }
 }
 void Small::after_update_grams(hipStream_t st, int PP, const double* red, double* small, Scalars* sc) {

@@ -570,11 +570,13 @@ __device__ inline int eig_dev(double* small, int p, bool warm, double* lds, doub
 // Exact line search (Sec. 5.2, Algorithm 3, Sec. 6.1) from V, b (eig_dev), C = small[S_C],
 // S = small[S_S] and the Grams P^T A P (PZr) and P^T A X (PYr). On success (*sok = 1) it
 // writes mu (*smu), M = small[S_M], the next C and W (small[S_C], small[S_W]) and the largest
-// b (*sbmax). lds: 4 PP^2 doubles; terms, smu, sok, sevals, sbmax in shared memory. Whole
-// workgroup.
+// b (*sbmax), and with want_mc also M C_next = small[S_MC] (the right factor of the next
+// gradient, G = (X - mu P) M C_next - (Y - mu Z) M, for the fused retraction pass). lds: 4 PP^2
+// doubles; terms, smu, sok, sevals, sbmax in shared memory. Whole workgroup.
 template <int PP>
 __device__ inline void linesearch_dev(const double* PZr, const double* PYr, double* small, int p, double* lds,
-                                      Terms& terms, double* smu, int* sok, int* sevals, double* sbmax) {
+                                      Terms& terms, double* smu, int* sok, int* sevals, double* sbmax,
+                                      bool want_mc = false) {
   double* V = lds;
   double* Mc = V + PP * PP;
   double* T1 = Mc + PP * PP;
@@ -658,6 +660,10 @@ __device__ inline void linesearch_dev(const double* PZr, const double* PYr, doub
     C[e] = 0.5 * (T2[e] + T2[j * PP + i]);
   }
   __syncthreads();
+  if (want_mc) {
+    wg_mm<PP>(Mc, false, C, false, small + S_MC * PP * PP);
+    __syncthreads();
+  }
 }
 
 }  // namespace gsi

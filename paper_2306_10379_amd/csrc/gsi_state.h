@@ -35,7 +35,8 @@ struct Scalars {
   int32_t stall_window; // > 0: stop (done = 4) when rho has not halved for this many iterations
   double rho_best;      // smallest rho so far (halving checkpoints)
   int32_t k_best;
-  int32_t pad_;
+  int32_t grad_ready;    // G, its sums and the stop test are current for X (set by the gradient's
+                         // bookkeeping, cleared when X is about to change or a step is void)
 };
 
 // Offsets (in doubles) of the p x p matrices (stored PP x PP, row-major) in the small buffer.
@@ -49,6 +50,7 @@ enum {
   S_PY,      // P^T A X
   S_V,       // eigenvectors of P^T P (also kept as the next warm start)
   S_M,       // retraction factor V diag((1 + mu^2 b)^-1/2) V^T
+  S_MC,      // M C_next: the right factor of the next gradient in the fused retraction pass
   S_T1,      // temporaries
   S_T2,
   S_VEC,     // vectors of length PP: b (eigenvalues of P^T P), then scratch

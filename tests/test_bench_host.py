@@ -32,9 +32,11 @@ def test_pass_bytes_at_the_benchmark_size():
     n, p, N = 128 ** 3, 64, 128
     nnz = 7 * N ** 3 - 6 * N ** 2
     blk = n * p * 8
-    nb = b.pass_bytes(n, p, nnz, 8)
+    nb = b.pass_bytes(n, p, nnz, 8, fused=False)
     assert blk == 1 << 30
     assert nb["update"] == 6 * blk == 6_442_450_944     # X, P, Y, Z read; X, Y written
+    # the retraction pass that also forms the next gradient: G_old read, G written as well
+    assert b.pass_bytes(n, p, nnz, 8)["update"] == 8 * blk
     assert nb["grad"] == nb["dir"] == 4 * blk
     assert nb["gram"] == 3 * blk
     # CSR once (8-byte values, 4-byte indices, n + 1 row pointers), P once, Z once
