@@ -229,6 +229,74 @@ __device__ __forceinline__ void gram_store(double* __restrict__ out,
   }
 }
 
+// Symmetric Gram A^T A of the workgroup's LDS tile: only the blocks (ib, jb) with ib <= jb are
+// formed, dealt round-robin to the 4 waves (at PP = 64: 10 blocks, at most 3 per wave instead of
+// 4). A block and its mirror multiply the same pairs of elements in the same order, so writing
+// the mirror gives bit for bit what the full product gives.
+template <int PP>
+struct SymSplit {
+  static constexpr int NBK = PP / 16;
+  static constexpr int NBLK = NBK * (NBK + 1) / 2;
+  static constexpr int PER_WAVE = (NBLK + 3) / 4;
+};
+
+// Block (ib, jb), ib <= jb, of upper-triangle index blk (row by row).
+template <int PP>
+__device__ __forceinline__ void sym_block(int blk, int& ib, int& jb) {
+  ib = 0;
+#pragma unroll
+  for (int i = 0; i < PP / 16; ++i) {
+    const int cnt = PP / 16 - i;
+    if (blk >= cnt && ib == i) {
+      blk -= cnt;
+      ib = i + 1;
+    }
+  }
+  jb = ib + blk;
+}
+
+template <typename T, int PP>
+__device__ __forceinline__ void gram_tile_sym(const T* __restrict__ sA,
+                                              typename Vec4<T>::type (&acc)[SymSplit<PP>::PER_WAVE]) {
+  using SS = SymSplit<PP>;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+#pragma unroll
+  for (int q = 0; q < SS::PER_WAVE; ++q) {
+    const int blk = w + 4 * q;
+    if (blk < SS::NBLK) {
+      int ib, jb;
+      sym_block<PP>(blk, ib, jb);
+#pragma unroll 4
+      for (int s = 0; s < TR / 4; ++s) {
+        const int row = 4 * s + g;
+        acc[q] = mfma(sA[row * PP + 16 * ib + c], sA[row * PP + 16 * jb + c], acc[q]);
+      }
+    }
+  }
+}
+
+// Write a wave's blocks of a symmetric Gram and the mirrors of its off-diagonal blocks.
+template <typename T, int PP>
+__device__ __forceinline__ void gram_store_sym(double* __restrict__ out,
+                                               const typename Vec4<T>::type (&acc)[SymSplit<PP>::PER_WAVE]) {
+  using SS = SymSplit<PP>;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+#pragma unroll
+  for (int q = 0; q < SS::PER_WAVE; ++q) {
+    const int blk = w + 4 * q;
+    if (blk < SS::NBLK) {
+      int ib, jb;
+      sym_block<PP>(blk, ib, jb);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * ib + rowof<T>(g, r), j = 16 * jb + c;
+        out[i * PP + j] = (double)acc[q][r];
+        if (ib != jb) out[j * PP + i] = (double)acc[q][r];
+      }
+    }
+  }
+}
+
 // Store a wave's RL tile into the workgroup LDS tile (rows 16*wave ...).
 template <typename T, int PP>
 __device__ __forceinline__ void rl_to_lds(T* __restrict__ s, const T (&v)[PP / 16][4]) {

@@ -126,7 +126,8 @@ struct gsi_ctx {
   int p = 0, PP = 0, nb = 0;
   Dev dev;
   int32_t *rowptr = nullptr, *colind = nullptr;
-  double* partials = nullptr;  // nb * (2 PP^2 + 8)
+  int nb_gram = 0;              // workgroups of the iteration's two-Gram pass
+  double* partials = nullptr;  // max(nb, nb_gram) * (2 PP^2 + 8)
   double* red = nullptr;       // 2 PP^2 + 8
   double* hist = nullptr;      // (hist_cap) * H_FIELDS
   double* dvec = nullptr;      // device vector scratch (Ritz values etc.)
@@ -399,9 +400,9 @@ void launch_iteration(gsi_ctx* h, Engine<T>& e, double* hist) {
     }
     {
       PassTimer t(h, GSI_PASS_GRAM);
-      Kernels<T, PP>::gram(h->st, e.nb, e.n, e.P0, e.P1, e.Z, e.Y, e.sc, 1, h->partials);
+      Kernels<T, PP>::gram(h->st, h->nb_gram, e.n, e.P0, e.P1, e.Z, e.Y, e.sc, 1, h->partials);
     }
-    reduce(h, e.nb, 2 * P2, 2 * P2, e.sc, 1);
+    reduce(h, h->nb_gram, 2 * P2, 2 * P2, e.sc, 1);
     if (!h->timing) (void)hipStreamWaitEvent(h->st, h->ev_join, 0);
     {
       PassTimer t(h, GSI_PASS_LINESEARCH);
@@ -901,13 +902,17 @@ gsi_status create_impl(gsi_handle* out, const gsi_csr* A, const gsi_stencil* S, 
   // float64 passes at p = 64): more workgroups did not move the passes and only enlarge the
   // per-workgroup partial sums the reductions read (measured at n = 128^3, p = 64)
   h->nb = (int)(ntiles < 2 * (int64_t)ncu ? ntiles : 2 * (int64_t)ncu);
+  // the iteration's P^T A P / P^T A X pass on four workgroups per CU: alone it ran 835 -> 730 us
+  // (128^3, p = 64); inside the solve the pass itself stays near 0.70 ms but the retraction pass
+  // after it runs 1.78 -> 1.72 ms (solve 12.47 -> 12.34 s, two builds on one GPU, two solves each)
+  h->nb_gram = (int)(ntiles < 4 * (int64_t)ncu ? ntiles : 4 * (int64_t)ncu);
   h->hist_cap = opt->max_iter + 2;
   Dev& d = h->dev;
   if (A) {
     h->rowptr = d.alloc<int32_t>(h->n + 1);
     h->colind = d.alloc<int32_t>(h->nnz);
   }
-  h->partials = d.alloc<double>((size_t)h->nb * (2 * h->PP * h->PP + 8) + 4096);
+  h->partials = d.alloc<double>((size_t)(h->nb > h->nb_gram ? h->nb : h->nb_gram) * (2 * h->PP * h->PP + 8) + 4096);
   h->red = d.alloc<double>(2 * h->PP * h->PP + 8);
   h->hist = d.alloc<double>((size_t)h->hist_cap * H_FIELDS);
   h->dvec = d.alloc<double>(4 * MAXP + 4096);

@@ -131,7 +131,8 @@ __global__ __launch_bounds__(WG) void k_grad(int64_t n, const T* __restrict__ X,
 
 // ---------------------------------------------------------------- direction pass
 // P = (I - X X^T)(G + beta P_old) = G + beta P_old - X (K + beta W)   (Sec. 5.1, eq. Pnew,
-// projected onto the tangent space as in Algorithm 4), fused with <G, P> and S = P^T P.
+// projected onto the tangent space as in Algorithm 4), fused with <G, P> and S = P^T P (its
+// upper blocks formed, the lower ones mirrored).
 // Partials: S (PP*PP), <G,P>.
 template <typename T, int PP>
 __global__ __launch_bounds__(WG) void k_dir(int64_t n, const T* __restrict__ X, const T* __restrict__ G0,
@@ -156,8 +157,9 @@ __global__ __launch_bounds__(WG) void k_dir(int64_t n, const T* __restrict__ X, 
   const int64_t ntiles = (n + TR - 1) / TR;
   int64_t t0, t1;
   tile_range(ntiles, t0, t1);
-  typename Vec4<T>::type sacc[GramSplit<PP>::PER_WAVE];
-  gram_zero<T, PP>(sacc);
+  typename Vec4<T>::type sacc[SymSplit<PP>::PER_WAVE];
+#pragma unroll
+  for (int q = 0; q < SymSplit<PP>::PER_WAVE; ++q) sacc[q] = typename Vec4<T>::type{0, 0, 0, 0};
   double gp = 0.0;
   for (int64_t t = t0; t < t1; ++t) {
     const int64_t row0 = t * TR + 16 * w;
@@ -209,12 +211,12 @@ __global__ __launch_bounds__(WG) void k_dir(int64_t n, const T* __restrict__ X, 
       for (int r = 0; r < 4; ++r) gp += (double)g[cb][r] * (double)p[cb][r];
     rl_to_lds<T, PP>(sP, p);
     __syncthreads();
-    gram_tile<T, PP>(sP, sP, sacc);
+    gram_tile_sym<T, PP>(sP, sacc);
     __syncthreads();
   }
   const int64_t nv = PP * PP + 1;
   double* out = partials + (int64_t)blockIdx.x * nv;
-  gram_store<T, PP>(out, sacc);
+  gram_store_sym<T, PP>(out, sacc);
   const int l = threadIdx.x & 63;
   double s = wave_sum(gp);
   if (l == 0) red[w] = s;
@@ -355,6 +357,10 @@ __global__ __launch_bounds__(WG) void k_update_grad(int64_t n, T* __restrict__ X
     V4 xacc[NB];
     zero_acc<T, PP>(xacc);
     if (full) {
+      // G_old with the other operands: one wait per tile (a load issued after the stores
+      // would wait for them too)
+      T go[NB][4];
+      load_rl<T, PP>(Gold, row0, n, go);
       load_al<T, PP>(Y, row0, n, a2);
       load_al<T, PP>(Z, row0, n, b);
 #pragma unroll
@@ -377,8 +383,6 @@ __global__ __launch_bounds__(WG) void k_update_grad(int64_t n, T* __restrict__ X
       store_rl<T, PP>(Y, row0, n, yo);
       store_rl<T, PP>(G, row0, n, g);
       double rs[4] = {0.0, 0.0, 0.0, 0.0};
-      T go[NB][4];
-      load_rl<T, PP>(Gold, row0, n, go);
 #pragma unroll
       for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
