@@ -48,6 +48,46 @@ def test_spmm_matches_oracle_operator(n, p, seed):
     assert np.max(np.abs(Z - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref)))
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_product_between_steps_does_not_reach_the_iteration(precision):
+    """gsi_spmm (gsi_spmm_lowp on a mixed handle) between steps stages its operand in the
+    engine's gradient buffer, where the retraction pass may have left the next step's gradient:
+    the next step must form the gradient again (and restart the direction) rather than read the
+    staged operand. Two solves that make the product with different operands at the same point
+    therefore take the same steps bit for bit; each product is A W; both reach the closed-form
+    eigenvalues."""
+    gsi = _gsi()
+    A = I.laplacian_2d(32)
+    p = 8
+    lam = laplacian_spectrum(32, 32)[:p]
+    X0 = I.start_block(A.n, p, 5)
+    kw = {"switch_tol": 1e-5} if precision == "mixed" else {}
+    runs = []
+    for wseed in (6, 7):
+        print(f"product between steps: {precision}, operand seed {wseed}", flush=True)
+        W = I.start_block(A.n, p, wseed)
+        with gsi.Solver(A, X0, p, tol=1e-10, max_iter=5000, precision=precision, **kw) as s:
+            s.step(10)
+            Z = (s.spmm if precision == "fp64" else s.spmm_lowp)(dev(W)).cpu().numpy()
+            status, iters = s.solve()
+            hist = s.history()
+            c = s.counters()
+            ritz = s.residuals()[0]
+        ref = A.to_scipy() @ W
+        # float64 product to rounding; the float32 one to float32 accumulation of 5 terms
+        bound = (1e-13 if precision == "fp64" else 1e-6) * np.max(np.abs(ref))
+        assert np.max(np.abs(Z - ref)) <= bound
+        assert status == 0
+        assert c["restarts"] >= 2  # the first step and the one after the product
+        if precision == "mixed":
+            assert c["low_iters"] > 10  # the product fell in the float32 phase
+        assert np.max(np.abs(ritz - lam) / lam) <= 1e-10
+        runs.append((iters, hist))
+    (i1, h1), (i2, h2) = runs
+    assert i1 == i2
+    assert np.array_equal(h1["mu"], h2["mu"]) and np.array_equal(h1["rho"], h2["rho"])
+
+
 def _solve_both(A, p, seed, which=1, method="rcg", tol=1e-10, max_iter=20000, **kw):
     gsi = _gsi()
     X0 = I.start_block(A.n, p, seed)
