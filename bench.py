@@ -740,7 +740,7 @@ def main():
     spmm_gbs = kern["spmm"]["GBps"]
     spmm_roof = {"bound": "hbm", "achieved": round(spmm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                  "frac": round(spmm_gbs / HBM_PEAK_GBS, 4), "kernel": "k_spmm",
-                 "traffic": measured_traffic(f"gsi::k_spmm<double, {PPd}>", f"traffic_laplace3d_{N}_p{p}_fp64.json"),
+                 "traffic": measured_traffic(f"gsi::k_spmm<double, {PPd},", f"traffic_laplace3d_{N}_p{p}_fp64.json"),
                  "bytes_per_launch": nb["spmm"], "avg_us": round(kern["spmm"]["avg_us"], 2)}
     s64.close()
     # the gradient variant (Algorithm 2) per iteration: a fixed run of 300 iterations from X0

@@ -135,6 +135,7 @@ struct gsi_ctx {
   int hist_cap = 0;
   double nA = 0.0;
   int64_t plane_tiles = 0;  // banded SpMM tile order (0: one slab per XCD)
+  int spmm_batch = 8;       // gathers per batch of the CSR SpMM: 7 when no row holds more than 7
   // matrix-free stencil operator (gsi_create_stencil): grid, neighbour weight (times the
   // sign of which); the engines' vals hold the n diagonal entries
   // RCG or RCG(+) (A X by the recursion or formed every iteration): recompute_ax = -1 lets
@@ -208,7 +209,8 @@ void spmm_op(gsi_ctx* h, Engine<T>& e, const T* W0, const T* W1, T* Z, int mode)
   if (h->stencil)
     Kernels<T, PP>::spmm_stencil(h->st, e.n, h->sdims, e.vals, h->soff, W0, W1, Z, e.sc, mode, h->plane_tiles);
   else
-    Kernels<T, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, W0, W1, Z, e.sc, mode, h->plane_tiles);
+    Kernels<T, PP>::spmm(h->st, e.n, h->rowptr, h->colind, e.vals, W0, W1, Z, e.sc, mode, h->plane_tiles,
+                         h->spmm_batch);
 }
 
 gsi_status hip_check(gsi_ctx* h, hipError_t e, const char* what) {
@@ -979,6 +981,7 @@ gsi_status create_impl(gsi_handle* out, const gsi_csr* A, const gsi_stencil* S, 
   if (fl[0] & 2) return bail(GSI_EINVAL, "column index out of range");
   if (fl[0] & 8) return bail(GSI_EINVAL, "column indices not sorted within a row");
   if (fl[0] & 4) return bail(GSI_BREAKDOWN, "non-finite matrix value");
+  h->spmm_batch = (A && !(fl[0] & 32)) ? 7 : 8;
   if (fl[1]) return bail(GSI_BREAKDOWN, "non-finite value in X0");
   if (A && opt->check_symmetric) {
     // the structure is valid (checked above), so the searches stay inside the arrays

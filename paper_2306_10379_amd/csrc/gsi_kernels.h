@@ -38,7 +38,8 @@ struct Kernels {
                           T* G0, T* G1, const double* small, const Scalars* sc, double* partials);
   // plane_tiles > 0: banded tile order (see spmm_tile in gsi_kernels.hip); 0: one slab per XCD
   static void spmm(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind, const T* vals,
-                   const T* W0, const T* W1, T* Z, const Scalars* sc, int mode, int64_t plane_tiles = 0);
+                   const T* W0, const T* W1, T* Z, const Scalars* sc, int mode, int64_t plane_tiles = 0,
+                   int batch = 8);
   // A^T B1 (and A^T B2 when B2 != nullptr); mode as for spmm (mode 1 picks A0/A1 by parity)
   static void gram(hipStream_t st, int nb, int64_t n, const T* A0, const T* A1, const T* B1, const T* B2,
                    const Scalars* sc, int mode, double* partials);

@@ -458,8 +458,10 @@ __global__ __launch_bounds__(WG) void k_update_grad(int64_t n, T* __restrict__ X
 // consecutive columns that one load moves (2 in float64, 4 in float32): a row of W is one
 // gather instruction's worth of lanes, and at 16 bytes per lane the kernel needs fewer
 // registers (more waves in flight) than with two loads per lane (777 -> 701 us at 128^3,
-// p = 64, float64). The column indices and values of up to 8 nonzeros are read before the
-// 8 gathers are issued, so each lane has up to 8 independent loads in flight.
+// p = 64, float64). The column indices and values of a batch of U nonzeros are read before
+// its U gathers are issued, so each lane has up to U independent loads in flight. U is 8, or 7
+// when no row holds more than 7 nonzeros (a 7-point stencil: 644 -> 627 us at 128^3, p = 64,
+// where a batch of 8 spends one gather of the 8 on padding; same bits).
 // mode 0: always run, W = W0. mode 1: the iteration's SpMM (skipped when the solve is done
 // or the step is null), W = P of the current iteration (W0/W1 by parity). mode 2: explicit
 // A X (runs only when requested).
@@ -518,7 +520,7 @@ __device__ __forceinline__ bool csr_stage(int32_t* s_rp, int32_t* s_col, V* s_va
   return staged;
 }
 
-template <typename T, int PP>
+template <typename T, int PP, int U>
 __global__ __launch_bounds__(WG) void k_spmm(int64_t n, const int32_t* __restrict__ rowptr,
                                              const int32_t* __restrict__ colind, const T* __restrict__ vals,
                                              const T* __restrict__ W0, const T* __restrict__ W1, T* __restrict__ Z,
@@ -528,7 +530,6 @@ __global__ __launch_bounds__(WG) void k_spmm(int64_t n, const int32_t* __restric
   constexpr int EPL = 16 / (int)sizeof(T);  // columns per lane: one 16-byte gather per nonzero
   constexpr int LPR = PP / EPL;             // lanes per row
   constexpr int RPB = WG / LPR;             // rows per block pass
-  constexpr int U = 8;                      // nonzeros per batch
   const int64_t ntiles = (n + TR - 1) / TR;
   const int64_t t = spmm_tile(ntiles, plane_tiles);
   if (t >= ntiles) return;
@@ -1361,6 +1362,7 @@ __global__ void k_csr_check(int64_t n, int64_t nnz, const int32_t* __restrict__ 
   for (int64_t row = (int64_t)blockIdx.x * WG + threadIdx.x; row < n; row += (int64_t)gridDim.x * WG) {
     const int64_t j0 = rowptr[row], j1 = rowptr[row + 1];
     if (j1 < j0 || j0 < 0 || j1 > nnz) { f |= 1; continue; }
+    if (j1 - j0 > 7) f |= 32;  // not an error: the SpMM's batch of gathers stays at 8
     double s = 0.0;
     int32_t prev = -1;
     for (int64_t j = j0; j < j1; ++j) {
@@ -1518,10 +1520,15 @@ void Kernels<T, PP>::update(hipStream_t st, int nb, int64_t n, T* X, T* Y, const
 }
 template <typename T, int PP>
 void Kernels<T, PP>::spmm(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind, const T* vals,
-                          const T* W0, const T* W1, T* Z, const Scalars* sc, int mode, int64_t plane_tiles) {
+                          const T* W0, const T* W1, T* Z, const Scalars* sc, int mode, int64_t plane_tiles,
+                          int batch) {
   const int64_t grid = spmm_grid((n + TR - 1) / TR, plane_tiles);
-  k_spmm<T, PP><<<dim3((unsigned)grid), dim3(WG), 0, st>>>(n, rowptr, colind, vals, W0, W1, Z, sc, mode,
-                                                          plane_tiles);
+  if (batch == 7)
+    k_spmm<T, PP, 7><<<dim3((unsigned)grid), dim3(WG), 0, st>>>(n, rowptr, colind, vals, W0, W1, Z, sc, mode,
+                                                               plane_tiles);
+  else
+    k_spmm<T, PP, 8><<<dim3((unsigned)grid), dim3(WG), 0, st>>>(n, rowptr, colind, vals, W0, W1, Z, sc, mode,
+                                                               plane_tiles);
 }
 template <typename T, int PP>
 void Kernels<T, PP>::gram(hipStream_t st, int nb, int64_t n, const T* A0, const T* A1, const T* B1, const T* B2,
