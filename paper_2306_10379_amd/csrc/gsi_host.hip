@@ -390,12 +390,14 @@ void launch_iteration(gsi_ctx* h, Engine<T>& e, double* hist) {
       PassTimer t(h, GSI_PASS_SPMM);
       if constexpr (std::is_same<T, float>::value) {
         if (e.P16)
-          Kernels<T, PP>::spmm16(h->st, e.n, h->rowptr, h->colind, e.vals16, e.P16, e.Z, e.sc, 1, h->plane_tiles);
+          Kernels<T, PP>::spmm16(h->st, e.n, h->rowptr, h->colind, e.vals16, e.P16, e.Z, e.sc, 1, h->plane_tiles,
+                                 h->spmm_batch);
         else
           spmm_op<T, PP>(h, e, e.P0, e.P1, e.Z, 1);
       } else {
         if (e.P32)
-          Kernels<T, PP>::spmm_fin(h->st, e.n, h->rowptr, h->colind, e.vals32, e.P32, e.Z, e.sc, 1, h->plane_tiles);
+          Kernels<T, PP>::spmm_fin(h->st, e.n, h->rowptr, h->colind, e.vals32, e.P32, e.Z, e.sc, 1, h->plane_tiles,
+                                   h->spmm_batch);
         else
           spmm_op<T, PP>(h, e, e.P0, e.P1, e.Z, 1);
       }
@@ -721,7 +723,7 @@ gsi_status si_iterate(gsi_ctx* h, int count) {
                                                    -c * a, -sigma * sigma_new, h->plane_tiles);
           else
             Kernels<double, PP>::spmm_axpy(h->st, e.n, h->rowptr, h->colind, e.vals, cur, prev, nxt, a, -c * a,
-                                           -sigma * sigma_new, h->plane_tiles);
+                                           -sigma * sigma_new, h->plane_tiles, h->spmm_batch);
         });
         prev = cur;
         cur = nxt;
@@ -1338,7 +1340,8 @@ gsi_status gsi_spmm_lowp(gsi_handle h, const double* W, double* Z) {
     if (h->bf16) {
       launch_pack<double>(h->st, h->n, h->p, h->PP, W, h->e64.G0, 1.0);
       launch_to_bf16(h->st, rows * PP, h->e64.G0, e.P16, 1.0);
-      Kernels<float, PP>::spmm16(h->st, e.n, h->rowptr, h->colind, e.vals16, e.P16, e.Z, e.sc, 0, h->plane_tiles);
+      Kernels<float, PP>::spmm16(h->st, e.n, h->rowptr, h->colind, e.vals16, e.P16, e.Z, e.sc, 0, h->plane_tiles,
+                                 h->spmm_batch);
     } else {
       launch_pack<float>(h->st, h->n, h->p, h->PP, W, e.G0, 1.0);
       spmm_op<float, PP>(h, e, e.G0, e.G0, e.Z, 0);

@@ -46,14 +46,16 @@ struct Kernels {
   static void product(hipStream_t st, int nb, int64_t n, const T* IN, T* OUT, const double* M);
   // Z = A W with bfloat16 values and W, float32 accumulation and output
   static void spmm16(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind, const uint16_t* vals,
-                     const uint16_t* W, float* Z, const Scalars* sc, int mode, int64_t plane_tiles = 0);
+                     const uint16_t* W, float* Z, const Scalars* sc, int mode, int64_t plane_tiles = 0,
+                     int batch = 8);
   // Z = alpha (A W) + beta W + gamma V (V nullable), always runs
   static void spmm_axpy(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind, const T* vals,
                         const T* W, const T* V, T* Z, double alpha, double beta, double gamma,
-                        int64_t plane_tiles = 0);
+                        int64_t plane_tiles = 0, int batch = 8);
   // Z (float64) = A W from float32 values and W, float64 products and accumulation
   static void spmm_fin(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind, const float* vals,
-                       const float* W, double* Z, const Scalars* sc, int mode, int64_t plane_tiles = 0);
+                       const float* W, double* Z, const Scalars* sc, int mode, int64_t plane_tiles = 0,
+                       int batch = 8);
   static void colres(hipStream_t st, int nb, int64_t n, const T* X, const T* Y, const double* theta,
                      double* partials);
   // matrix-free stencil operator on the grid dims[0] x dims[1] x dims[2] (host array):

@@ -580,7 +580,7 @@ __global__ __launch_bounds__(WG) void k_spmm(int64_t n, const int32_t* __restric
 // Z (float32) = A W with bfloat16 values and a bfloat16 W, float32 accumulation (the
 // products of two bfloat16 numbers are exact in float32). Same tiling and modes as k_spmm;
 // a lane owns 8 consecutive columns (one 16-byte gather per nonzero).
-template <int PP>
+template <int PP, int U>
 __global__ __launch_bounds__(WG) void k_spmm16(int64_t n, const int32_t* __restrict__ rowptr,
                                                const int32_t* __restrict__ colind, const uint16_t* __restrict__ vals,
                                                const uint16_t* __restrict__ W, float* __restrict__ Z,
@@ -589,7 +589,6 @@ __global__ __launch_bounds__(WG) void k_spmm16(int64_t n, const int32_t* __restr
   constexpr int EPL = 8;
   constexpr int LPR = PP / EPL;  // lanes per row
   constexpr int RPB = WG / LPR;  // rows per block pass
-  constexpr int U = 8;           // nonzeros per batch
   const int64_t ntiles = (n + TR - 1) / TR;
   const int64_t t = spmm_tile(ntiles, plane_tiles);
   if (t >= ntiles) return;
@@ -647,7 +646,7 @@ __global__ __launch_bounds__(WG) void k_spmm16(int64_t n, const int32_t* __restr
 // Z (float64) = A W from float32 values and a float32 W: each product of two float32 numbers
 // is exact in float64 and the sum is float64, so the only error is the rounding of A and W
 // to float32 (half the gather bytes of float64). Same tiling and modes as k_spmm.
-template <int PP>
+template <int PP, int U>
 __global__ __launch_bounds__(WG) void k_spmm_fin(int64_t n, const int32_t* __restrict__ rowptr,
                                                  const int32_t* __restrict__ colind, const float* __restrict__ vals,
                                                  const float* __restrict__ W, double* __restrict__ Z,
@@ -656,7 +655,6 @@ __global__ __launch_bounds__(WG) void k_spmm_fin(int64_t n, const int32_t* __res
   constexpr int EPL = 4;
   constexpr int LPR = PP / EPL;  // lanes per row
   constexpr int RPB = WG / LPR;  // rows per block pass
-  constexpr int U = 8;           // nonzeros per batch
   const int64_t ntiles = (n + TR - 1) / TR;
   const int64_t t = spmm_tile(ntiles, plane_tiles);
   if (t >= ntiles) return;
@@ -706,7 +704,7 @@ __global__ __launch_bounds__(WG) void k_spmm_fin(int64_t n, const int32_t* __res
 // Z = alpha (A W) + beta W + gamma V (V nullable): one step of a polynomial filter's
 // three-term recurrence fused into the SpMM (the row of W and of V a lane needs for the
 // epilogue is its own output row). Always runs (mode 0), same tiling as k_spmm.
-template <typename T, int PP>
+template <typename T, int PP, int U>
 __global__ __launch_bounds__(WG) void k_spmm_axpy(int64_t n, const int32_t* __restrict__ rowptr,
                                                   const int32_t* __restrict__ colind, const T* __restrict__ vals,
                                                   const T* __restrict__ W, const T* __restrict__ V, T* __restrict__ Z,
@@ -715,7 +713,6 @@ __global__ __launch_bounds__(WG) void k_spmm_axpy(int64_t n, const int32_t* __re
   constexpr int EPL = 16 / (int)sizeof(T);  // one 16-byte gather per nonzero per lane
   constexpr int LPR = PP / EPL;
   constexpr int RPB = WG / LPR;
-  constexpr int U = 8;
   const int64_t ntiles = (n + TR - 1) / TR;
   const int64_t t = spmm_tile(ntiles, plane_tiles);
   if (t >= ntiles) return;
@@ -1464,10 +1461,14 @@ void Kernels<T, PP>::dir(hipStream_t st, int nb, int64_t n, const T* X, const T*
 template <typename T, int PP>
 void Kernels<T, PP>::spmm_axpy(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind, const T* vals,
                                const T* W, const T* V, T* Z, double alpha, double beta, double gamma,
-                               int64_t plane_tiles) {
+                               int64_t plane_tiles, int batch) {
   const int64_t grid = spmm_grid((n + TR - 1) / TR, plane_tiles);
-  k_spmm_axpy<T, PP><<<dim3((unsigned)grid), dim3(WG), 0, st>>>(n, rowptr, colind, vals, W, V, Z, alpha, beta, gamma,
-                                                               plane_tiles);
+  if (batch == 7)
+    k_spmm_axpy<T, PP, 7><<<dim3((unsigned)grid), dim3(WG), 0, st>>>(n, rowptr, colind, vals, W, V, Z, alpha, beta,
+                                                                    gamma, plane_tiles);
+  else
+    k_spmm_axpy<T, PP, 8><<<dim3((unsigned)grid), dim3(WG), 0, st>>>(n, rowptr, colind, vals, W, V, Z, alpha, beta,
+                                                                    gamma, plane_tiles);
 }
 // Grids with at least SY rows in y march through their planes (k_spmm_march); lines use
 // the row-tile kernel.
@@ -1499,16 +1500,22 @@ void Kernels<T, PP>::spmm_stencil_axpy(hipStream_t st, int64_t n, const int32_t*
 template <typename T, int PP>
 void Kernels<T, PP>::spmm_fin(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind,
                               const float* vals, const float* W, double* Z, const Scalars* sc, int mode,
-                              int64_t plane_tiles) {
+                              int64_t plane_tiles, int batch) {
   const int64_t grid = spmm_grid((n + TR - 1) / TR, plane_tiles);
-  k_spmm_fin<PP><<<dim3((unsigned)grid), dim3(WG), 0, st>>>(n, rowptr, colind, vals, W, Z, sc, mode, plane_tiles);
+  if (batch == 7)
+    k_spmm_fin<PP, 7><<<dim3((unsigned)grid), dim3(WG), 0, st>>>(n, rowptr, colind, vals, W, Z, sc, mode, plane_tiles);
+  else
+    k_spmm_fin<PP, 8><<<dim3((unsigned)grid), dim3(WG), 0, st>>>(n, rowptr, colind, vals, W, Z, sc, mode, plane_tiles);
 }
 template <typename T, int PP>
 void Kernels<T, PP>::spmm16(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind,
                             const uint16_t* vals, const uint16_t* W, float* Z, const Scalars* sc, int mode,
-                            int64_t plane_tiles) {
+                            int64_t plane_tiles, int batch) {
   const int64_t grid = spmm_grid((n + TR - 1) / TR, plane_tiles);
-  k_spmm16<PP><<<dim3((unsigned)grid), dim3(WG), 0, st>>>(n, rowptr, colind, vals, W, Z, sc, mode, plane_tiles);
+  if (batch == 7)
+    k_spmm16<PP, 7><<<dim3((unsigned)grid), dim3(WG), 0, st>>>(n, rowptr, colind, vals, W, Z, sc, mode, plane_tiles);
+  else
+    k_spmm16<PP, 8><<<dim3((unsigned)grid), dim3(WG), 0, st>>>(n, rowptr, colind, vals, W, Z, sc, mode, plane_tiles);
 }
 template <typename T, int PP>
 void Kernels<T, PP>::update(hipStream_t st, int nb, int64_t n, T* X, T* Y, const T* P0, const T* P1, const T* Z,
