@@ -27,11 +27,12 @@ using namespace gsi;
 
 namespace {
 
-constexpr int MAXP = 64;
+constexpr int MAXP = 64;    // widest block of the mixed-precision, SI, stencil and explicit-C paths
+constexpr int MAXP_F64 = 128;  // widest block of plain float64 RCG / RSD on a CSR matrix
 
 // Padded block width: the kernels are built for 16, 32 and 64 columns; the padding
 // columns stay zero.
-int padded_width(int p) { return p <= 16 ? 16 : (p <= 32 ? 32 : 64); }
+int padded_width(int p) { return p <= 16 ? 16 : (p <= 32 ? 32 : (p <= 64 ? 64 : 128)); }
 
 // The seeded start block of gsi_create with X0 == NULL (the generator is stated in gsi.h):
 // SplitMix64 as a counter-based generator (output k is the mixing function of
@@ -102,7 +103,7 @@ struct Engine {
       vals16 = d.alloc<uint16_t>((size_t)nnz);
       P16 = d.alloc<uint16_t>(blk);
     }
-    small = d.alloc<double>((size_t)S_COUNT * PP * PP + 8 * PP);
+    small = d.alloc<double>(small_doubles(PP));
     sc = d.alloc<Scalars>(1);
     if (d.err != hipSuccess) return false;
     for (T* b : {X, Y, G0, G1, P0, P1, Z})
@@ -230,6 +231,9 @@ void dispatch_pp(int PP, F&& f) {
     case 16: f(std::integral_constant<int, 16>()); break;
     case 32: f(std::integral_constant<int, 32>()); break;
     case 64: f(std::integral_constant<int, 64>()); break;
+    case 128:  // float64 only (p above 64: plain float64 RCG / RSD)
+      if constexpr (std::is_same<T, double>::value) f(std::integral_constant<int, 128>());
+      break;
     default: break;
   }
 }
@@ -329,7 +333,7 @@ gsi_status init_state(gsi_ctx* h, Engine<T>& e, double tol, int max_iter, int hi
   s.p = e.p;
   s.hist_cap = h->hist_cap - hist_off;
   GSI_TRY(hip_check(h, hipMemcpyAsync(e.sc, &s, sizeof(s), hipMemcpyHostToDevice, h->st), "state upload"));
-  GSI_TRY(hip_check(h, hipMemsetAsync(e.small, 0, sizeof(double) * ((size_t)S_COUNT * e.PP * e.PP + 8 * e.PP), h->st),
+  GSI_TRY(hip_check(h, hipMemsetAsync(e.small, 0, sizeof(double) * small_doubles(e.PP), h->st),
                     "small reset"));
   dispatch_pp<T>(e.PP, [&](auto PPc) {
     constexpr int PP = decltype(PPc)::value;
@@ -870,7 +874,9 @@ gsi_status create_impl(gsi_handle* out, const gsi_csr* A, const gsi_stencil* S, 
     if (opt->precision == GSI_MIXED_BF16) return bail(GSI_EUNSUPPORTED, "bfloat16 mode needs a CSR matrix");
   }
   if (opt->p < 1 || opt->p >= n_op) return bail(GSI_EINVAL, "need 1 <= p < n");
-  if (opt->p > MAXP) return bail(GSI_EUNSUPPORTED, "p above 64 is not built");
+  if (opt->p > MAXP_F64) return bail(GSI_EUNSUPPORTED, "p above 128 is not built");
+  if (opt->p > MAXP && (S || opt->precision != GSI_FP64 || opt->method == GSI_SI || opt->explicit_c))
+    return bail(GSI_EUNSUPPORTED, "p above 64 is built for float64 RCG / RSD on a CSR matrix without explicit_c");
   if (opt->which != 1 && opt->which != -1) return bail(GSI_EINVAL, "which must be +1 or -1");
   if (opt->method != GSI_RSD && opt->method != GSI_RCG && opt->method != GSI_SI)
     return bail(GSI_EINVAL, "unknown method");
@@ -919,7 +925,7 @@ gsi_status create_impl(gsi_handle* out, const gsi_csr* A, const gsi_stencil* S, 
   h->partials = d.alloc<double>((size_t)(h->nb > h->nb_gram ? h->nb : h->nb_gram) * (2 * h->PP * h->PP + 8) + 4096);
   h->red = d.alloc<double>(2 * h->PP * h->PP + 8);
   h->hist = d.alloc<double>((size_t)h->hist_cap * H_FIELDS);
-  h->dvec = d.alloc<double>(4 * MAXP + 4096);
+  h->dvec = d.alloc<double>(4 * MAXP_F64 + 4096);
   h->flags = d.alloc<int>(4);
   if (d.err != hipSuccess) { d.release(); return bail(GSI_ENOMEM, "device allocation failed"); }
   if (!h->e64.alloc(d, h->n, h->p, h->nb, h->nnz)) { d.release(); return bail(GSI_ENOMEM, "device allocation failed"); }
@@ -932,7 +938,8 @@ gsi_status create_impl(gsi_handle* out, const gsi_csr* A, const gsi_stencil* S, 
   dispatch_pp<double>(h->PP, [&](auto PPc) {
     constexpr int PP = decltype(PPc)::value;
     if (ke == hipSuccess) ke = Kernels<double, PP>::init();
-    if (ke == hipSuccess) ke = Kernels<float, PP>::init();
+    if constexpr (PP <= MAXP)
+      if (ke == hipSuccess) ke = Kernels<float, PP>::init();
   });
   if (ke != hipSuccess) return bail(GSI_EDEVICE, std::string("kernel attributes: ") + hipGetErrorString(ke));
   hipStream_t st = h->st;
@@ -1021,7 +1028,8 @@ gsi_status create_impl(gsi_handle* out, const gsi_csr* A, const gsi_stencil* S, 
   }
   h->e64.explicit_grams = opt->explicit_c != 0;
   h->e32.explicit_grams = opt->explicit_c != 0;
-  h->e64.fused = !h->e64.explicit_grams && (opt->method == GSI_RCG || opt->method == GSI_RSD);
+  // the fused pass keeps M and M C in LDS: up to PP = 64
+  h->e64.fused = !h->e64.explicit_grams && (opt->method == GSI_RCG || opt->method == GSI_RSD) && h->PP <= MAXP;
   s = start(h, X0);
   if (s != GSI_OK) return bail(s, h->err);
   *out = h;

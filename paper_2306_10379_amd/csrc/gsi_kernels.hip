@@ -31,14 +31,19 @@ __global__ __launch_bounds__(WG) void k_grad(int64_t n, const T* __restrict__ X,
   if (sc->done) return;
   if (cond == GRAD_PENDING && sc->grad_ready) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
+  // the p x p factor in LDS up to PP = 64; above (128 KB in float64) it is read from the
+  // small buffer through the caches and LDS holds only the Gram's tile
+  constexpr bool WIDE = PP > PP_LDS_MAX;
+  static_assert(!WIDE || std::is_same<T, double>::value, "block widths above 64 are float64 only");
   T* sC = reinterpret_cast<T*>(lds_raw);
-  T* sG = sC + PP * PP;
+  T* sG = WIDE ? sC : sC + PP * PP;
+  const T* Cm = WIDE ? reinterpret_cast<const T*>(small + S_C * PP * PP) : sC;
   __shared__ double red[4 * 3];
   const int par = sc->k & 1;
   T* G = par ? G1 : G0;
   const T* Gold = par ? G0 : G1;
   const bool have_old = sc->k > 0;
-  load_matrix_lds<T, PP>(sC, small + S_C * PP * PP);
+  if (!WIDE) load_matrix_lds<T, PP>(sC, small + S_C * PP * PP);
   __syncthreads();
   const int w = threadIdx.x >> 6;
   const int64_t ntiles = (n + TR - 1) / TR;
@@ -63,7 +68,7 @@ __global__ __launch_bounds__(WG) void k_grad(int64_t n, const T* __restrict__ X,
     load_al<T, PP>(X, row0, n, a);
     typename Vec4<T>::type acc[PP / 16];
     zero_acc<T, PP>(acc);
-    product<T, PP>(a, sC, acc);
+    product<T, PP>(a, Cm, acc);
     T y[PP / 16][4], g[PP / 16][4];
     load_rl<T, PP>(Y, row0, n, y);
 #pragma unroll
@@ -142,8 +147,12 @@ __global__ __launch_bounds__(WG) void k_dir(int64_t n, const T* __restrict__ X, 
                                             float* __restrict__ P32) {
   if (sc->done) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
+  // the p x p factor in LDS up to PP = 64, read through the caches above (as in k_grad)
+  constexpr bool WIDE = PP > PP_LDS_MAX;
+  static_assert(!WIDE || std::is_same<T, double>::value, "block widths above 64 are float64 only");
   T* sK = reinterpret_cast<T*>(lds_raw);
-  T* sP = sK + PP * PP;
+  T* sP = WIDE ? sK : sK + PP * PP;
+  const T* Km = WIDE ? reinterpret_cast<const T*>(small + S_KD * PP * PP) : sK;
   __shared__ double red[4];
   const int par = sc->k & 1;
   const T* G = par ? G1 : G0;
@@ -151,7 +160,7 @@ __global__ __launch_bounds__(WG) void k_dir(int64_t n, const T* __restrict__ X, 
   const T* Pold = par ? P0 : P1;
   const T beta = (T)sc->beta_pr;
   const bool use_old = sc->beta_pr != 0.0;
-  load_matrix_lds<T, PP>(sK, small + S_KD * PP * PP);
+  if (!WIDE) load_matrix_lds<T, PP>(sK, small + S_KD * PP * PP);
   __syncthreads();
   const int w = threadIdx.x >> 6;
   const int64_t ntiles = (n + TR - 1) / TR;
@@ -167,7 +176,7 @@ __global__ __launch_bounds__(WG) void k_dir(int64_t n, const T* __restrict__ X, 
     load_al<T, PP>(X, row0, n, a);
     typename Vec4<T>::type acc[PP / 16];
     zero_acc<T, PP>(acc);
-    product<T, PP>(a, sK, acc);
+    product<T, PP>(a, Km, acc);
     T g[PP / 16][4], p[PP / 16][4];
     load_rl<T, PP>(G, row0, n, g);
     if (use_old) {
@@ -1406,8 +1415,8 @@ template <typename T, int PP>
 int lds_bytes(Pass pass) {
   const int m = PP * PP * (int)sizeof(T), tile = TR * PP * (int)sizeof(T);
   switch (pass) {
-    case Pass::Grad: return m + tile;
-    case Pass::Dir: return m + tile;
+    case Pass::Grad: return (PP > PP_LDS_MAX ? 0 : m) + tile;
+    case Pass::Dir: return (PP > PP_LDS_MAX ? 0 : m) + tile;
     case Pass::Update: return m;
     case Pass::UpdateGrams: return m + 3 * tile;
     case Pass::UpdateGrad: return 2 * m;
@@ -1429,8 +1438,12 @@ hipError_t set_lds_limits() {
   GSI_SET((k_grad<T, PP>), Pass::Grad)
   GSI_SET((k_dir<T, PP>), Pass::Dir)
   GSI_SET((k_update<T, PP, false>), Pass::Update)
-  GSI_SET((k_update<T, PP, true>), Pass::UpdateGrams)
-  GSI_SET((k_update_grad<T, PP>), Pass::UpdateGrad)
+  // the retraction with Gram epilogue and the fused retraction-gradient pass are not used above
+  // PP = 64 (their LDS would exceed a CU's)
+  if constexpr (PP <= PP_LDS_MAX) {
+    GSI_SET((k_update<T, PP, true>), Pass::UpdateGrams)
+    GSI_SET((k_update_grad<T, PP>), Pass::UpdateGrad)
+  }
   GSI_SET((k_product<T, PP>), Pass::Product)
   if constexpr (PP == 64) {
     if (e == hipSuccess)
@@ -1450,8 +1463,9 @@ template <typename T, int PP>
 void Kernels<T, PP>::update_grad(hipStream_t st, int nb, int64_t n, T* X, T* Y, const T* P0, const T* P1,
                                  const T* Z, T* G0, T* G1, const double* small, const Scalars* sc,
                                  double* partials) {
-  k_update_grad<T, PP><<<nb, WG, lds_bytes<T, PP>(Pass::UpdateGrad), st>>>(n, X, Y, P0, P1, Z, G0, G1, small, sc,
-                                                                          partials);
+  if constexpr (PP <= PP_LDS_MAX)  // not used above (the host keeps the separate passes there)
+    k_update_grad<T, PP><<<nb, WG, lds_bytes<T, PP>(Pass::UpdateGrad), st>>>(n, X, Y, P0, P1, Z, G0, G1, small, sc,
+                                                                            partials);
 }
 template <typename T, int PP>
 void Kernels<T, PP>::dir(hipStream_t st, int nb, int64_t n, const T* X, const T* G0, const T* G1, T* P0, T* P1,
@@ -1520,10 +1534,15 @@ void Kernels<T, PP>::spmm16(hipStream_t st, int64_t n, const int32_t* rowptr, co
 template <typename T, int PP>
 void Kernels<T, PP>::update(hipStream_t st, int nb, int64_t n, T* X, T* Y, const T* P0, const T* P1, const T* Z,
                             const double* small, const Scalars* sc, double* partials, bool grams) {
-  if (grams)
-    k_update<T, PP, true><<<nb, WG, lds_bytes<T, PP>(Pass::UpdateGrams), st>>>(n, X, Y, P0, P1, Z, small, sc, partials);
-  else
-    k_update<T, PP, false><<<nb, WG, lds_bytes<T, PP>(Pass::Update), st>>>(n, X, Y, P0, P1, Z, small, sc, partials);
+  // the Gram epilogue exists up to PP = 64 (the host refuses explicit_c above)
+  if constexpr (PP <= PP_LDS_MAX) {
+    if (grams) {
+      k_update<T, PP, true><<<nb, WG, lds_bytes<T, PP>(Pass::UpdateGrams), st>>>(n, X, Y, P0, P1, Z, small, sc,
+                                                                               partials);
+      return;
+    }
+  }
+  k_update<T, PP, false><<<nb, WG, lds_bytes<T, PP>(Pass::Update), st>>>(n, X, Y, P0, P1, Z, small, sc, partials);
 }
 template <typename T, int PP>
 void Kernels<T, PP>::spmm(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind, const T* vals,
@@ -1633,6 +1652,7 @@ void launch_finite(hipStream_t st, int64_t count, const double* x, int* flags) {
 template struct Kernels<double, 16>;
 template struct Kernels<double, 32>;
 template struct Kernels<double, 64>;
+template struct Kernels<double, 128>;
 template struct Kernels<float, 16>;
 template struct Kernels<float, 32>;
 template struct Kernels<float, 64>;

@@ -4,9 +4,9 @@
 // the exact line search (bracket from the branch roots, Brent's method on phi'), the
 // retraction factor M, Cholesky QR and Rayleigh-Ritz.
 //
-// The p x p matrices live in the small buffer as PP x PP row-major arrays (PP = 16, 32 or
-// 64, the smallest that holds p) whose padding is zero; dense products among them use f64
-// MFMA.
+// The p x p matrices live in the small buffer as PP x PP row-major arrays (PP = 16, 32, 64 or
+// 128, the smallest that holds p) whose padding is zero; dense products among them use f64
+// MFMA. Working matrices sit in LDS up to PP = 64 and in the small buffer's work area above.
 #include <math.h>
 
 #include "gsi_kernels.h"
@@ -134,8 +134,8 @@ __global__ __launch_bounds__(WG) void k_eig(double* __restrict__ small, Scalars*
   __shared__ double cs[2 * MAXP];
   __shared__ int uv[MAXP];
   __shared__ int nrot, anyr;
-  const int sweeps = eig_dev<PP>(small, sc->p, sc->v_valid != 0, reinterpret_cast<double*>(lds_raw), cs, uv, &nrot,
-                                 &anyr);
+  double* work = PP > PP_LDS_MAX ? small + small_work_offset(PP) : reinterpret_cast<double*>(lds_raw);
+  const int sweeps = eig_dev<PP>(small, sc->p, sc->v_valid != 0, work, cs, uv, &nrot, &anyr);
   if (threadIdx.x == 0) {
     sc->v_valid = 1;
     sc->sweeps = sweeps;
@@ -160,8 +160,9 @@ __global__ __launch_bounds__(WG) void k_linesearch(const double* __restrict__ re
     reinterpret_cast<int32_t*>(&ls)[i] = reinterpret_cast<const int32_t*>(sc)[i];
   __syncthreads();
   const int p = ls.p;
-  linesearch_dev<PP>(red, red + PP * PP, small, p, reinterpret_cast<double*>(lds_raw), terms, &smu, &sok, &sevals,
-                     &sbmax, want_mc != 0);
+  double* work = PP > PP_LDS_MAX ? small + small_work_offset(PP) + 4 * PP * (PP + 1)
+                                 : reinterpret_cast<double*>(lds_raw);
+  linesearch_dev<PP>(red, red + PP * PP, small, p, work, terms, &smu, &sok, &sevals, &sbmax, want_mc != 0);
   if (threadIdx.x == 0) {
     sc->brent_evals = sevals;
     sc->grad_ready = 0;  // X changes (or the step is void and the next iteration restarts)
@@ -216,8 +217,10 @@ __global__ __launch_bounds__(WG) void k_after_refresh(int PP, const double* __re
 __global__ __launch_bounds__(WG) void k_chol_inv(int PP, int p, const double* __restrict__ red,
                                                  double* __restrict__ small, int* __restrict__ flag) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  double* L = reinterpret_cast<double*>(lds_raw);
-  double* Li = L + MAXP * MAXP;
+  // p up to 64 in LDS; above, in the work area of the small buffer
+  const bool wide = PP > PP_LDS_MAX;
+  double* L = wide ? small + small_work_offset(PP) + 4 * PP * (PP + 1) : reinterpret_cast<double*>(lds_raw);
+  double* Li = L + (wide ? PP * PP : MAXP * MAXP);
   __shared__ int bad;
   __shared__ double dmax;
   for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
@@ -269,7 +272,7 @@ __global__ __launch_bounds__(WG) void k_chol_inv(int PP, int p, const double* __
 template <int PP>
 __global__ __launch_bounds__(WG) void k_transform_cw(double* __restrict__ small, int* __restrict__ flag) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  double* T1 = reinterpret_cast<double*>(lds_raw);
+  double* T1 = PP > PP_LDS_MAX ? small + small_work_offset(PP) + 4 * PP * (PP + 1) : reinterpret_cast<double*>(lds_raw);
   double* T2 = T1 + PP * PP;
   double* M = small + S_M * PP * PP;
   double* C = small + S_C * PP * PP;
@@ -301,12 +304,14 @@ __global__ __launch_bounds__(WG) void k_transform_cw(double* __restrict__ small,
 __global__ __launch_bounds__(WG) void k_ritz(int PP, int p, const double* __restrict__ red, double* __restrict__ small,
                                              double* __restrict__ vals) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  double* A = reinterpret_cast<double*>(lds_raw);
-  double* V = A + MAXP * (MAXP + 1);
-  __shared__ double cs[2 * MAXP];
+  // p up to 64 in LDS; above, in the work area of the small buffer
+  const bool wide = PP > PP_LDS_MAX;
+  double* A = wide ? small + small_work_offset(PP) + 4 * PP * (PP + 1) : reinterpret_cast<double*>(lds_raw);
+  double* V = A + (wide ? PP * (PP + 1) : MAXP * (MAXP + 1));
+  __shared__ double cs[2 * MAXP];  // at most 64 rotations per round (p <= 128)
   __shared__ int uv[MAXP];
   __shared__ int nrot, anyr;
-  __shared__ int order[MAXP];
+  __shared__ int order[TMAXP];
   const int ld = p | 1;  // odd stride: no LDS bank conflicts in the column sweeps
   for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
     const int i = e / p, j = e % p;
@@ -373,6 +378,7 @@ void Small::eig(hipStream_t st, int PP, double* small, Scalars* sc) {
     case 16: k_eig<16><<<1, WG, 3 * 16 * 17 * 8, st>>>(small, sc); break;
     case 32: k_eig<32><<<1, WG, 3 * 32 * 33 * 8, st>>>(small, sc); break;
     case 64: k_eig<64><<<1, WG, 3 * 64 * 65 * 8, st>>>(small, sc); break;
+    case 128: k_eig<128><<<1, WG, 0, st>>>(small, sc); break;
   }
 }
 void Small::linesearch(hipStream_t st, int PP, const double* red, double* small, Scalars* sc, double* hist,
@@ -382,6 +388,7 @@ void Small::linesearch(hipStream_t st, int PP, const double* red, double* small,
     case 16: k_linesearch<16><<<1, WG, 4 * 16 * 16 * 8, st>>>(red, small, sc, hist, recompute_ax, mc); break;
     case 32: k_linesearch<32><<<1, WG, 4 * 32 * 32 * 8, st>>>(red, small, sc, hist, recompute_ax, mc); break;
     case 64: k_linesearch<64><<<1, WG, 4 * 64 * 64 * 8, st>>>(red, small, sc, hist, recompute_ax, mc); break;
+    case 128: k_linesearch<128><<<1, WG, 0, st>>>(red, small, sc, hist, recompute_ax, mc); break;
   }
 }
 void Small::after_update_grams(hipStream_t st, int PP, const double* red, double* small, Scalars* sc) {
@@ -391,17 +398,18 @@ void Small::after_refresh(hipStream_t st, int PP, const double* red, double* sma
   hipLaunchKernelGGL(k_after_refresh, dim3(1), dim3(WG), 0, st, PP, red, small, sc);
 }
 void Small::chol_inv(hipStream_t st, int PP, int p, const double* red, double* small, int* flag) {
-  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(WG), RITZ_LDS, st, PP, p, red, small, flag);
+  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(WG), PP > PP_LDS_MAX ? 0 : RITZ_LDS, st, PP, p, red, small, flag);
 }
 void Small::transform_cw(hipStream_t st, int PP, double* small, int* flag) {
   switch (PP) {
     case 16: k_transform_cw<16><<<1, WG, 2 * 16 * 16 * 8, st>>>(small, flag); break;
     case 32: k_transform_cw<32><<<1, WG, 2 * 32 * 32 * 8, st>>>(small, flag); break;
     case 64: k_transform_cw<64><<<1, WG, 2 * 64 * 64 * 8, st>>>(small, flag); break;
+    case 128: k_transform_cw<128><<<1, WG, 0, st>>>(small, flag); break;
   }
 }
 void Small::ritz(hipStream_t st, int PP, int p, const double* red, double* small, double* out_vals) {
-  hipLaunchKernelGGL(k_ritz, dim3(1), dim3(WG), RITZ_LDS, st, PP, p, red, small, out_vals);
+  hipLaunchKernelGGL(k_ritz, dim3(1), dim3(WG), PP > PP_LDS_MAX ? 0 : RITZ_LDS, st, PP, p, red, small, out_vals);
 }
 
 }  // namespace gsi

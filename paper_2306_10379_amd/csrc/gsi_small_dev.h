@@ -11,7 +11,9 @@
 namespace gsi {
 
 constexpr double EPS = 2.220446049250313e-16;
-constexpr int MAXP = 64;
+constexpr int MAXP = 64;    // block width of the batched solve and of the one-wave routines below
+constexpr int TMAXP = 128;  // block width of the single-problem float64 path (two terms per lane)
+constexpr int JCODE = 256;  // pair code u * JCODE + v of the Jacobi rotations (u, v < TMAXP)
 
 // Order LDS traffic among the lanes of one wavefront (used where only wave 0 runs).
 __device__ __forceinline__ void wave_sync() {
@@ -100,7 +102,7 @@ __device__ inline int jacobi(int p, int ld, double* A, double* V, double* cs /* 
               const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
               c = 1.0 / sqrt(1.0 + t * t);
               s = t * c;
-              code = u * MAXP + v;
+              code = u * JCODE + v;
               rot = true;
             }
           }
@@ -120,12 +122,12 @@ __device__ inline int jacobi(int p, int ld, double* A, double* V, double* cs /* 
       __syncthreads();
       const int nrot = *nrot_s;
       if (nrot == 0) continue;  // uniform: every thread read the same value after the barrier
-      // rows: A <- J^T A. Lane k of every wave takes column k (p <= 64), the waves take the
-      // rotations in turn: no integer division by the runtime p
-      const int k = threadIdx.x & 63, w0 = threadIdx.x >> 6, nw = blockDim.x >> 6;
-      if (k < p)
+      // rows: A <- J^T A. Lane k of every wave takes columns k, k + 64 (p <= 128), the waves
+      // take the rotations in turn: no integer division by the runtime p
+      const int w0 = threadIdx.x >> 6, nw = blockDim.x >> 6;
+      for (int k = threadIdx.x & 63; k < p; k += 64)
         for (int i = w0; i < nrot; i += nw) {
-          const int u = uv[i] / MAXP, v = uv[i] % MAXP;
+          const int u = uv[i] / JCODE, v = uv[i] % JCODE;
           const double c = cs[2 * i], s = cs[2 * i + 1];
           const double au = A[u * ld + k], av = A[v * ld + k];
           A[u * ld + k] = c * au - s * av;
@@ -133,9 +135,9 @@ __device__ inline int jacobi(int p, int ld, double* A, double* V, double* cs /* 
         }
       __syncthreads();
       // columns: A <- A J, V <- V J (row k)
-      if (k < p)
+      for (int k = threadIdx.x & 63; k < p; k += 64)
         for (int i = w0; i < nrot; i += nw) {
-          const int u = uv[i] / MAXP, v = uv[i] % MAXP;
+          const int u = uv[i] / JCODE, v = uv[i] % JCODE;
           const double c = cs[2 * i], s = cs[2 * i + 1];
           const double au = A[k * ld + u], av = A[k * ld + v];
           A[k * ld + u] = c * au - s * av;
@@ -387,20 +389,22 @@ __device__ inline int jacobi_regs(int p, const double* A0, int lda, double* Abuf
 // ---------------------------------------------------------------- line search (wave 0)
 
 struct Terms {
-  double a[MAXP], b[MAXP], g[MAXP], z[MAXP];
-  int act[MAXP];
+  double a[TMAXP], b[TMAXP], g[TMAXP], z[TMAXP];
+  int act[TMAXP];
 };
 
 // phi'(mu) = - sum over active terms of (z + d mu - b z mu^2) / (1 + b mu^2)^2 (Sec. 5.2,
-// eq. deriv_P), evaluated by wave 0 (lane i holds term i).
+// eq. deriv_P), evaluated by wave 0 (lane i holds terms i and i + 64).
+__device__ inline double dphi_term(const Terms& T, int i, double mu) {
+  const double b = T.b[i], z = T.z[i], d = T.g[i] - T.a[i] * b;
+  const double den = 1.0 + b * mu * mu;
+  return (z + d * mu - b * z * mu * mu) / (den * den);
+}
 __device__ inline double dphi(const Terms& T, int p, double mu) {
   const int l = threadIdx.x & 63;
   double v = 0.0;
-  if (l < p && T.act[l]) {
-    const double b = T.b[l], z = T.z[l], d = T.g[l] - T.a[l] * b;
-    const double den = 1.0 + b * mu * mu;
-    v = (z + d * mu - b * z * mu * mu) / (den * den);
-  }
+  if (l < p && T.act[l]) v = dphi_term(T, l, mu);
+  if (l + 64 < p && T.act[l + 64]) v += dphi_term(T, l + 64, mu);
   return -wave_sum(v);
 }
 
@@ -408,44 +412,54 @@ __device__ inline double dphi(const Terms& T, int p, double mu) {
 // Called by wave 0 only; p terms (padding terms have b = 0), preal the block size for the
 // activity threshold; *evals counts phi' evaluations.
 __device__ inline double get_mu(Terms& T, int p, int preal, int* evals) {
-  const int l = threadIdx.x & 63;
+  // lane l holds terms l and l + 64 (the second only for p > 64)
+  const int l = threadIdx.x & 63, l2 = l + 64;
   const double bl = l < p ? T.b[l] : 0.0;
-  const double bmax = wave_max(bl);
+  const double bl2 = l2 < p ? T.b[l2] : 0.0;
+  const double bmax = wave_max(l2 < p ? fmax(bl, bl2) : bl);
   int ev = 0;
   if (!(bmax > 0.0)) { *evals = 0; return -1.0; }
   const bool act = l < p && bl > preal * EPS * bmax;
+  const bool act2 = l2 < p && bl2 > preal * EPS * bmax;
   if (l < p) T.act[l] = act ? 1 : 0;
+  if (l2 < p) T.act[l2] = act2 ? 1 : 0;
   wave_sync();
   const bool conv = act && T.z[l] > 0.0;
-  if (__ballot(conv) == 0) { *evals = 0; return -1.0; }
+  const bool conv2 = act2 && T.z[l2] > 0.0;
+  if (__ballot(conv || conv2) == 0) { *evals = 0; return -1.0; }
   // f(0) = -sum of active zeta
   const double f0 = dphi(T, p, 0.0);
   ++ev;
   if (!(f0 < 0.0)) { *evals = ev; return -1.0; }
   // branch roots of the convex branches, without cancellation (Sec. 6.1, eqs. derv1/derv2)
-  double xi = INFINITY;
-  if (conv) {
-    const double b = T.b[l], z = T.z[l], d = T.g[l] - T.a[l] * b;
+  auto root = [&](int i) {
+    const double b = T.b[i], z = T.z[i], d = T.g[i] - T.a[i] * b;
     const double s = sqrt(d * d + 4.0 * b * z * z);
-    xi = d < 0.0 ? 2.0 * z / (fabs(d) + s) : (d + s) / (2.0 * b * z);
-  }
-  // phi' at every candidate root, each lane evaluating its own candidate
-  double fxi = -1.0;
-  if (conv) {
+    return d < 0.0 ? 2.0 * z / (fabs(d) + s) : (d + s) / (2.0 * b * z);
+  };
+  // phi' at a candidate root: the sum over every active term
+  auto dphi_all = [&](double x) {
     double acc = 0.0;
     for (int i = 0; i < p; ++i) {
       if (!T.act[i]) continue;
       const double b = T.b[i], z = T.z[i], d = T.g[i] - T.a[i] * b;
-      const double den = 1.0 + b * xi * xi;
-      acc += (z + d * xi - b * z * xi * xi) / (den * den);
+      const double den = 1.0 + b * x * x;
+      acc += (z + d * x - b * z * x * x) / (den * den);
     }
-    fxi = -acc;
-  }
+    return -acc;
+  };
+  // every lane evaluates its own candidates
+  const double xi = conv ? root(l) : INFINITY;
+  const double xi2 = conv2 ? root(l2) : INFINITY;
+  const double fxi = conv ? dphi_all(xi) : -1.0;
+  const double fxi2 = conv2 ? dphi_all(xi2) : -1.0;
   ev += 1;
   // hi: smallest root with phi' >= 0; lo: largest root below hi (or 0)
   double hi = (conv && fxi >= 0.0) ? xi : INFINITY;
+  if (conv2 && fxi2 >= 0.0) hi = fmin(hi, xi2);
   for (int o = 32; o > 0; o >>= 1) hi = fmin(hi, __shfl_xor(hi, o, 64));
   double lo = (conv && xi < hi) ? xi : 0.0;
+  if (conv2 && xi2 < hi) lo = fmax(lo, xi2);
   for (int o = 32; o > 0; o >>= 1) lo = fmax(lo, __shfl_xor(lo, o, 64));
   double fhi;
   if (hi == INFINITY) {
@@ -530,8 +544,45 @@ __device__ inline double get_mu(Terms& T, int p, int preal, int* evals) {
 // which also hold the temporaries of the products (stride PP). Whole workgroup. The
 // arguments cs, uv, nrot, anyr are unused (kept for the callers' shared-memory layout).
 template <int PP>
-__device__ inline int eig_dev(double* small, int p, bool warm, double* lds, double* /*cs*/, int* /*uv*/,
-                              int* /*nrot*/, int* /*anyr*/) {
+__device__ inline int eig_dev(double* small, int p, bool warm, double* lds, double* cs, int* uv, int* nrot,
+                              int* anyr) {
+  if constexpr (PP > PP_LDS_MAX) {
+    // p up to 128: the parallel cyclic Jacobi (jacobi) on matrices in the work area of the
+    // small buffer (lds is that area here): A = V^T S V and the eigenvectors, stride PP
+    double* A = lds;
+    double* Vw = lds + PP * PP;
+    double* T0 = lds + 2 * PP * PP;
+    const double* S = small + S_S * PP * PP;
+    double* Vg = small + S_V * PP * PP;
+    if (warm) {
+      wg_mm<PP>(Vg, true, Vg, false, T0);  // T0 = V^T V
+      __syncthreads();
+      for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) T0[e] = 0.5 * (((e / PP) == (e % PP) ? 3.0 : 0.0) - T0[e]);
+      __syncthreads();
+      wg_mm<PP>(Vg, false, T0, false, Vw);  // Vw = V (3I - V^T V) / 2
+    } else {
+      for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) Vw[e] = (e / PP) == (e % PP) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    wg_mm<PP>(S, false, Vw, false, T0);  // T0 = S V
+    __syncthreads();
+    wg_mm<PP>(Vw, true, T0, false, A);   // A = V^T S V
+    __syncthreads();
+    // symmetric to the last bit before the rotations (they read both triangles)
+    for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) {
+      const int i = e / PP, j = e % PP;
+      T0[e] = 0.5 * (A[i * PP + j] + A[j * PP + i]);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) A[e] = T0[e];
+    __syncthreads();
+    const int sweeps = jacobi(p, PP, A, Vw, cs, uv, nrot, anyr);
+    double* b = small + S_VEC * PP * PP;
+    for (int i = threadIdx.x; i < PP; i += blockDim.x) b[i] = i < p ? fmax(A[i * PP + i], 0.0) : 0.0;
+    for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) Vg[e] = Vw[e];
+    __syncthreads();
+    return sweeps;
+  } else {
   constexpr int LV = PP + 1;
   double* Vv = lds;             // PP x LV
   double* Ab = lds + PP * LV;   // 2 PP^2: jacobi_regs buffers
@@ -563,6 +614,7 @@ __device__ inline int eig_dev(double* small, int p, bool warm, double* lds, doub
   for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) Vg[e] = Vv[(e / PP) * LV + e % PP];
   __syncthreads();
   return sweeps;
+  }
 }
 
 // ---------------------------------------------------------------- line search and retraction factor
@@ -585,7 +637,7 @@ __device__ inline void linesearch_dev(const double* PZr, const double* PYr, doub
   double* C = small + S_C * PP * PP;
   const double* bvec = small + S_VEC * PP * PP;
   for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) V[e] = small[S_V * PP * PP + e];
-  for (int i = threadIdx.x; i < MAXP; i += blockDim.x) terms.b[i] = i < PP ? bvec[i] : 0.0;
+  for (int i = threadIdx.x; i < TMAXP; i += blockDim.x) terms.b[i] = i < PP ? bvec[i] : 0.0;
   __syncthreads();
   // line-search diagonals (Sec. 5.2, eq. CG_linesearch_D) in the basis V; the diagonal of
   // V^T B V only needs the symmetric part of B, so the raw Grams are used

@@ -1,5 +1,6 @@
 // Per-solve device state shared by the kernels and the host driver.
 #pragma once
+#include <stddef.h>
 #include <stdint.h>
 
 namespace gsi {
@@ -56,5 +57,14 @@ enum {
   S_VEC,     // vectors of length PP: b (eigenvalues of P^T P), then scratch
   S_COUNT
 };
+
+// Block widths above 64 (p up to 128, float64): a PP x PP float64 matrix is 128 KB, so the
+// single-workgroup p x p kernels keep their working matrices in a work area after the slots
+// and vectors instead of LDS: [0, 3 PP (PP + 1)) for the eigendecomposition of P^T P, which
+// runs beside the SpMM on a second stream, [4 PP (PP + 1), 8 PP (PP + 1)) for the others.
+constexpr int PP_LDS_MAX = 64;
+constexpr size_t small_work_offset(int PP) { return (size_t)S_COUNT * PP * PP + 8 * (size_t)PP; }
+constexpr size_t small_work_doubles(int PP) { return PP > PP_LDS_MAX ? (size_t)8 * PP * (PP + 1) : 0; }
+constexpr size_t small_doubles(int PP) { return small_work_offset(PP) + small_work_doubles(PP); }
 
 }  // namespace gsi

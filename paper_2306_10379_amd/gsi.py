@@ -197,7 +197,7 @@ def gsi_create(rowptr, colind, vals, n: int, X0, opt: GsiOptions, stream=None):
             raise TypeError(f"{name} must be a contiguous {dt} device tensor")
     _need_shape("rowptr", rowptr, (int(n) + 1,))
     _need_shape("vals", vals, (colind.numel(),))
-    if X0 is not None and 1 <= opt.p <= 64 and int(n) >= 1:  # the library rejects other sizes first
+    if X0 is not None and 1 <= opt.p <= 128 and int(n) >= 1:  # the library rejects other sizes first
         _need_shape("X0", X0, (int(n), int(opt.p)))
     csr = GsiCsr(n=int(n), nnz=int(colind.numel()), rowptr=_dptr(rowptr), colind=_dptr(colind), vals=_dptr(vals))
     h = ctypes.c_void_p()
@@ -220,7 +220,7 @@ def gsi_create_stencil(S: Stencil, dvec, X0, opt: GsiOptions, stream=None):
         raise TypeError("X0 must be a contiguous float64 device tensor")
     if dvec is not None and (not dvec.is_cuda or dvec.dtype != torch.float64 or dvec.numel() != S.n):
         raise TypeError("diag_vec must be a float64 device tensor of n values")
-    if X0 is not None and 1 <= opt.p <= 64 and min(int(S.nx), int(S.ny), int(S.nz)) >= 1:
+    if X0 is not None and 1 <= opt.p <= 128 and min(int(S.nx), int(S.ny), int(S.nz)) >= 1:
         _need_shape("X0", X0, (int(S.n), int(opt.p)))
     st_ = GsiStencil(nx=int(S.nx), ny=int(S.ny), nz=int(S.nz), diag=float(S.diag), off=float(S.off),
                      diag_vec=_dptr(dvec) if dvec is not None else None)

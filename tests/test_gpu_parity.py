@@ -147,6 +147,33 @@ def test_ragged_shapes_smallest_and_largest(n, p, seed):
         assert O.principal_angles(X, ref.X).max() <= 1e-7
 
 
+@pytest.mark.parametrize("n,p,seed", [(3000, 65, 21), (4000, 96, 22), (5000, 128, 23)])
+def test_block_sizes_above_64(n, p, seed):
+    """Blocks of 65 to 128 columns (float64 RCG on a CSR matrix): the passes at width 128 with the
+    p x p factors read through the caches, the p x p solves with their matrices in the work
+    area, two Get_Mu terms per lane and the Jacobi on 128 players. Ritz values equal the
+    oracle's to 1e-10, the bases agree, and the iteration counts match."""
+    A = I.spiked_sparse(n, 4, p, seed, gap=0.3)
+    print(f"wide block n={n} p={p}", flush=True)
+    ref, r, X, hist = _solve_both(A, p, seed, tol=1e-10, max_iter=20000)
+    assert ref.converged and r.status == 0
+    assert np.max(np.abs(r.ritz - ref.theta) / np.maximum(np.abs(ref.theta), 1e-300)) <= 1e-10
+    assert O.principal_angles(X, ref.X).max() <= 1e-7
+    assert np.allclose(X.T @ X, np.eye(p), atol=1e-12)
+    assert abs(r.iters - ref.iters) <= max(3, ref.iters // 20)
+    k = min(20, len(ref.mu))
+    assert np.allclose(hist["mu"][:k], ref.mu[:k], rtol=1e-7)
+
+
+def test_block_size_above_64_rsd():
+    A = I.spiked_sparse(3000, 4, 100, 24, gap=0.3)
+    print("wide block rsd p=100", flush=True)
+    ref, r, X, hist = _solve_both(A, 100, 24, method="rsd", tol=1e-9, max_iter=20000)
+    assert ref.converged and r.status == 0
+    assert np.max(np.abs(r.ritz - ref.theta) / np.maximum(np.abs(ref.theta), 1e-300)) <= 1e-9
+    assert O.principal_angles(X, ref.X).max() <= 1e-6
+
+
 def _true_rho(A, X):
     """rho of a basis recomputed from scratch in float64: ||A X - X sym(X^T A X)||_F / (sqrt(p) ||A||_inf)."""
     S = A.to_scipy()
@@ -902,7 +929,7 @@ def test_stepping_cap_and_argument_errors():
     assert r.status == 0 and np.max(np.abs(r.ritz - refs.theta) / np.abs(refs.theta)) <= 1e-9
     # argument errors come back as statuses with a message, not crashes
     for kw in (dict(p=A.n), dict(p=0), dict(p=4, which=0), dict(p=4, method=7), dict(p=4, precision=9),
-               dict(p=65), dict(p=4, tol=-1.0)):
+               dict(p=129), dict(p=65, precision="mixed"), dict(p=65, method="si"), dict(p=4, tol=-1.0)):
         q = kw.pop("p")
         with pytest.raises(gsi.GsiError):
             gsi.Solver(A, I.start_block(A.n, max(q, 1), 0) if 0 < q <= A.n else X0, q, **kw)
