@@ -139,6 +139,40 @@ def c3_leg(args, gsi, inputs, torch):
         s.close()
     res["speedup_bf16_vs_fp64"] = round(res["fp64"]["s"] / res["bf16"]["s"], 3)
     res["speedup_fp32_vs_fp64"] = round(res["fp64"]["s"] / res["fp32"]["s"], 3)
+    del rowptr, colind, vals, X0d, A
+    # the configured block width, p = 128 (float64: the wider blocks are built for float64 RCG):
+    # the same family with 128 spikes
+    pw = 128
+    log(f"building the spiked sparse matrix n={n} with {pw} spikes")
+    A = inputs.spiked_sparse(n, 12, pw, 7)
+    X0 = inputs.start_block(n, pw, 8)
+    rowptr = torch.as_tensor(A.rowptr.astype(np.int32), device=dev)
+    colind = torch.as_tensor(A.colind, device=dev)
+    vals = torch.as_tensor(A.vals, device=dev)
+    X0d = torch.as_tensor(X0, device=dev)
+    del X0
+    s = gsi.Solver((rowptr, colind, vals, n), X0d, pw, tol=args.tol, max_iter=20000, precision="fp64",
+                   check_every=50)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status, iters = s.solve()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rho = s.residuals()[2]
+    log(f"c3 fp64 p={pw}: {dt:.2f} s, {iters} iterations, status {status}, rho {rho:.3e}")
+    s.set_x0(X0d)
+    s.pass_times(1)
+    s.step(20)
+    pt = s.pass_times(0)
+    ms, cnt = pt["spmm"]
+    avg = ms / max(cnt, 1) * 1e-3
+    compulsory = A.nnz * 12 + 4 * (n + 1) + n * pw * 16
+    gathers = A.nnz * pw * 8
+    per_iter = {k: round(v[0] / max(v[1], 1) * 1e3, 1) for k, v in pt.items() if v[1]}
+    res["fp64_p128"] = {"p": pw, "s": round(dt, 3), "iters": iters, "status": status, "rho": rho,
+                        "spmm_us": round(avg * 1e6, 1), "spmm_gather_GBps": round((gathers + compulsory - n * pw * 8) / avg / 1e9, 1),
+                        "pass_avg_us": per_iter}
+    s.close()
     return res
 
 

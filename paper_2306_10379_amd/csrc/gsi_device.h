@@ -147,6 +147,9 @@ __device__ __forceinline__ void product(const T (&a)[PP / 4], const T* __restric
     const T* mrow = M + AL<T>::kappa(s, g) * PP + c;
 #pragma unroll
     for (int ncb = 0; ncb < PP / 16; ++ncb) acc[ncb] = mfma(a[s], mrow[16 * ncb], acc[ncb]);
+    // at PP = 128 the unrolled loop holds 256 operand loads, which the scheduler would issue
+    // all at once (spilling); one k-step at a time keeps 8 in flight
+    if constexpr (PP > 64) __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -165,6 +168,7 @@ __device__ __forceinline__ void product2(const T (&a1)[PP / 4], const T (&a2)[PP
       acc1[ncb] = mfma(a1[s], b, acc1[ncb]);
       acc2[ncb] = mfma(a2[s], b, acc2[ncb]);
     }
+    if constexpr (PP > 64) __builtin_amdgcn_sched_barrier(0);  // as in product
   }
 }
 
@@ -209,6 +213,8 @@ __device__ __forceinline__ void gram_tile(const T* __restrict__ sA, const T* __r
         acc[q] = mfma(sA[row * PP + 16 * ib + c], sB[row * PP + 16 * jb + c], acc[q]);
       }
     }
+    // at PP = 128 (16 blocks per wave) one block's loads at a time (as in product)
+    if constexpr (PP > 64) __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -272,6 +278,7 @@ __device__ __forceinline__ void gram_tile_sym(const T* __restrict__ sA,
         acc[q] = mfma(sA[row * PP + 16 * ib + c], sA[row * PP + 16 * jb + c], acc[q]);
       }
     }
+    if constexpr (PP > 64) __builtin_amdgcn_sched_barrier(0);  // as in gram_tile
   }
 }
 

@@ -37,6 +37,7 @@ __global__ __launch_bounds__(WG) void k_grad(int64_t n, const T* __restrict__ X,
   static_assert(!WIDE || std::is_same<T, double>::value, "block widths above 64 are float64 only");
   T* sC = reinterpret_cast<T*>(lds_raw);
   T* sG = WIDE ? sC : sC + PP * PP;
+  T* sX = sG + TR * PP;  // WIDE: the tile of X for the Gram (LDS holds the two tiles)
   const T* Cm = WIDE ? reinterpret_cast<const T*>(small + S_C * PP * PP) : sC;
   __shared__ double red[4 * 3];
   const int par = sc->k & 1;
@@ -66,6 +67,12 @@ __global__ __launch_bounds__(WG) void k_grad(int64_t n, const T* __restrict__ X,
     }
     T a[PP / 4];
     load_al<T, PP>(X, row0, n, a);
+    if constexpr (WIDE) {
+      // the X rows into the Gram's LDS tile (read after the barrier below; the previous tile's
+      // reads ended at the previous barrier): lane (lg, lc) holds row lc at columns kappa(s, lg)
+#pragma unroll
+      for (int s = 0; s < PP / 4; ++s) sX[(16 * w + lc) * PP + AL<T>::kappa(s, lg)] = a[s];
+    }
     typename Vec4<T>::type acc[PP / 16];
     zero_acc<T, PP>(acc);
     product<T, PP>(a, Cm, acc);
@@ -104,6 +111,8 @@ __global__ __launch_bounds__(WG) void k_grad(int64_t n, const T* __restrict__ X,
       for (int s = 0; s < TR / 4; ++s)
 #pragma unroll
         for (int q = 0; q < 4; ++q) kacc[q] = mfma(sG[(4 * s + lg) * PP + 16 * q + lc], xcol[s], kacc[q]);
+    } else if constexpr (WIDE) {
+      gram_tile<T, PP>(sX, sG, kacc);
     } else {
       gram_tile<T, PP>(X + t * TR * PP, sG, kacc);
     }
@@ -1415,7 +1424,7 @@ template <typename T, int PP>
 int lds_bytes(Pass pass) {
   const int m = PP * PP * (int)sizeof(T), tile = TR * PP * (int)sizeof(T);
   switch (pass) {
-    case Pass::Grad: return (PP > PP_LDS_MAX ? 0 : m) + tile;
+    case Pass::Grad: return PP > PP_LDS_MAX ? 2 * tile : m + tile;
     case Pass::Dir: return (PP > PP_LDS_MAX ? 0 : m) + tile;
     case Pass::Update: return m;
     case Pass::UpdateGrams: return m + 3 * tile;

@@ -134,8 +134,8 @@ __global__ __launch_bounds__(WG) void k_eig(double* __restrict__ small, Scalars*
   __shared__ double cs[2 * MAXP];
   __shared__ int uv[MAXP];
   __shared__ int nrot, anyr;
-  double* work = PP > PP_LDS_MAX ? small + small_work_offset(PP) : reinterpret_cast<double*>(lds_raw);
-  const int sweeps = eig_dev<PP>(small, sc->p, sc->v_valid != 0, work, cs, uv, &nrot, &anyr);
+  const int sweeps = eig_dev<PP>(small, sc->p, sc->v_valid != 0, reinterpret_cast<double*>(lds_raw), cs, uv, &nrot,
+                                 &anyr);
   if (threadIdx.x == 0) {
     sc->v_valid = 1;
     sc->sweeps = sweeps;
@@ -365,6 +365,10 @@ hipError_t Small::init() {
   if (e == hipSuccess) e = init_pp<16>();
   if (e == hipSuccess) e = init_pp<32>();
   if (e == hipSuccess) e = init_pp<64>();
+  // p up to 128: the Jacobi's matrix in LDS (the other p x p kernels use the work area)
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_eig<128>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            128 * 129 * 8);
   return e;
 }
 void Small::after_grad(hipStream_t st, int PP, const double* red, double* small, Scalars* sc, double* hist, int cond) {
@@ -378,7 +382,7 @@ void Small::eig(hipStream_t st, int PP, double* small, Scalars* sc) {
     case 16: k_eig<16><<<1, WG, 3 * 16 * 17 * 8, st>>>(small, sc); break;
     case 32: k_eig<32><<<1, WG, 3 * 32 * 33 * 8, st>>>(small, sc); break;
     case 64: k_eig<64><<<1, WG, 3 * 64 * 65 * 8, st>>>(small, sc); break;
-    case 128: k_eig<128><<<1, WG, 0, st>>>(small, sc); break;
+    case 128: k_eig<128><<<1, WG, 128 * 129 * 8, st>>>(small, sc); break;
   }
 }
 void Small::linesearch(hipStream_t st, int PP, const double* red, double* small, Scalars* sc, double* hist,

@@ -547,11 +547,15 @@ template <int PP>
 __device__ inline int eig_dev(double* small, int p, bool warm, double* lds, double* cs, int* uv, int* nrot,
                               int* anyr) {
   if constexpr (PP > PP_LDS_MAX) {
-    // p up to 128: the parallel cyclic Jacobi (jacobi) on matrices in the work area of the
-    // small buffer (lds is that area here): A = V^T S V and the eigenvectors, stride PP
+    // p up to 128: the parallel cyclic Jacobi (jacobi) with A = V^T S V in LDS (PP x (PP + 1),
+    // 132 KB) and the eigenvectors and the products' temporaries in the work area of the small
+    // buffer
+    constexpr int LD = PP + 1;
     double* A = lds;
-    double* Vw = lds + PP * PP;
-    double* T0 = lds + 2 * PP * PP;
+    double* work = small + small_work_offset(PP);
+    double* Vw = work;                 // PP x LD
+    double* T0 = work + PP * LD;       // PP x PP
+    double* T1 = work + 2 * PP * LD;   // PP x PP
     const double* S = small + S_S * PP * PP;
     double* Vg = small + S_V * PP * PP;
     if (warm) {
@@ -559,27 +563,27 @@ __device__ inline int eig_dev(double* small, int p, bool warm, double* lds, doub
       __syncthreads();
       for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) T0[e] = 0.5 * (((e / PP) == (e % PP) ? 3.0 : 0.0) - T0[e]);
       __syncthreads();
-      wg_mm<PP>(Vg, false, T0, false, Vw);  // Vw = V (3I - V^T V) / 2
+      wg_mm<PP>(Vg, false, T0, false, T1);  // T1 = V (3I - V^T V) / 2
     } else {
-      for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) Vw[e] = (e / PP) == (e % PP) ? 1.0 : 0.0;
+      for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) T1[e] = (e / PP) == (e % PP) ? 1.0 : 0.0;
     }
     __syncthreads();
-    wg_mm<PP>(S, false, Vw, false, T0);  // T0 = S V
+    wg_mm<PP>(S, false, T1, false, T0);  // T0 = S V
     __syncthreads();
-    wg_mm<PP>(Vw, true, T0, false, A);   // A = V^T S V
+    wg_mm<PP>(T1, true, T0, false, Vw);  // V^T S V (Vw as a stride-PP temporary)
     __syncthreads();
     // symmetric to the last bit before the rotations (they read both triangles)
     for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) {
       const int i = e / PP, j = e % PP;
-      T0[e] = 0.5 * (A[i * PP + j] + A[j * PP + i]);
+      A[i * LD + j] = 0.5 * (Vw[i * PP + j] + Vw[j * PP + i]);
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) A[e] = T0[e];
+    for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) Vw[(e / PP) * LD + e % PP] = T1[e];
     __syncthreads();
-    const int sweeps = jacobi(p, PP, A, Vw, cs, uv, nrot, anyr);
+    const int sweeps = jacobi(p, LD, A, Vw, cs, uv, nrot, anyr);
     double* b = small + S_VEC * PP * PP;
-    for (int i = threadIdx.x; i < PP; i += blockDim.x) b[i] = i < p ? fmax(A[i * PP + i], 0.0) : 0.0;
-    for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) Vg[e] = Vw[e];
+    for (int i = threadIdx.x; i < PP; i += blockDim.x) b[i] = i < p ? fmax(A[i * LD + i], 0.0) : 0.0;
+    for (int e = threadIdx.x; e < PP * PP; e += blockDim.x) Vg[e] = Vw[(e / PP) * LD + e % PP];
     __syncthreads();
     return sweeps;
   } else {
