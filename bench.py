@@ -140,8 +140,7 @@ def c3_leg(args, gsi, inputs, torch):
     res["speedup_bf16_vs_fp64"] = round(res["fp64"]["s"] / res["bf16"]["s"], 3)
     res["speedup_fp32_vs_fp64"] = round(res["fp64"]["s"] / res["fp32"]["s"], 3)
     del rowptr, colind, vals, X0d, A
-    # the configured block width, p = 128 (float64: the wider blocks are built for float64 RCG):
-    # the same family with 128 spikes
+    # the configured block width, p = 128, in the three precisions: the same family with 128 spikes
     pw = 128
     log(f"building the spiked sparse matrix n={n} with {pw} spikes")
     A = inputs.spiked_sparse(n, 12, pw, 7)
@@ -151,28 +150,35 @@ def c3_leg(args, gsi, inputs, torch):
     vals = torch.as_tensor(A.vals, device=dev)
     X0d = torch.as_tensor(X0, device=dev)
     del X0
-    s = gsi.Solver((rowptr, colind, vals, n), X0d, pw, tol=args.tol, max_iter=20000, precision="fp64",
-                   check_every=50)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    status, iters = s.solve()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    rho = s.residuals()[2]
-    log(f"c3 fp64 p={pw}: {dt:.2f} s, {iters} iterations, status {status}, rho {rho:.3e}")
-    s.set_x0(X0d)
-    s.pass_times(1)
-    s.step(20)
-    pt = s.pass_times(0)
-    ms, cnt = pt["spmm"]
-    avg = ms / max(cnt, 1) * 1e-3
-    compulsory = A.nnz * 12 + 4 * (n + 1) + n * pw * 16
-    gathers = A.nnz * pw * 8
-    per_iter = {k: round(v[0] / max(v[1], 1) * 1e3, 1) for k, v in pt.items() if v[1]}
-    res["fp64_p128"] = {"p": pw, "s": round(dt, 3), "iters": iters, "status": status, "rho": rho,
-                        "spmm_us": round(avg * 1e6, 1), "spmm_gather_GBps": round((gathers + compulsory - n * pw * 8) / avg / 1e9, 1),
-                        "pass_avg_us": per_iter}
-    s.close()
+    for prec, sw in (("fp64", 1e-6), ("bf16", 1e-4), ("fp32", 1e-6)):
+        s = gsi.Solver((rowptr, colind, vals, n), X0d, pw, tol=args.tol, max_iter=20000, precision=prec,
+                       check_every=50, switch_tol=sw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        status, iters = s.solve()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        c = s.counters()
+        rho = s.residuals()[2]
+        log(f"c3 {prec} p={pw}: {dt:.2f} s, {iters} iterations (low-precision {c['low_iters']}), status {status}, "
+            f"rho {rho:.3e}")
+        entry = {"p": pw, "s": round(dt, 3), "iters": iters, "low_iters": c["low_iters"], "status": status, "rho": rho}
+        if prec == "fp64":
+            s.set_x0(X0d)
+            s.pass_times(1)
+            s.step(20)
+            pt = s.pass_times(0)
+            ms, cnt = pt["spmm"]
+            avg = ms / max(cnt, 1) * 1e-3
+            compulsory = A.nnz * 12 + 4 * (n + 1) + n * pw * 16
+            gathers = A.nnz * pw * 8
+            entry.update({"spmm_us": round(avg * 1e6, 1),
+                          "spmm_gather_GBps": round((gathers + compulsory - n * pw * 8) / avg / 1e9, 1),
+                          "pass_avg_us": {k: round(v[0] / max(v[1], 1) * 1e3, 1) for k, v in pt.items() if v[1]}})
+        res[f"{prec}_p128"] = entry
+        s.close()
+    res["speedup_bf16_vs_fp64_p128"] = round(res["fp64_p128"]["s"] / res["bf16_p128"]["s"], 3)
+    res["speedup_fp32_vs_fp64_p128"] = round(res["fp64_p128"]["s"] / res["fp32_p128"]["s"], 3)
     return res
 
 

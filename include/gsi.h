@@ -103,8 +103,8 @@ typedef struct {
 } gsi_stencil;
 
 typedef struct {
-  int32_t p;            /* block size, 1 <= p < n; p <= 128 for float64 RCG / RSD on a CSR matrix
-                           with explicit_c = 0, p <= 64 otherwise (GSI_EUNSUPPORTED above) */
+  int32_t p;            /* block size, 1 <= p < n; p <= 128 for RCG / RSD on a CSR matrix with
+                           explicit_c = 0 (any precision), p <= 64 otherwise (GSI_EUNSUPPORTED) */
   int32_t which;        /* +1 largest eigenvalues, -1 smallest (the solver runs on -A) */
   int32_t method;       /* gsi_method */
   int32_t precision;    /* gsi_precision */

@@ -19,6 +19,11 @@ namespace gsi {
 constexpr int WG = 256;      // threads per workgroup
 constexpr int TR = 64;       // rows per workgroup tile (4 waves x 16 rows)
 
+// Whether a PP x PP factor of element type T is too wide for LDS beside a tile (above 64 KB:
+// float64 at PP = 128); such passes read it through the caches.
+template <typename T, int PP>
+constexpr bool factor_wide() { return (size_t)PP * PP * sizeof(T) > 65536; }
+
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));

@@ -27,8 +27,8 @@ using namespace gsi;
 
 namespace {
 
-constexpr int MAXP = 64;    // widest block of the mixed-precision, SI, stencil and explicit-C paths
-constexpr int MAXP_F64 = 128;  // widest block of plain float64 RCG / RSD on a CSR matrix
+constexpr int MAXP = 64;    // widest block of the SI, stencil and explicit-C paths
+constexpr int MAXP_F64 = 128;  // widest block of RCG / RSD on a CSR matrix (float64 or mixed)
 
 // Padded block width: the kernels are built for 16, 32 and 64 columns; the padding
 // columns stay zero.
@@ -231,9 +231,7 @@ void dispatch_pp(int PP, F&& f) {
     case 16: f(std::integral_constant<int, 16>()); break;
     case 32: f(std::integral_constant<int, 32>()); break;
     case 64: f(std::integral_constant<int, 64>()); break;
-    case 128:  // float64 only (p above 64: plain float64 RCG / RSD)
-      if constexpr (std::is_same<T, double>::value) f(std::integral_constant<int, 128>());
-      break;
+    case 128: f(std::integral_constant<int, 128>()); break;  // p above 64: RCG / RSD on a CSR matrix
     default: break;
   }
 }
@@ -875,8 +873,8 @@ gsi_status create_impl(gsi_handle* out, const gsi_csr* A, const gsi_stencil* S, 
   }
   if (opt->p < 1 || opt->p >= n_op) return bail(GSI_EINVAL, "need 1 <= p < n");
   if (opt->p > MAXP_F64) return bail(GSI_EUNSUPPORTED, "p above 128 is not built");
-  if (opt->p > MAXP && (S || opt->precision != GSI_FP64 || opt->method == GSI_SI || opt->explicit_c))
-    return bail(GSI_EUNSUPPORTED, "p above 64 is built for float64 RCG / RSD on a CSR matrix without explicit_c");
+  if (opt->p > MAXP && (S || opt->method == GSI_SI || opt->explicit_c))
+    return bail(GSI_EUNSUPPORTED, "p above 64 is built for RCG / RSD on a CSR matrix without explicit_c");
   if (opt->which != 1 && opt->which != -1) return bail(GSI_EINVAL, "which must be +1 or -1");
   if (opt->method != GSI_RSD && opt->method != GSI_RCG && opt->method != GSI_SI)
     return bail(GSI_EINVAL, "unknown method");
@@ -938,8 +936,7 @@ gsi_status create_impl(gsi_handle* out, const gsi_csr* A, const gsi_stencil* S, 
   dispatch_pp<double>(h->PP, [&](auto PPc) {
     constexpr int PP = decltype(PPc)::value;
     if (ke == hipSuccess) ke = Kernels<double, PP>::init();
-    if constexpr (PP <= MAXP)
-      if (ke == hipSuccess) ke = Kernels<float, PP>::init();
+    if (ke == hipSuccess) ke = Kernels<float, PP>::init();
   });
   if (ke != hipSuccess) return bail(GSI_EDEVICE, std::string("kernel attributes: ") + hipGetErrorString(ke));
   hipStream_t st = h->st;

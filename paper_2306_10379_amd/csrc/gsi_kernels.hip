@@ -31,10 +31,9 @@ __global__ __launch_bounds__(WG) void k_grad(int64_t n, const T* __restrict__ X,
   if (sc->done) return;
   if (cond == GRAD_PENDING && sc->grad_ready) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  // the p x p factor in LDS up to PP = 64; above (128 KB in float64) it is read from the
-  // small buffer through the caches and LDS holds only the Gram's tile
-  constexpr bool WIDE = PP > PP_LDS_MAX;
-  static_assert(!WIDE || std::is_same<T, double>::value, "block widths above 64 are float64 only");
+  // the p x p factor in LDS up to 64 KB; a wider one (float64 at PP = 128: 128 KB) is read
+  // from the small buffer through the caches and LDS holds the Gram's tiles
+  constexpr bool WIDE = factor_wide<T, PP>();
   T* sC = reinterpret_cast<T*>(lds_raw);
   T* sG = WIDE ? sC : sC + PP * PP;
   T* sX = sG + TR * PP;  // WIDE: the tile of X for the Gram (LDS holds the two tiles)
@@ -156,9 +155,8 @@ __global__ __launch_bounds__(WG) void k_dir(int64_t n, const T* __restrict__ X, 
                                             float* __restrict__ P32) {
   if (sc->done) return;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  // the p x p factor in LDS up to PP = 64, read through the caches above (as in k_grad)
-  constexpr bool WIDE = PP > PP_LDS_MAX;
-  static_assert(!WIDE || std::is_same<T, double>::value, "block widths above 64 are float64 only");
+  // the p x p factor in LDS up to 64 KB, read through the caches above (as in k_grad)
+  constexpr bool WIDE = factor_wide<T, PP>();
   T* sK = reinterpret_cast<T*>(lds_raw);
   T* sP = WIDE ? sK : sK + PP * PP;
   const T* Km = WIDE ? reinterpret_cast<const T*>(small + S_KD * PP * PP) : sK;
@@ -1424,8 +1422,8 @@ template <typename T, int PP>
 int lds_bytes(Pass pass) {
   const int m = PP * PP * (int)sizeof(T), tile = TR * PP * (int)sizeof(T);
   switch (pass) {
-    case Pass::Grad: return PP > PP_LDS_MAX ? 2 * tile : m + tile;
-    case Pass::Dir: return (PP > PP_LDS_MAX ? 0 : m) + tile;
+    case Pass::Grad: return factor_wide<T, PP>() ? 2 * tile : m + tile;
+    case Pass::Dir: return (factor_wide<T, PP>() ? 0 : m) + tile;
     case Pass::Update: return m;
     case Pass::UpdateGrams: return m + 3 * tile;
     case Pass::UpdateGrad: return 2 * m;
@@ -1662,6 +1660,7 @@ template struct Kernels<double, 16>;
 template struct Kernels<double, 32>;
 template struct Kernels<double, 64>;
 template struct Kernels<double, 128>;
+template struct Kernels<float, 128>;
 template struct Kernels<float, 16>;
 template struct Kernels<float, 32>;
 template struct Kernels<float, 64>;

@@ -174,6 +174,20 @@ def test_block_size_above_64_rsd():
     assert O.principal_angles(X, ref.X).max() <= 1e-6
 
 
+@pytest.mark.parametrize("precision,p,sw", [("mixed", 96, 1e-5), ("bf16", 80, 1e-4)])
+def test_block_sizes_above_64_mixed(precision, p, sw):
+    """The low-precision engines at width 128 (float32 factors fit LDS there), then the float64
+    phase: the basis meets the tolerance recomputed in float64 and the Ritz values equal the
+    oracle's."""
+    A = I.spiked_sparse(4000, 6, p, 25, gap=0.3)
+    print(f"wide block {precision} p={p}", flush=True)
+    ref, r, X, hist = _solve_both(A, p, 25, tol=1e-10, max_iter=20000, precision=precision, switch_tol=sw)
+    assert ref.converged and r.status == 0
+    assert r.counters["low_iters"] > 0
+    assert _true_rho(A, X) <= 1.05e-10
+    assert np.max(np.abs(r.ritz - ref.theta) / np.maximum(np.abs(ref.theta), 1e-300)) <= 1e-10
+
+
 def _true_rho(A, X):
     """rho of a basis recomputed from scratch in float64: ||A X - X sym(X^T A X)||_F / (sqrt(p) ||A||_inf)."""
     S = A.to_scipy()
@@ -929,7 +943,7 @@ def test_stepping_cap_and_argument_errors():
     assert r.status == 0 and np.max(np.abs(r.ritz - refs.theta) / np.abs(refs.theta)) <= 1e-9
     # argument errors come back as statuses with a message, not crashes
     for kw in (dict(p=A.n), dict(p=0), dict(p=4, which=0), dict(p=4, method=7), dict(p=4, precision=9),
-               dict(p=129), dict(p=65, precision="mixed"), dict(p=65, method="si"), dict(p=4, tol=-1.0)):
+               dict(p=129), dict(p=65, explicit_c=1), dict(p=65, method="si"), dict(p=4, tol=-1.0)):
         q = kw.pop("p")
         with pytest.raises(gsi.GsiError):
             gsi.Solver(A, I.start_block(A.n, max(q, 1), 0) if 0 < q <= A.n else X0, q, **kw)
