@@ -30,20 +30,17 @@ __global__ __launch_bounds__(WG) void k_grad(int64_t n, const T* __restrict__ X,
                                              double* __restrict__ partials, int cond) {
   if (sc->done) return;
   if (cond == GRAD_PENDING && sc->grad_ready) return;
+  // the p x p factor in LDS (a wider one runs k_grad_wide)
+  static_assert(!factor_wide<T, PP>(), "k_grad_wide takes this width");
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  // the p x p factor in LDS up to 64 KB; a wider one (float64 at PP = 128: 128 KB) is read
-  // from the small buffer through the caches and LDS holds the Gram's tiles
-  constexpr bool WIDE = factor_wide<T, PP>();
   T* sC = reinterpret_cast<T*>(lds_raw);
-  T* sG = WIDE ? sC : sC + PP * PP;
-  T* sX = sG + TR * PP;  // WIDE: the tile of X for the Gram (LDS holds the two tiles)
-  const T* Cm = WIDE ? reinterpret_cast<const T*>(small + S_C * PP * PP) : sC;
+  T* sG = sC + PP * PP;
   __shared__ double red[4 * 3];
   const int par = sc->k & 1;
   T* G = par ? G1 : G0;
   const T* Gold = par ? G0 : G1;
   const bool have_old = sc->k > 0;
-  if (!WIDE) load_matrix_lds<T, PP>(sC, small + S_C * PP * PP);
+  load_matrix_lds<T, PP>(sC, small + S_C * PP * PP);
   __syncthreads();
   const int w = threadIdx.x >> 6;
   const int64_t ntiles = (n + TR - 1) / TR;
@@ -66,15 +63,9 @@ __global__ __launch_bounds__(WG) void k_grad(int64_t n, const T* __restrict__ X,
     }
     T a[PP / 4];
     load_al<T, PP>(X, row0, n, a);
-    if constexpr (WIDE) {
-      // the X rows into the Gram's LDS tile (read after the barrier below; the previous tile's
-      // reads ended at the previous barrier): lane (lg, lc) holds row lc at columns kappa(s, lg)
-#pragma unroll
-      for (int s = 0; s < PP / 4; ++s) sX[(16 * w + lc) * PP + AL<T>::kappa(s, lg)] = a[s];
-    }
     typename Vec4<T>::type acc[PP / 16];
     zero_acc<T, PP>(acc);
-    product<T, PP>(a, Cm, acc);
+    product<T, PP>(a, sC, acc);
     T y[PP / 16][4], g[PP / 16][4];
     load_rl<T, PP>(Y, row0, n, y);
 #pragma unroll
@@ -110,8 +101,6 @@ __global__ __launch_bounds__(WG) void k_grad(int64_t n, const T* __restrict__ X,
       for (int s = 0; s < TR / 4; ++s)
 #pragma unroll
         for (int q = 0; q < 4; ++q) kacc[q] = mfma(sG[(4 * s + lg) * PP + 16 * q + lc], xcol[s], kacc[q]);
-    } else if constexpr (WIDE) {
-      gram_tile<T, PP>(sX, sG, kacc);
     } else {
       gram_tile<T, PP>(X + t * TR * PP, sG, kacc);
     }
@@ -154,12 +143,11 @@ __global__ __launch_bounds__(WG) void k_dir(int64_t n, const T* __restrict__ X, 
                                             double* __restrict__ partials, uint16_t* __restrict__ P16,
                                             float* __restrict__ P32) {
   if (sc->done) return;
+  // the p x p factor in LDS (a wider one runs k_dir_wide)
+  static_assert(!factor_wide<T, PP>(), "k_dir_wide takes this width");
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  // the p x p factor in LDS up to 64 KB, read through the caches above (as in k_grad)
-  constexpr bool WIDE = factor_wide<T, PP>();
   T* sK = reinterpret_cast<T*>(lds_raw);
-  T* sP = WIDE ? sK : sK + PP * PP;
-  const T* Km = WIDE ? reinterpret_cast<const T*>(small + S_KD * PP * PP) : sK;
+  T* sP = sK + PP * PP;
   __shared__ double red[4];
   const int par = sc->k & 1;
   const T* G = par ? G1 : G0;
@@ -167,7 +155,7 @@ __global__ __launch_bounds__(WG) void k_dir(int64_t n, const T* __restrict__ X, 
   const T* Pold = par ? P0 : P1;
   const T beta = (T)sc->beta_pr;
   const bool use_old = sc->beta_pr != 0.0;
-  if (!WIDE) load_matrix_lds<T, PP>(sK, small + S_KD * PP * PP);
+  load_matrix_lds<T, PP>(sK, small + S_KD * PP * PP);
   __syncthreads();
   const int w = threadIdx.x >> 6;
   const int64_t ntiles = (n + TR - 1) / TR;
@@ -183,7 +171,7 @@ __global__ __launch_bounds__(WG) void k_dir(int64_t n, const T* __restrict__ X, 
     load_al<T, PP>(X, row0, n, a);
     typename Vec4<T>::type acc[PP / 16];
     zero_acc<T, PP>(acc);
-    product<T, PP>(a, Km, acc);
+    product<T, PP>(a, sK, acc);
     T g[PP / 16][4], p[PP / 16][4];
     load_rl<T, PP>(G, row0, n, g);
     if (use_old) {
@@ -238,6 +226,365 @@ __global__ __launch_bounds__(WG) void k_dir(int64_t n, const T* __restrict__ X, 
   if (l == 0) red[w] = s;
   __syncthreads();
   if (threadIdx.x == 0) out[PP * PP] = red[0] + red[1] + red[2] + red[3];
+}
+
+// ---------------------------------------------------------------- wide blocks (float64, PP = 128)
+// At PP = 128 the float64 factor (128 KB) does not fit LDS beside a tile, and a wave that holds
+// 16 rows of every operand across 128 columns runs out of registers. The gradient and direction
+// passes there use workgroups of 8 waves over the same 64-row tiles: the tile of X is staged in
+// LDS, wave w forms column block w (16 columns) of the product for all 64 rows, reading the
+// factor's column block through the caches, and in the Gram that column block, still in the
+// wave's registers in the D layout, is the right operand of the blocks (ib, w). An LDS tile
+// keeps its rows 144 elements apart, with the 16-byte granules of a row permuted by row
+// (wide_at), so that both the product's reads (16 rows, one granule each) and the Gram's (4
+// consecutive rows, 16 columns each) fall on distinct banks.
+constexpr int WGW = 2 * WG;  // threads per workgroup of the wide passes
+constexpr int WPP = 128;     // their padded width
+constexpr int WLD = 144;     // LDS row stride: odd rows start half a bank period (128 B) on
+
+// LDS element of (row, col): 16-byte granule k of the row within its group of 8 is stored at
+// k ^ ((row / 2) mod 8). The permutation depends on row mod 16 and moves elements within
+// aligned groups of 16 columns, so wide_at(row + 16 a, col + 16 b) = wide_at(row, col) +
+// 16 a WLD + 16 b: the accesses below take a lane base from wide_at and constant offsets.
+__device__ __forceinline__ int wide_at(int row, int col) { return row * WLD + (col ^ (2 * ((row >> 1) & 7))); }
+constexpr int WTILE = TR * WLD;  // elements of an LDS tile
+
+// Global load / store at a wave-uniform base plus a per-lane element offset of 32 bits, the
+// offset made opaque where it is formed: each access takes one offset register at its point
+// of use, where 64-bit addresses formed ahead for a whole tile would hold many.
+template <typename V>
+__device__ __forceinline__ V wld(const V* base, int off) {
+  asm volatile("" : "+v"(off));
+  return *(const __attribute__((address_space(1))) V*)(reinterpret_cast<const char*>(base) +
+                                                       (uint32_t)(off * (int)sizeof(V)));
+}
+template <typename V>
+__device__ __forceinline__ void wst(V* base, int off, V v) {
+  asm volatile("" : "+v"(off));
+  *(__attribute__((address_space(1))) V*)(reinterpret_cast<char*>(base) + (uint32_t)(off * (int)sizeof(V))) = v;
+}
+
+// The whole tile t of a tall block (its rows past n are zero rows of the allocation), 16 bytes
+// per lane, and its store into an LDS tile (a wave writes one row per step).
+// Parts [m0, m0 + M) of the 8 granules per lane (the first half, the second half or all).
+template <int M = 8>
+__device__ __forceinline__ void wide_load(int tid, const double* __restrict__ A, int64_t t, d2 (&v)[M], int m0 = 0) {
+  const d2* src = reinterpret_cast<const d2*>(A + t * TR * WPP);
+#pragma unroll
+  for (int m = 0; m < M; ++m) v[m] = wld(src, tid + WGW * (m0 + m));
+}
+template <int M = 8>
+__device__ __forceinline__ void wide_store(int tid, double* __restrict__ s, const d2 (&v)[M], int m0 = 0) {
+  // granule m of the lane: row tid / 64 + 8 m, column 2 (tid mod 64)
+  const int b0 = wide_at(tid >> 6, 2 * (tid & 63)), b1 = wide_at((tid >> 6) + 8, 2 * (tid & 63));
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int mm = m0 + m;
+    *reinterpret_cast<d2*>(s + ((mm & 1) ? b1 : b0) + 16 * (mm >> 1) * WLD) = v[m];
+  }
+}
+
+// The wave's column block of the tile's 64 rows in the D layout: v[rg][r] is element
+// (row0 + 16 rg + rowof(g, r), 16 w + c). Loads read whole tiles (rows past n are zero rows of
+// the allocation); stores skip rows past n.
+__device__ __forceinline__ void wide_load_cols(int tid, const double* __restrict__ B, int64_t row0, double (&v)[4][4]) {
+  const int w = tid >> 6, l = tid & 63, g = l >> 4, c = l & 15;
+  const double* b = B + row0 * WPP;
+  const int o = rowof<double>(g, 0) * WPP + 16 * w + c;
+#pragma unroll
+  for (int rg = 0; rg < 4; ++rg)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[rg][r] = wld(b, o + (16 * rg + 4 * r) * WPP);
+}
+__device__ __forceinline__ void wide_store_cols(int tid, double* __restrict__ B, int64_t row0, int64_t n,
+                                                const double (&v)[4][4]) {
+  const int w = tid >> 6, l = tid & 63, g = l >> 4, c = l & 15;
+  double* b = B + row0 * WPP;
+  const int o = rowof<double>(g, 0) * WPP + 16 * w + c;
+  const int64_t left = n - row0 - rowof<double>(g, 0);  // rows of this lane group below n
+#pragma unroll
+  for (int rg = 0; rg < 4; ++rg)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (16 * rg + 4 * r < left) wst(b, o + (16 * rg + 4 * r) * WPP, v[rg][r]);
+}
+
+// acc[rg] += (LDS tile) * M, the wave's column block: k-steps in pairs, lane group g taking
+// contraction indices 8 j + 2 g and 8 j + 2 g + 1 of pair j (one 16-byte LDS read per row
+// group), the factor's elements loaded two pairs ahead.
+__device__ __forceinline__ void wide_product(int tid, const double* __restrict__ s, const double* __restrict__ M,
+                                             d4 (&acc)[4]) {
+  const int w = tid >> 6, l = tid & 63, g = l >> 4, c = l & 15;
+  const int mc = 16 * w + c + 2 * g * WPP;
+  // element (16 rg + c, 8 j + 2 g) of the tile: la0 / la1 (j even / odd) + 16 rg WLD + 16 (j / 2)
+  const int la0 = wide_at(c, 2 * g), la1 = wide_at(c, 8 + 2 * g);
+  double bq[3][2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    bq[j][0] = wld(M, mc + 8 * j * WPP);
+    bq[j][1] = wld(M, mc + (8 * j + 1) * WPP);
+  }
+#pragma unroll
+  for (int j = 0; j < WPP / 8; ++j) {
+    if (j + 2 < WPP / 8) {
+      bq[(j + 2) % 3][0] = wld(M, mc + 8 * (j + 2) * WPP);
+      bq[(j + 2) % 3][1] = wld(M, mc + (8 * (j + 2) + 1) * WPP);
+    }
+    d2 a[4];
+#pragma unroll
+    for (int rg = 0; rg < 4; ++rg)
+      a[rg] = *reinterpret_cast<const d2*>(s + ((j & 1) ? la1 : la0) + 16 * rg * WLD + 16 * (j >> 1));
+#pragma unroll
+    for (int rg = 0; rg < 4; ++rg) acc[rg] = mfma(a[rg].x, bq[j % 3][0], acc[rg]);
+#pragma unroll
+    for (int rg = 0; rg < 4; ++rg) acc[rg] = mfma(a[rg].y, bq[j % 3][1], acc[rg]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Lane bases of the Gram's A operand: element (16 rg + rowof(g, r), 16 ib + c) of an LDS tile
+// is at lb[r] + 16 rg WLD + 16 ib.
+__device__ __forceinline__ void wide_gram_bases(int tid, int (&lb)[4]) {
+  const int l = tid & 63, g = l >> 4, c = l & 15;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) lb[r] = wide_at(rowof<double>(g, r), c);
+}
+// One step (rows 16 rg + 4 r + 0..3) of a Gram block (ib, w): A = the LDS tile's columns
+// 16 ib .., B = the wave's column block b (D layout).
+__device__ __forceinline__ d4 wide_gram_step(const int (&lb)[4], const double* __restrict__ s, int rg, int r, int ib,
+                                             double b, d4 acc) {
+  return mfma(s[lb[r] + 16 * rg * WLD + 16 * ib], b, acc);
+}
+
+// Gradient pass at PP = 128 (as k_grad): G, <G, G>, <G_old, G>, ||G||_inf and K = X^T G, the
+// wave's blocks (ib, w) of K. The X tiles are double-buffered in LDS (the next one is loaded
+// during the current one), so one barrier per tile; the row sums of |G| of the 8 column blocks
+// meet in LDS and wave 0 takes their maximum one tile later.
+template <typename T, int PP>
+__global__ __launch_bounds__(WGW) void k_grad_wide(int64_t n, const T* __restrict__ X, const T* __restrict__ Y,
+                                                  T* __restrict__ G0, T* __restrict__ G1,
+                                                  const double* __restrict__ small, const Scalars* __restrict__ sc,
+                                                  double* __restrict__ partials, int cond) {
+  static_assert(std::is_same<T, double>::value && PP == WPP, "the wide passes are float64 at PP = 128");
+  if (sc->done) return;
+  if (cond == GRAD_PENDING && sc->grad_ready) return;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  double* sX = reinterpret_cast<double*>(lds_raw);  // two tiles
+  double* rsum = sX + 2 * WTILE;                    // [2][8][TR]
+  __shared__ double red[8 * 3];
+  const double* Cm = small + S_C * PP * PP;
+  const int par = sc->k & 1;
+  double* G = par ? G1 : G0;
+  const double* Gold = par ? G0 : G1;
+  const bool have_old = sc->k > 0;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+  const int64_t ntiles = (n + TR - 1) / TR;
+  int64_t t0, t1;
+  tile_range(ntiles, t0, t1);
+  d4 kacc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) kacc[q] = d4{0, 0, 0, 0};
+  double gg = 0.0, gdot = 0.0, ginf = 0.0;
+  d2 xn[8];
+  if (t0 < t1) {
+    wide_load(threadIdx.x, X, t0, xn);
+    wide_store(threadIdx.x, sX, xn);
+  }
+  for (int64_t t = t0; t < t1; ++t) {
+    // the lane's offsets are formed anew in every tile (held across the loop they would take
+    // the registers the tile needs)
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int buf = (int)((t - t0) & 1);
+    const double* sx = sX + buf * WTILE;
+    // tile t is in sx; every wave is past the previous tile (its Gram's reads of the other
+    // buffer, its row sums)
+    __syncthreads();
+    if (w == 0 && t > t0) {
+      const double* rs = rsum + (buf ^ 1) * 8 * TR;
+      double v = 0.0;
+#pragma unroll
+      for (int ww = 0; ww < 8; ++ww) v += rs[ww * TR + l];
+      ginf = fmax(ginf, v);
+    }
+    const int64_t row0 = t * TR;
+    double y[4][4], go[4][4];
+    wide_load_cols(tid, Y, row0, y);
+    if (have_old) wide_load_cols(tid, Gold, row0, go);
+    d4 acc[4];
+#pragma unroll
+    for (int rg = 0; rg < 4; ++rg) acc[rg] = d4{0, 0, 0, 0};
+    wide_product(tid, sx, Cm, acc);
+    // G = X C - Y in place of y
+    double* rs = rsum + buf * 8 * TR + w * TR;
+#pragma unroll
+    for (int rg = 0; rg < 4; ++rg)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double gv = acc[rg][r] - y[rg][r];
+        y[rg][r] = gv;
+        gg += gv * gv;
+        if (have_old) gdot += go[rg][r] * gv;
+        const double a = group16_sum(fabs(gv));
+        if (c == 0) rs[16 * rg + rowof<double>(g, r)] = a;
+      }
+    wide_store_cols(tid, G, row0, n, y);
+    if (t + 1 < t1) wide_load(tid, X, t + 1, xn);
+    // K += X^T G over the tile
+    int lb[4];
+    wide_gram_bases(tid, lb);
+#pragma unroll
+    for (int rg = 0; rg < 4; ++rg)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+#pragma unroll
+        for (int ib = 0; ib < 8; ++ib) kacc[ib] = wide_gram_step(lb, sx, rg, r, ib, y[rg][r], kacc[ib]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    if (t + 1 < t1) wide_store(tid, sX + (buf ^ 1) * WTILE, xn);
+  }
+  __syncthreads();
+  if (w == 0 && t1 > t0) {
+    const double* rs = rsum + (int)((t1 - 1 - t0) & 1) * 8 * TR;
+    double v = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < 8; ++ww) v += rs[ww * TR + l];
+    ginf = fmax(ginf, v);
+  }
+  const int64_t nv = PP * PP + 3;
+  double* out = partials + (int64_t)blockIdx.x * nv;
+#pragma unroll
+  for (int ib = 0; ib < 8; ++ib)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[(16 * ib + rowof<double>(g, r)) * PP + 16 * w + c] = kacc[ib][r];
+  const double s0 = wave_sum(gg), s1 = wave_sum(gdot), s2 = wave_max(ginf);
+  if (l == 0) {
+    red[w * 3 + 0] = s0;
+    red[w * 3 + 1] = s1;
+    red[w * 3 + 2] = s2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0, m = 0.0;
+    for (int ww = 0; ww < 8; ++ww) {
+      a += red[ww * 3 + 0];
+      b += red[ww * 3 + 1];
+      m = fmax(m, red[ww * 3 + 2]);
+    }
+    out[PP * PP + 0] = a;
+    out[PP * PP + 1] = b;
+    out[PP * PP + 2] = m;
+  }
+}
+
+// Direction pass at PP = 128 (as k_dir): P, <G, P> and S = P^T P. The blocks of S are shared
+// out by pairs of column blocks {i, i + d mod 8}: wave w forms (w + d mod 8, w) for d = 0 .. 3
+// and, when w < 4, d = 4 (4 or 5 blocks each, 36 in all), and writes the mirror of each
+// off-diagonal one.
+template <typename T, int PP>
+__global__ __launch_bounds__(WGW) void k_dir_wide(int64_t n, const T* __restrict__ X, const T* __restrict__ G0,
+                                                 const T* __restrict__ G1, T* __restrict__ P0, T* __restrict__ P1,
+                                                 const double* __restrict__ small, const Scalars* __restrict__ sc,
+                                                 double* __restrict__ partials, uint16_t* __restrict__ P16,
+                                                 float* __restrict__ P32) {
+  static_assert(std::is_same<T, double>::value && PP == WPP, "the wide passes are float64 at PP = 128");
+  if (sc->done) return;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  double* sX = reinterpret_cast<double*>(lds_raw);
+  double* sP = sX + WTILE;
+  __shared__ double red[8];
+  const double* Km = small + S_KD * PP * PP;
+  const int par = sc->k & 1;
+  const double* G = par ? G1 : G0;
+  double* P = par ? P1 : P0;
+  const double* Pold = par ? P0 : P1;
+  const double beta = sc->beta_pr;
+  const bool use_old = beta != 0.0;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+  const int nd = w < 4 ? 5 : 4;
+  const int64_t ntiles = (n + TR - 1) / TR;
+  int64_t t0, t1;
+  tile_range(ntiles, t0, t1);
+  d4 sacc[5];
+#pragma unroll
+  for (int d = 0; d < 5; ++d) sacc[d] = d4{0, 0, 0, 0};
+  double gp = 0.0;
+  d2 xn[8];
+  if (t0 < t1) wide_load(threadIdx.x, X, t0, xn);
+  for (int64_t t = t0; t < t1; ++t) {
+    int tid = threadIdx.x;  // offsets formed anew in every tile (as in k_grad_wide)
+    asm volatile("" : "+v"(tid));
+    // every wave is past the previous tile's reads of sX and sP
+    __syncthreads();
+    wide_store(tid, sX, xn);
+    const int64_t row0 = t * TR;
+    double gv[4][4], p[4][4];
+    wide_load_cols(tid, G, row0, gv);
+    if (use_old) wide_load_cols(tid, Pold, row0, p);
+    __syncthreads();
+    d4 acc[4];
+#pragma unroll
+    for (int rg = 0; rg < 4; ++rg) acc[rg] = d4{0, 0, 0, 0};
+    wide_product(tid, sX, Km, acc);
+    int lb[4];
+    wide_gram_bases(tid, lb);
+#pragma unroll
+    for (int rg = 0; rg < 4; ++rg)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double pv = use_old ? gv[rg][r] + beta * p[rg][r] - acc[rg][r] : gv[rg][r] - acc[rg][r];
+        p[rg][r] = pv;
+        gp += gv[rg][r] * pv;
+        sP[lb[r] + 16 * rg * WLD + 16 * w] = pv;
+      }
+    wide_store_cols(tid, P, row0, n, p);
+    if (P16 || P32) {
+      // bfloat16 / float32 copies of P for the SpMM of the mixed modes
+#pragma unroll
+      for (int rg = 0; rg < 4; ++rg)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = row0 + 16 * rg + rowof<double>(g, r);
+          if (row < n) {
+            if (P16) gst(P16 + row * PP + 16 * w + c, bf16_round((float)p[rg][r]));
+            if (P32) gst(P32 + row * PP + 16 * w + c, (float)p[rg][r]);
+          }
+        }
+    }
+    if (t + 1 < t1) wide_load(tid, X, t + 1, xn);
+    __syncthreads();
+#pragma unroll
+    for (int d = 0; d < 5; ++d)
+      if (d < nd) {
+        const int ib = (w + d) & 7;
+#pragma unroll
+        for (int rg = 0; rg < 4; ++rg)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) sacc[d] = wide_gram_step(lb, sP, rg, r, ib, p[rg][r], sacc[d]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+  }
+  const int64_t nv = PP * PP + 1;
+  double* out = partials + (int64_t)blockIdx.x * nv;
+#pragma unroll
+  for (int d = 0; d < 5; ++d)
+    if (d < nd) {
+      const int ib = (w + d) & 7;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * ib + rowof<double>(g, r), j = 16 * w + c;
+        out[i * PP + j] = sacc[d][r];
+        if (d) out[j * PP + i] = sacc[d][r];
+      }
+    }
+  const double s = wave_sum(gp);
+  if (l == 0) red[w] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0;
+    for (int ww = 0; ww < 8; ++ww) a += red[ww];
+    out[PP * PP] = a;
+  }
 }
 
 // ---------------------------------------------------------------- retraction pass
@@ -1147,6 +1494,86 @@ __global__ __launch_bounds__(WG) void k_gram(int64_t n, const T* __restrict__ A0
   }
 }
 
+// A^T B1 and (TWO) A^T B2 at PP = 128 in float64, with the workgroups of the wide passes: the
+// A tiles double-buffered in LDS as in k_grad_wide, wave w holding column block w of B1 and B2
+// in the D layout and forming the blocks (ib, w) of both Grams. The B values of a row group
+// are replaced by the next tile's as soon as its MFMAs have issued (the last tile reloads
+// itself, unused), and the next A tile goes to the other buffer in two halves during the
+// current one, so one barrier per tile and no load waits on the next tile's start.
+template <typename T, int PP, bool TWO>
+__global__ __launch_bounds__(WGW) void k_gram_wide(int64_t n, const T* __restrict__ A0, const T* __restrict__ A1,
+                                                  const T* __restrict__ B1, const T* __restrict__ B2,
+                                                  const Scalars* __restrict__ sc, int mode,
+                                                  double* __restrict__ partials) {
+  static_assert(std::is_same<T, double>::value && PP == WPP, "the wide passes are float64 at PP = 128");
+  if (spmm_skip(sc, mode)) return;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  double* sA = reinterpret_cast<double*>(lds_raw);  // two tiles
+  const double* A = (mode == 1 && (sc->k & 1)) ? A1 : A0;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+  const int64_t ntiles = (n + TR - 1) / TR;
+  int64_t t0, t1;
+  tile_range(ntiles, t0, t1);
+  d4 acc1[8], acc2[TWO ? 8 : 1];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc1[q] = d4{0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < (TWO ? 8 : 1); ++q) acc2[q] = d4{0, 0, 0, 0};
+  double b1[4][4], b2[TWO ? 4 : 1][4];
+  if (t0 < t1) {
+    d2 x0[8];
+    wide_load(threadIdx.x, A, t0, x0);
+    wide_store(threadIdx.x, sA, x0);
+    wide_load_cols(threadIdx.x, B1, t0 * TR, b1);
+    if constexpr (TWO) wide_load_cols(threadIdx.x, B2, t0 * TR, b2);
+  }
+  for (int64_t t = t0; t < t1; ++t) {
+    int tid = threadIdx.x;  // offsets formed anew in every tile (as in k_grad_wide)
+    asm volatile("" : "+v"(tid));
+    const int buf = (int)((t - t0) & 1);
+    const double* sa = sA + buf * WTILE;
+    const int64_t tn = t + 1 < t1 ? t + 1 : t;
+    double* sn = sA + (buf ^ 1) * WTILE;
+    __syncthreads();  // tile t is in sa; every wave is past the previous tile's reads
+    d2 xn[4];
+    int lb[4];
+    wide_gram_bases(tid, lb);
+    const int o = rowof<double>(g, 0) * PP + 16 * w + c;
+    const double* n1 = B1 + tn * TR * PP;
+    const double* n2 = TWO ? B2 + tn * TR * PP : nullptr;
+#pragma unroll
+    for (int rg = 0; rg < 4; ++rg)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+#pragma unroll
+        for (int ib = 0; ib < 8; ++ib) {
+          const double a = sa[lb[r] + 16 * rg * WLD + 16 * ib];
+          acc1[ib] = mfma(a, b1[rg][r], acc1[ib]);
+          if constexpr (TWO) acc2[ib] = mfma(a, b2[rg][r], acc2[ib]);
+        }
+        b1[rg][r] = wld(n1, o + (16 * rg + 4 * r) * PP);
+        if constexpr (TWO) b2[rg][r] = wld(n2, o + (16 * rg + 4 * r) * PP);
+        if (r == 3 && rg < 3) {
+          // the next A tile: first half loaded after row group 0, stored after row group 1
+          // (when the second half is loaded), second half stored after row group 2
+          if (rg > 0) wide_store<4>(tid, sn, xn, 4 * (rg - 1));
+          if (rg < 2) wide_load<4>(tid, A, tn, xn, 4 * rg);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+  }
+  double* out = partials + (int64_t)blockIdx.x * (TWO ? 2 : 1) * PP * PP;
+#pragma unroll
+  for (int ib = 0; ib < 8; ++ib)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int e = (16 * ib + rowof<double>(g, r)) * PP + 16 * w + c;
+      out[e] = acc1[ib][r];
+      if constexpr (TWO) out[PP * PP + e] = acc2[ib][r];
+    }
+  (void)l;
+}
+
 // A^T B1 and (TWO) A^T B2 at PP = 64 (the iteration's P^T Z and P^T Y): wave w owns the 16 columns
 // 16w .. 16w+15 of P (loaded at the top of each tile, so the loads overlap the staging) and
 // the eight 16 x 16 output blocks (w, q) of both Grams; each wave stages its 16 rows of Z
@@ -1422,8 +1849,9 @@ template <typename T, int PP>
 int lds_bytes(Pass pass) {
   const int m = PP * PP * (int)sizeof(T), tile = TR * PP * (int)sizeof(T);
   switch (pass) {
-    case Pass::Grad: return factor_wide<T, PP>() ? 2 * tile : m + tile;
-    case Pass::Dir: return (factor_wide<T, PP>() ? 0 : m) + tile;
+    // the wide passes: two tiles (and the row sums [2][8][TR] of the gradient pass)
+    case Pass::Grad: return factor_wide<T, PP>() ? (2 * WTILE + 16 * TR) * (int)sizeof(double) : m + tile;
+    case Pass::Dir: return factor_wide<T, PP>() ? 2 * WTILE * (int)sizeof(double) : m + tile;
     case Pass::Update: return m;
     case Pass::UpdateGrams: return m + 3 * tile;
     case Pass::UpdateGrad: return 2 * m;
@@ -1442,8 +1870,17 @@ hipError_t set_lds_limits() {
   if (e == hipSuccess)                                                                                            \
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, \
                             lds_bytes<T, PP>(pass));
-  GSI_SET((k_grad<T, PP>), Pass::Grad)
-  GSI_SET((k_dir<T, PP>), Pass::Dir)
+  if constexpr (factor_wide<T, PP>()) {
+    GSI_SET((k_grad_wide<T, PP>), Pass::Grad)
+    GSI_SET((k_dir_wide<T, PP>), Pass::Dir)
+    for (const void* k : {reinterpret_cast<const void*>(k_gram_wide<T, PP, true>),
+                          reinterpret_cast<const void*>(k_gram_wide<T, PP, false>)})
+      if (e == hipSuccess)
+        e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * WTILE * (int)sizeof(double));
+  } else {
+    GSI_SET((k_grad<T, PP>), Pass::Grad)
+    GSI_SET((k_dir<T, PP>), Pass::Dir)
+  }
   GSI_SET((k_update<T, PP, false>), Pass::Update)
   // the retraction with Gram epilogue and the fused retraction-gradient pass are not used above
   // PP = 64 (their LDS would exceed a CU's)
@@ -1464,7 +1901,10 @@ hipError_t set_lds_limits() {
 template <typename T, int PP>
 void Kernels<T, PP>::grad(hipStream_t st, int nb, int64_t n, const T* X, const T* Y, T* G0, T* G1,
                           const double* small, const Scalars* sc, double* partials, int cond) {
-  k_grad<T, PP><<<nb, WG, lds_bytes<T, PP>(Pass::Grad), st>>>(n, X, Y, G0, G1, small, sc, partials, cond);
+  if constexpr (factor_wide<T, PP>())
+    k_grad_wide<T, PP><<<nb, WGW, lds_bytes<T, PP>(Pass::Grad), st>>>(n, X, Y, G0, G1, small, sc, partials, cond);
+  else
+    k_grad<T, PP><<<nb, WG, lds_bytes<T, PP>(Pass::Grad), st>>>(n, X, Y, G0, G1, small, sc, partials, cond);
 }
 template <typename T, int PP>
 void Kernels<T, PP>::update_grad(hipStream_t st, int nb, int64_t n, T* X, T* Y, const T* P0, const T* P1,
@@ -1477,7 +1917,11 @@ void Kernels<T, PP>::update_grad(hipStream_t st, int nb, int64_t n, T* X, T* Y, 
 template <typename T, int PP>
 void Kernels<T, PP>::dir(hipStream_t st, int nb, int64_t n, const T* X, const T* G0, const T* G1, T* P0, T* P1,
                          const double* small, const Scalars* sc, double* partials, uint16_t* P16, float* P32) {
-  k_dir<T, PP><<<nb, WG, lds_bytes<T, PP>(Pass::Dir), st>>>(n, X, G0, G1, P0, P1, small, sc, partials, P16, P32);
+  if constexpr (factor_wide<T, PP>())
+    k_dir_wide<T, PP><<<nb, WGW, lds_bytes<T, PP>(Pass::Dir), st>>>(n, X, G0, G1, P0, P1, small, sc, partials, P16,
+                                                                    P32);
+  else
+    k_dir<T, PP><<<nb, WG, lds_bytes<T, PP>(Pass::Dir), st>>>(n, X, G0, G1, P0, P1, small, sc, partials, P16, P32);
 }
 template <typename T, int PP>
 void Kernels<T, PP>::spmm_axpy(hipStream_t st, int64_t n, const int32_t* rowptr, const int32_t* colind, const T* vals,
@@ -1573,6 +2017,13 @@ void Kernels<T, PP>::gram(hipStream_t st, int nb, int64_t n, const T* A0, const 
       k_gram2<T, PP, true><<<nb, WG, 2 * TR * PP * sizeof(T), st>>>(n, A0, A1, B1, B2, sc, mode, partials);
     else
       k_gram2<T, PP, false><<<nb, WG, TR * PP * sizeof(T), st>>>(n, A0, A1, B1, B2, sc, mode, partials);
+    return;
+  }
+  if constexpr (factor_wide<T, PP>()) {
+    if (B2)
+      k_gram_wide<T, PP, true><<<nb, WGW, 2 * WTILE * sizeof(double), st>>>(n, A0, A1, B1, B2, sc, mode, partials);
+    else
+      k_gram_wide<T, PP, false><<<nb, WGW, 2 * WTILE * sizeof(double), st>>>(n, A0, A1, B1, B2, sc, mode, partials);
     return;
   }
   k_gram<T, PP><<<nb, WG, 0, st>>>(n, A0, A1, B1, B2, sc, mode, partials);
