@@ -33,6 +33,9 @@ step "$O/c2_write" 120 --pmc WRITE_SIZE -d "$O/c2_write" -o w -- $B --profile-st
 step "$O/c3_trace" 300 --kernel-trace --stats -d "$O/c3_trace" -o c3 -- $B --profile-steps 20 --profile-matrix spiked --profile-precision bf16 || exit 1
 step "$O/c3_fetch" 180 --pmc FETCH_SIZE -d "$O/c3_fetch" -o f -- $B --profile-steps 3 --profile-matrix spiked --profile-precision bf16 || exit 1
 step "$O/c3_write" 180 --pmc WRITE_SIZE -d "$O/c3_write" -o w -- $B --profile-steps 3 --profile-matrix spiked --profile-precision bf16 || exit 1
+step "$O/w128_trace" 300 --kernel-trace --stats -d "$O/w128_trace" -o w128 -- $B --profile-steps 20 --profile-matrix spiked --profile-precision fp64 --p 128 || exit 1
+step "$O/w128_fetch" 180 --pmc FETCH_SIZE -d "$O/w128_fetch" -o f -- $B --profile-steps 3 --profile-matrix spiked --profile-precision fp64 --p 128 || exit 1
+step "$O/w128_write" 180 --pmc WRITE_SIZE -d "$O/w128_write" -o w -- $B --profile-steps 3 --profile-matrix spiked --profile-precision fp64 --p 128 || exit 1
 step "$O/st_fetch" 120 --pmc FETCH_SIZE -d "$O/st_fetch" -o f -- $B --profile-steps 3 --profile-matrix stencil || exit 1
 step "$O/st_write" 120 --pmc WRITE_SIZE -d "$O/st_write" -o w -- $B --profile-steps 3 --profile-matrix stencil || exit 1
 step "$O/c4_trace" 400 --kernel-trace --stats -d "$O/c4_trace" -o c4 -- $B --legs-only --legs batched --steps 1 --warmup 0 || exit 1
@@ -45,6 +48,8 @@ $S trace "$(db "$O/c2_trace")" "$C --kernel-trace --stats -- $B --no-cpu --legs 
 $S traffic "$(db "$O/c2_fetch")" "$(db "$O/c2_write")" "$C --pmc FETCH_SIZE / WRITE_SIZE -- $B --profile-steps 3)" profiles/traffic_laplace3d_128_p64_fp64.json > /dev/null
 $S trace "$(db "$O/c3_trace")" "$C --kernel-trace --stats -- $B --profile-steps 20 --profile-matrix spiked --profile-precision bf16)" > profiles/kernels_spiked4M_p64_bf16.md
 $S traffic "$(db "$O/c3_fetch")" "$(db "$O/c3_write")" "$C --pmc FETCH_SIZE / WRITE_SIZE -- $B --profile-steps 3 --profile-matrix spiked --profile-precision bf16)" profiles/traffic_spiked4M_p64_bf16.json > /dev/null
+$S trace "$(db "$O/w128_trace")" "$C --kernel-trace --stats -- $B --profile-steps 20 --profile-matrix spiked --profile-precision fp64 --p 128)" > profiles/kernels_spiked4M_p128_fp64.md
+$S traffic "$(db "$O/w128_fetch")" "$(db "$O/w128_write")" "$C --pmc FETCH_SIZE / WRITE_SIZE -- $B --profile-steps 3 --profile-matrix spiked --profile-precision fp64 --p 128)" profiles/traffic_spiked4M_p128_fp64.json > /dev/null
 $S traffic "$(db "$O/st_fetch")" "$(db "$O/st_write")" "$C --pmc FETCH_SIZE / WRITE_SIZE -- $B --profile-steps 3 --profile-matrix stencil)" profiles/traffic_laplace3d_128_p64_fp64_stencil.json > /dev/null
 $S trace "$(db "$O/c4_trace")" "$C --kernel-trace --stats -- $B --legs-only --legs batched --steps 1 --warmup 0)" > profiles/kernels_schrodinger_batch512.md
 $S trace "$(db "$O/fno_trace")" "$C --kernel-trace --stats -- python3 -m pytest tests/test_gpu_fno.py)" > profiles/kernels_warmstart_network.md
