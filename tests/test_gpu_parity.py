@@ -149,10 +149,10 @@ def test_ragged_shapes_smallest_and_largest(n, p, seed):
 
 @pytest.mark.parametrize("n,p,seed", [(3000, 65, 21), (4000, 96, 22), (5000, 128, 23)])
 def test_block_sizes_above_64(n, p, seed):
-    """Blocks of 65 to 128 columns (float64 RCG on a CSR matrix): the passes at width 128 with the
-    p x p factors read through the caches, the p x p solves with their matrices in the work
-    area, two Get_Mu terms per lane and the Jacobi on 128 players. Ritz values equal the
-    oracle's to 1e-10, the bases agree, and the iteration counts match."""
+    """Blocks of 65 to 128 columns (float64 RCG on a CSR matrix): the 8-wave passes at width
+    128 with the p x p factors read through the caches, the p x p solves with their matrices in
+    the work area, two Get_Mu terms per lane and the Jacobi on 128 players. Ritz values equal
+    the oracle's to 1e-10, the bases agree, and the iteration counts match."""
     A = I.spiked_sparse(n, 4, p, seed, gap=0.3)
     print(f"wide block n={n} p={p}", flush=True)
     ref, r, X, hist = _solve_both(A, p, seed, tol=1e-10, max_iter=20000)
@@ -163,6 +163,25 @@ def test_block_sizes_above_64(n, p, seed):
     assert abs(r.iters - ref.iters) <= max(3, ref.iters // 20)
     k = min(20, len(ref.mu))
     assert np.allclose(hist["mu"][:k], ref.mu[:k], rtol=1e-7)
+
+
+def test_block_size_128_many_tiles_per_workgroup():
+    """Width 128 with enough rows that the float64 gradient and direction passes (512
+    workgroups) and the Gram pass (1024) give workgroups several tiles, idle workgroups and a
+    ragged last tile: the double-buffered tiles and the next-tile loads run, which the smaller
+    cases (one tile per workgroup) never reach. 40 iterations against the oracle's: the same
+    step sizes, the same basis and Ritz values, orthonormal columns."""
+    n, p, seed = 70_000, 128, 26
+    ntiles = (n + 63) // 64
+    assert ntiles > 1024 and n % 64  # more tiles than Gram workgroups; a ragged last tile
+    A = I.spiked_sparse(n, 4, p, seed, gap=0.3)
+    print(f"wide block many tiles n={n} p={p}", flush=True)
+    ref, r, X, hist = _solve_both(A, p, seed, tol=1e-14, max_iter=40)
+    assert r.iters == ref.iters == 40 and len(ref.mu) >= 40
+    assert np.allclose(hist["mu"][:40], ref.mu[:40], rtol=1e-7)
+    assert O.principal_angles(X, ref.X).max() <= 1e-7
+    assert np.allclose(X.T @ X, np.eye(p), atol=1e-12)
+    assert np.max(np.abs(r.ritz - ref.theta) / np.maximum(np.abs(ref.theta), 1e-300)) <= 1e-10
 
 
 def test_block_size_above_64_rsd():
