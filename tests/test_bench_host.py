@@ -50,13 +50,16 @@ def test_measured_traffic_follows_the_profile_and_its_source_hash(monkeypatch):
         rec = json.load(f)
     if rec["source_hash"] != profsum.source_hash():
         pytest.skip("the committed profile predates the kernel sources in this tree")
-    t = b.measured_traffic("gsi::k_update<double, 64", "traffic_laplace3d_128_p64_fp64.json")
-    # the retraction pass moves what it must: within 1% of its algorithmic bytes
-    assert t is not None and abs(t / 6_442_450_944 - 1.0) < 0.01
+    tag = "gsi::k_update_grad<double, 64"  # the iteration's retraction, fused with the gradient
+    t = b.measured_traffic(tag, "traffic_laplace3d_128_p64_fp64.json")
+    # it moves what it must: within 1% of its algorithmic bytes (8 blocks of 2^21 x 64 doubles)
+    assert t is not None and abs(t / 8_589_934_592 - 1.0) < 0.01
+    # a kernel that the profiled iterations do not launch has no entry
+    assert b.measured_traffic("gsi::k_update<double, 64", "traffic_laplace3d_128_p64_fp64.json") is None
     # counters taken on other sources are not reported
     monkeypatch.setattr(profsum, "source_hash", lambda: "0" * 16)
-    assert b.measured_traffic("gsi::k_update<double, 64", "traffic_laplace3d_128_p64_fp64.json") is None
-    assert b.measured_traffic("gsi::k_update<double, 64", "no_such_profile.json") is None
+    assert b.measured_traffic(tag, "traffic_laplace3d_128_p64_fp64.json") is None
+    assert b.measured_traffic(tag, "no_such_profile.json") is None
 
 
 def test_more_than_one_gpu_is_refused():
