@@ -94,3 +94,19 @@ def test_lds_budget(layout):
     tile = 64 * wld * 8
     assert 2 * tile + 16 * 64 * 8 + 8 * 3 * 8 <= 160 * 1024  # gradient pass: two tiles, row sums, red
     assert 2 * tile <= 160 * 1024  # direction and Gram passes
+
+
+def test_direction_pass_shares_out_each_block_of_the_symmetric_gram_once():
+    """k_dir_wide: wave w forms blocks (w + d mod 8, w) for d < 5 when w < 4, d < 4 otherwise,
+    and mirrors the off-diagonal ones; every block of P^T P is then written exactly once."""
+    text = open(SRC).read()
+    assert "const int nd = w < 4 ? 5 : 4;" in text and "const int ib = (w + d) & 7;" in text
+    written = {}
+    for w in range(8):
+        for d in range(5 if w < 4 else 4):
+            ib = (w + d) & 7
+            for blk in {(ib, w), (w, ib)}:
+                written[blk] = written.get(blk, 0) + 1
+    assert sorted(written) == [(i, j) for i in range(8) for j in range(8)]
+    assert set(written.values()) == {1}
+    assert sum(5 if w < 4 else 4 for w in range(8)) == 36  # the upper blocks, diagonal included
